@@ -1,0 +1,178 @@
+/*
+ * dfmm.h -- C ABI of the directional fast multipole matvec for MI355X (gfx950).
+ *
+ * Computes u_i = sum_{j : p_j != p_i} G(p_i, p_j) f_j with
+ * G(x, y) = exp(2 pi i |x - y|) / |x - y| (Eq. 1 of Benson, Poulson, Tran,
+ * Engquist, Ying, "A parallel directional fast multipole method", Section 1),
+ * approximately, by the evaluation pass of the sequential directional FMM
+ * (Algorithm 1, Section 2.3) plus the near-field sum between adjacent leaves.
+ *
+ * Conventions shared by every call:
+ *   - Lengths are in wavelengths; the points satisfy |p| <= K/2 (Eq. 1) and the
+ *     root box is the cube [-K/2, K/2]^3; K is a power of two >= 1.
+ *   - Every function returns an int status (DFMM_OK = 0 or a negative
+ *     dfmm_status); no C++ exception crosses the ABI.  dfmm_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - Host pointers are read during the call only; the library copies what it
+ *     keeps.  Device pointers must stay valid until the work enqueued on the
+ *     stream has completed.
+ */
+#ifndef DFMM_H
+#define DFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DFMM_OK = 0,
+  DFMM_EINVAL = -1,       /* bad argument: null pointer, N < 1, nrhs < 1, bad size */
+  DFMM_EDOMAIN = -2,      /* a point is not finite or |p| > K/2 (1 + 1e-12) */
+  DFMM_EUNSUPPORTED = -3, /* K not a power of two, eps out of range, tree wider than the operator set */
+  DFMM_ENOMEM = -4,       /* host or device allocation failed */
+  DFMM_EDEVICE = -5,      /* a HIP call failed */
+  DFMM_EIO = -6           /* operator-set file could not be read or written */
+} dfmm_status;
+
+typedef struct dfmm_plan_s* dfmm_plan_t;
+typedef struct dfmm_opset_s* dfmm_opset_t;
+
+/* Human-readable name of a status code (static storage). */
+const char* dfmm_status_string(int status);
+/* Detail of the last failure on the calling thread (empty if none). */
+const char* dfmm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Operator sets: the directional skeletons of Eq. 2 (Section 2.1).
+ *
+ * For each high-frequency width w in {1, 2, 4, ..., w_hi} and each of the
+ * 6 w^2 wedges (cube-face cells, Section 2.2), and once for the
+ * low-frequency width 1/2, a skeleton holds r equivalent points b (inside the
+ * box, box-centred frame), r check points a (in the far region) and the r x r
+ * complex matrix D with G(x, y) ~= sum_q G(x, b_q) sum_p D_qp G(a_p, y) for y
+ * in the box and x in the wedge.  Skeletons depend only on (tau, w, wedge),
+ * not on the geometry (Section 2.2), so one set serves every plan whose top
+ * interaction width is <= w_hi.
+ *
+ * Width argument: w = 0.5 selects the low-frequency skeleton (dir must be 0);
+ * w = 1, 2, 4, ... selects a high-frequency width, dir in [0, 6 w^2).
+ * Point arrays are r x 3 row-major float64; D is r x r row-major complex128
+ * stored as interleaved (re, im) doubles.
+ * ---------------------------------------------------------------------- */
+
+/* Build a set with the library's own float64 precompute (column-pivoted QR,
+ * Eq. 2): tau is the relative Frobenius truncation of each skeleton.  Uses
+ * all host cores; results are cached in cache_dir when it is non-null. */
+int dfmm_opset_build(double tau, int w_hi, const char* cache_dir, dfmm_opset_t* out);
+/* An empty set to be filled with dfmm_opset_set (every skeleton must be set
+ * before the set is used by a plan). */
+int dfmm_opset_create(double tau, int w_hi, dfmm_opset_t* out);
+/* Copy one skeleton into the set (r >= 1). */
+int dfmm_opset_set(dfmm_opset_t set, double w, int dir, int r,
+                   const double* a, const double* b, const double* D);
+/* Query one skeleton: *r receives its rank; a, b, D (may be null) receive
+ * copies of size r*3, r*3 and 2*r*r doubles. */
+int dfmm_opset_get(dfmm_opset_t set, double w, int dir, int* r,
+                   double* a, double* b, double* D);
+/* tau and w_hi of a set. */
+int dfmm_opset_info(dfmm_opset_t set, double* tau, int* w_hi);
+/* Binary file round trip (little-endian; format documented in the source). */
+int dfmm_opset_save(dfmm_opset_t set, const char* path);
+int dfmm_opset_load(const char* path, dfmm_opset_t* out);
+void dfmm_opset_destroy(dfmm_opset_t set);
+
+/* ------------------------------------------------------------------------
+ * Plans
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  double eps;             /* end-to-end relative L2 target; selects tau when opset is null */
+  dfmm_opset_t opset;     /* skeletons to use (borrowed; must outlive the plan's creation
+                             call only -- the plan copies what it needs); null = build */
+  const char* cache_dir;  /* operator-set cache directory for the build (may be null) */
+  int device;             /* HIP device ordinal; -1 = current device */
+  int reserved[7];
+} dfmm_options;
+
+/* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device. */
+void dfmm_options_default(dfmm_options* opt);
+
+/* Plan for N points (host pointer, N x 3 row-major float64, original order)
+ * in a domain of width K with end-to-end target eps (1e-7 <= eps <= 1e-2).
+ * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
+ * every level (Section 2.2), the wedge labels, the needed directions and the
+ * translation tables, all resident on the device.  Synchronous. */
+int dfmm_plan(const double* points, int64_t N, double K, double eps, dfmm_plan_t* out);
+int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* opt,
+                 dfmm_plan_t* out);
+
+/* u = A f for nrhs right-hand sides.  f and u are DEVICE pointers to complex64
+ * data (interleaved float re, im), layout [nrhs][N], in the caller's original
+ * point order; u is overwritten; f and u must not overlap.  Work is enqueued
+ * on `stream` (a hipStream_t; null = the null stream) and the call returns
+ * without waiting.  The plan owns a workspace sized for the largest nrhs seen
+ * so far; a larger nrhs grows it (a synchronous allocation).  Applies on one
+ * plan must not run concurrently. */
+int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
+
+void dfmm_destroy(dfmm_plan_t plan);
+
+/* ------------------------------------------------------------------------
+ * Introspection (tests and benchmarks)
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int64_t N;
+  double K;
+  int depth;              /* D: leaves are at level D, width 1/2 */
+  int w_top;              /* largest width with a non-empty interaction list (0 if none) */
+  int nlevels_hf;         /* number of HF levels from w_top down to 1 */
+  int64_t boxes[32];      /* non-empty boxes per level 0..D */
+  int64_t pairs[32];      /* interaction pairs per level 0..D (0 where no list) */
+  int64_t offsets[32];    /* distinct offsets per level */
+  int64_t out_slots[32];  /* needed outgoing (box, wedge) slots per HF level */
+  int64_t in_slots[32];   /* needed incoming (box, wedge) slots per HF level */
+  int rank[32];           /* skeleton size (padded) per level (HF levels and the leaf level) */
+  int64_t near_pairs;     /* adjacent leaf pairs, self included */
+  int64_t near_point_pairs; /* point pairs of the near-field sum (targets x sources) */
+  double flops_m2l_hf;    /* 8 r_in r_out summed over HF pairs, per right-hand side */
+  double flops_m2l_lf;    /* 8 r r summed over leaf-level pairs, per right-hand side */
+  double plan_seconds;
+  int64_t device_bytes;   /* device memory held by the plan (without the apply workspace) */
+} dfmm_info;
+
+int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);
+
+/* Export a plan structure into a host buffer.  If buf is null, *bytes receives
+ * the size needed.  `level` selects the level where relevant.
+ *   DFMM_EXPORT_PERM        int64[N]: original index of each sorted point
+ *   DFMM_EXPORT_BOXES       int64[nb][5]: (ix, iy, iz, first point, end point), Morton order
+ *   DFMM_EXPORT_PAIRS       int64[np][5]: (B, A, dir_in, dir_out, 0), sorted by (B, A);
+ *                           boxes are indices into that level's box table; dirs -1 at the leaves
+ *   DFMM_EXPORT_NEAR        int64[np][2]: near-field leaf pairs (B, A), sorted
+ *   DFMM_EXPORT_OUT_SLOTS   int64[ns][2]: needed outgoing (box, dir), sorted
+ *   DFMM_EXPORT_IN_SLOTS    int64[ns][2]: needed incoming (box, dir), sorted */
+enum {
+  DFMM_EXPORT_PERM = 1,
+  DFMM_EXPORT_BOXES = 2,
+  DFMM_EXPORT_PAIRS = 3,
+  DFMM_EXPORT_NEAR = 4,
+  DFMM_EXPORT_OUT_SLOTS = 5,
+  DFMM_EXPORT_IN_SLOTS = 6
+};
+int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes);
+
+/* Per-stage device times (milliseconds) of the last apply on this plan, when
+ * stage timing was enabled with dfmm_set_timing(plan, 1).  Stages, in order:
+ * 0 permute-in, 1 S2M, 2 HF-M2M, 3 HF-M2L, 4 HF-L2L, 5 LF-M2L, 6 L2T,
+ * 7 near field, 8 permute-out.  n receives the count written (<= cap). */
+int dfmm_set_timing(dfmm_plan_t plan, int enable);
+int dfmm_stage_times(dfmm_plan_t plan, double* ms, int cap, int* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFMM_H */

@@ -1,0 +1,357 @@
+// C ABI of libdfmm (declarations and contracts in include/dfmm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <sys/stat.h>
+
+#include "internal.hpp"
+
+namespace dfmm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+template <class F>
+int guarded(F&& fn) {
+  try {
+    set_error("");
+    return fn();
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(DFMM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(DFMM_EINVAL, e.what());
+  } catch (...) {
+    return fail(DFMM_EINVAL, "unknown error");
+  }
+}
+
+bool is_pow2(double K) {
+  if (!(K >= 1.0) || !(K <= 1048576.0)) return false;
+  double r = std::round(K);
+  if (r != K) return false;
+  int64_t k = int64_t(r);
+  return (k & (k - 1)) == 0;
+}
+
+// Per-skeleton truncation tau for an end-to-end relative L2 target eps.
+double tau_for_eps(double eps) { return 0.1 * eps; }
+
+int dir_count(double w, int* e) {
+  if (w == 0.5) {
+    *e = -1;
+    return 1;
+  }
+  if (!(w >= 1.0)) return -1;
+  int ee = 0;
+  while (std::ldexp(1.0, ee) < w) ++ee;
+  if (std::ldexp(1.0, ee) != w) return -1;
+  *e = ee;
+  return 6 << (2 * ee);
+}
+
+std::string cache_path(const char* dir, double tau, int w_hi) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "/dfmm_opset_tau%.3e_w%d_v1.bin", tau, w_hi);
+  return std::string(dir) + buf;
+}
+
+struct PlanCtx {
+  const dfmm_options* opt;
+  std::unique_ptr<OpSetImpl> owned;
+  const OpSetImpl* used = nullptr;
+};
+
+const OpSetImpl* plan_ops(void* vctx, int w_needed) {
+  PlanCtx& c = *static_cast<PlanCtx*>(vctx);
+  if (c.opt->opset) {
+    c.used = c.opt->opset;
+    return c.used;
+  }
+  double tau = tau_for_eps(c.opt->eps);
+  int w_hi = 1;
+  while (w_hi < w_needed) w_hi *= 2;
+  const char* dir = c.opt->cache_dir ? c.opt->cache_dir : std::getenv("DFMM_CACHE_DIR");
+  c.owned.reset(new OpSetImpl());
+  if (dir) {
+    for (int w = w_hi; w <= 64; w *= 2)
+      if (load_opset(*c.owned, cache_path(dir, tau, w)) && c.owned->tau == tau) {
+        c.used = c.owned.get();
+        return c.used;
+      }
+  }
+  c.owned.reset(new OpSetImpl());
+  c.owned->tau = tau;
+  c.owned->w_hi = w_hi;
+  build_opset(*c.owned);
+  if (dir) {
+    ::mkdir(dir, 0755);
+    (void)save_opset(*c.owned, cache_path(dir, tau, w_hi));
+  }
+  c.used = c.owned.get();
+  return c.used;
+}
+
+}  // namespace
+}  // namespace dfmm
+
+using namespace dfmm;
+
+extern "C" {
+
+const char* dfmm_status_string(int s) {
+  switch (s) {
+    case DFMM_OK: return "DFMM_OK";
+    case DFMM_EINVAL: return "DFMM_EINVAL";
+    case DFMM_EDOMAIN: return "DFMM_EDOMAIN";
+    case DFMM_EUNSUPPORTED: return "DFMM_EUNSUPPORTED";
+    case DFMM_ENOMEM: return "DFMM_ENOMEM";
+    case DFMM_EDEVICE: return "DFMM_EDEVICE";
+    case DFMM_EIO: return "DFMM_EIO";
+    default: return "DFMM_UNKNOWN";
+  }
+}
+
+const char* dfmm_last_error(void) { return g_last_error.c_str(); }
+
+int dfmm_opset_build(double tau, int w_hi, const char* cache_dir, dfmm_opset_t* out) {
+  return guarded([&]() {
+    if (!out) return fail(DFMM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!(tau > 0.0 && tau < 1.0)) return fail(DFMM_EINVAL, "tau must be in (0, 1)");
+    if (w_hi < 1 || w_hi > 64 || (w_hi & (w_hi - 1))) return fail(DFMM_EINVAL, "w_hi must be a power of two in [1, 64]");
+    std::unique_ptr<OpSetImpl> s(new OpSetImpl());
+    if (cache_dir && load_opset(*s, cache_path(cache_dir, tau, w_hi)) && s->tau == tau && s->w_hi == w_hi) {
+      *out = s.release();
+      return int(DFMM_OK);
+    }
+    s.reset(new OpSetImpl());
+    s->tau = tau;
+    s->w_hi = w_hi;
+    build_opset(*s);
+    if (cache_dir) {
+      ::mkdir(cache_dir, 0755);
+      (void)save_opset(*s, cache_path(cache_dir, tau, w_hi));
+    }
+    *out = s.release();
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_opset_create(double tau, int w_hi, dfmm_opset_t* out) {
+  return guarded([&]() {
+    if (!out) return fail(DFMM_EINVAL, "null output pointer");
+    if (w_hi < 1 || w_hi > 64 || (w_hi & (w_hi - 1))) return fail(DFMM_EINVAL, "w_hi must be a power of two in [1, 64]");
+    std::unique_ptr<OpSetImpl> s(new OpSetImpl());
+    s->tau = tau;
+    s->w_hi = w_hi;
+    int emax = 0;
+    while ((1 << emax) < w_hi) ++emax;
+    s->hf.assign(emax + 1, {});
+    for (int e = 0; e <= emax; ++e) s->hf[e].assign(size_t(6) << (2 * e), Skel());
+    *out = s.release();
+    return int(DFMM_OK);
+  });
+}
+
+static Skel* find_skel(dfmm_opset_t set, double w, int dir) {
+  int e = 0;
+  int n = dir_count(w, &e);
+  if (n < 0 || dir < 0 || dir >= n) return nullptr;
+  if (e < 0) return &set->lf;
+  if (e >= int(set->hf.size())) return nullptr;
+  return &set->hf[e][dir];
+}
+
+int dfmm_opset_set(dfmm_opset_t set, double w, int dir, int r, const double* a, const double* b,
+                   const double* D) {
+  return guarded([&]() {
+    if (!set || !a || !b || !D || r < 1 || r > 4096) return fail(DFMM_EINVAL, "bad argument");
+    Skel* s = find_skel(set, w, dir);
+    if (!s) return fail(DFMM_EINVAL, "no such width / direction in this set");
+    s->r = r;
+    s->a.assign(a, a + 3 * size_t(r));
+    s->b.assign(b, b + 3 * size_t(r));
+    s->D.assign(D, D + 2 * size_t(r) * r);
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_opset_get(dfmm_opset_t set, double w, int dir, int* r, double* a, double* b, double* D) {
+  return guarded([&]() {
+    if (!set || !r) return fail(DFMM_EINVAL, "bad argument");
+    Skel* s = find_skel(set, w, dir);
+    if (!s) return fail(DFMM_EINVAL, "no such width / direction in this set");
+    *r = s->r;
+    if (a) std::memcpy(a, s->a.data(), sizeof(double) * s->a.size());
+    if (b) std::memcpy(b, s->b.data(), sizeof(double) * s->b.size());
+    if (D) std::memcpy(D, s->D.data(), sizeof(double) * s->D.size());
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_opset_info(dfmm_opset_t set, double* tau, int* w_hi) {
+  if (!set) return fail(DFMM_EINVAL, "null set");
+  if (tau) *tau = set->tau;
+  if (w_hi) *w_hi = set->w_hi;
+  return DFMM_OK;
+}
+
+int dfmm_opset_save(dfmm_opset_t set, const char* path) {
+  return guarded([&]() {
+    if (!set || !path) return fail(DFMM_EINVAL, "bad argument");
+    if (!save_opset(*set, path)) return fail(DFMM_EIO, std::string("cannot write ") + path);
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_opset_load(const char* path, dfmm_opset_t* out) {
+  return guarded([&]() {
+    if (!path || !out) return fail(DFMM_EINVAL, "bad argument");
+    std::unique_ptr<OpSetImpl> s(new OpSetImpl());
+    if (!load_opset(*s, path)) return fail(DFMM_EIO, std::string("cannot read ") + path);
+    *out = s.release();
+    return int(DFMM_OK);
+  });
+}
+
+void dfmm_opset_destroy(dfmm_opset_t set) { delete set; }
+
+void dfmm_options_default(dfmm_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->eps = 1e-4;
+  opt->device = -1;
+}
+
+int dfmm_plan(const double* points, int64_t N, double K, double eps, dfmm_plan_t* out) {
+  dfmm_options o;
+  dfmm_options_default(&o);
+  o.eps = eps;
+  return dfmm_plan_ex(points, N, K, &o, out);
+}
+
+int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* opt, dfmm_plan_t* out) {
+  return guarded([&]() {
+    if (!out) return fail(DFMM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!points || !opt) return fail(DFMM_EINVAL, "null points or options");
+    if (N < 1 || N > (int64_t(1) << 31) - 1) return fail(DFMM_EINVAL, "N must be in [1, 2^31 - 1]");
+    if (!is_pow2(K)) return fail(DFMM_EUNSUPPORTED, "K must be a power of two in [1, 2^20]");
+    if (!opt->opset && !(opt->eps >= 1e-7 && opt->eps <= 1e-2))
+      return fail(DFMM_EUNSUPPORTED, "eps must be in [1e-7, 1e-2]");
+    if (opt->opset) {
+      for (auto& v : opt->opset->hf)
+        for (auto& s : v)
+          if (s.r < 1) return fail(DFMM_EINVAL, "operator set has unset skeletons");
+      if (opt->opset->lf.r < 1) return fail(DFMM_EINVAL, "operator set has no LF skeleton");
+    }
+    const double lim = K / 2.0 * (1.0 + 1e-12);
+    for (int64_t i = 0; i < N; ++i) {
+      double x = points[3 * i], y = points[3 * i + 1], z = points[3 * i + 2];
+      if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+        return fail(DFMM_EDOMAIN, "point " + std::to_string(i) + " is not finite");
+      if (std::sqrt(x * x + y * y + z * z) > lim)
+        return fail(DFMM_EDOMAIN, "point " + std::to_string(i) + " lies outside |p| <= K/2");
+    }
+    int dev = opt->device;
+    if (dev < 0) DFMM_HIP(hipGetDevice(&dev));
+    DFMM_HIP(hipSetDevice(dev));
+    std::unique_ptr<dfmm_plan_s> P(new dfmm_plan_s());
+    P->device = dev;
+    PlanCtx ctx{opt, nullptr, nullptr};
+    build_plan(*P, points, N, K, &plan_ops, &ctx);
+    *out = P.release();
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream) {
+  return guarded([&]() {
+    if (!plan || !f || !u) return fail(DFMM_EINVAL, "null plan or vector");
+    if (nrhs < 1 || nrhs > 4096) return fail(DFMM_EINVAL, "nrhs must be in [1, 4096]");
+    const char* fb = static_cast<const char*>(f);
+    const char* ub = static_cast<const char*>(u);
+    size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
+    if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
+    int cur = 0;
+    DFMM_HIP(hipGetDevice(&cur));
+    if (cur != plan->device) DFMM_HIP(hipSetDevice(plan->device));
+    run_apply(*plan, f, u, nrhs, static_cast<hipStream_t>(stream));
+    if (cur != plan->device) DFMM_HIP(hipSetDevice(cur));
+    return int(DFMM_OK);
+  });
+}
+
+void dfmm_destroy(dfmm_plan_t plan) {
+  if (!plan) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) (void)hipSetDevice(plan->device);
+  destroy_apply_state(plan->ws);
+  plan->ws = nullptr;
+  delete plan;
+  if (cur != 0) (void)hipSetDevice(cur);
+}
+
+int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info) {
+  if (!plan || !info) return fail(DFMM_EINVAL, "null argument");
+  *info = plan->info;
+  return DFMM_OK;
+}
+
+int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes) {
+  return guarded([&]() {
+    if (!plan || !bytes) return fail(DFMM_EINVAL, "null argument");
+    const std::vector<int64_t>* v = nullptr;
+    auto lvl_ok = [&]() { return level >= 0 && level <= plan->D; };
+    switch (what) {
+      case DFMM_EXPORT_PERM: v = &plan->perm; break;
+      case DFMM_EXPORT_BOXES: if (lvl_ok()) v = &plan->boxes[level]; break;
+      case DFMM_EXPORT_PAIRS: if (lvl_ok()) v = &plan->pairs[level]; break;
+      case DFMM_EXPORT_NEAR: v = &plan->near; break;
+      case DFMM_EXPORT_OUT_SLOTS: if (lvl_ok()) v = &plan->out_slots[level]; break;
+      case DFMM_EXPORT_IN_SLOTS: if (lvl_ok()) v = &plan->in_slots[level]; break;
+      default: break;
+    }
+    if (!v) return fail(DFMM_EINVAL, "bad export selector or level");
+    size_t need = v->size() * sizeof(int64_t);
+    if (!buf) {
+      *bytes = need;
+      return int(DFMM_OK);
+    }
+    if (*bytes < need) return fail(DFMM_EINVAL, "buffer too small");
+    std::memcpy(buf, v->data(), need);
+    *bytes = need;
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_set_timing(dfmm_plan_t plan, int enable) {
+  if (!plan) return fail(DFMM_EINVAL, "null plan");
+  plan->timing = enable != 0;
+  return DFMM_OK;
+}
+
+int dfmm_stage_times(dfmm_plan_t plan, double* ms, int cap, int* n) {
+  if (!plan || !n) return fail(DFMM_EINVAL, "null argument");
+  int k = int(std::min<size_t>(plan->stage_ms.size(), size_t(cap < 0 ? 0 : cap)));
+  for (int i = 0; i < k; ++i) ms[i] = plan->stage_ms[i];
+  *n = k;
+  return DFMM_OK;
+}
+
+}  // extern "C"

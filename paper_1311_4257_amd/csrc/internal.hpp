@@ -1,0 +1,190 @@
+// Internal declarations shared by the host sources of libdfmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dfmm.h"
+
+namespace dfmm {
+
+// ---- errors ----------------------------------------------------------------
+void set_error(const std::string& msg);
+struct Error {
+  int code;
+  std::string msg;
+};
+#define DFMM_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::dfmm::Error{e_ == hipErrorOutOfMemory ? DFMM_ENOMEM : DFMM_EDEVICE,         \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};              \
+  } while (0)
+
+// ---- skeletons (Eq. 2) -------------------------------------------------------
+struct Skel {
+  int r = 0;
+  std::vector<double> a, b;  // r x 3, box-centred frame
+  std::vector<double> D;     // r x r complex, row-major, interleaved
+};
+
+}  // namespace dfmm
+
+struct dfmm_opset_s {
+  double tau = 0.0;
+  int w_hi = 1;
+  std::vector<std::vector<dfmm::Skel>> hf;  // [log2 w][dir]
+  dfmm::Skel lf;
+};
+
+namespace dfmm {
+using OpSetImpl = dfmm_opset_s;
+void build_opset(OpSetImpl& set);
+bool save_opset(const OpSetImpl& set, const std::string& path);
+bool load_opset(OpSetImpl& set, const std::string& path);
+
+// ---- device buffers ---------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 16;
+    DFMM_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <class T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) DFMM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// ---- one HF level of the plan -------------------------------------------------
+struct HFLevel {
+  int l = 0;      // tree level
+  int e = 0;      // log2 of the width
+  int R = 0;      // padded skeleton size (multiple of 8)
+  int Rc = 0;     // padded skeleton size of the child level (LF at e = 0)
+  int64_t nout = 0, nin = 0, npairs = 0, ngroups = 0;
+  double flops = 0.0;  // 8 r_in r_out over pairs (unpadded ranks)
+  // M2M: out-slot -> its 8 child out-slots (or LF leaves at e = 0), -1 if absent
+  DevBuf m2m_child;    // int32[nout][8]
+  DevBuf m2m_op;       // int32[nout]: base operator index (dir * 8) of the slot
+  DevBuf Mup;          // float2[ndir * 8][R][Rc]: G(a^{w,l} - delta_o, b^c) D^c
+  DevBuf Mdn;          // float2[ndir * 8][Rc][R]: G(b^c + delta_o, a^{w,l}) (D^{w,l})^T
+  // L2L: child in-slot (next level, or LF leaf at e = 0) <- parent in-slots
+  int l2l_terms = 0;   // 4 (HF child) or 6 (LF child)
+  int64_t nchild_in = 0;
+  DevBuf l2l_par;      // int32[nchild_in][terms]: parent in-slot or -1
+  DevBuf l2l_op;       // int32[nchild_in][terms]: operator index (dir * 8 + octant) or -1
+  // M2L grouped by offset
+  DevBuf T;            // float2[ngroups][R][R]
+  DevBuf grp_start;    // int32[ngroups + 1] into the grouped pair order
+  DevBuf pair_src;     // int32[npairs]: out-slot of the source (grouped order)
+  DevBuf red_start;    // int32[nin + 1]: CSR of grouped pair positions per in-slot
+  DevBuf red_idx;      // int32[npairs]
+  int max_group = 0;
+  std::vector<int32_t> gs_h;  // host copy of grp_start
+};
+
+struct LFLevel {
+  int R = 0;           // padded rank (multiple of 8)
+  int r = 0;           // rank of the LF skeleton
+  int64_t nleaf = 0, npairs = 0, ngroups = 0;
+  double flops = 0.0;
+  DevBuf a;            // float4[R]  check points a_LF (box frame)
+  DevBuf a64;          // double4[R] the same in float64 (for L2T)
+  DevBuf D64;          // double2[R][R] D_LF, row-major, float64 (for L2T)
+  DevBuf T, grp_start, pair_src, red_start, red_idx;
+  int max_group = 0;
+  std::vector<int32_t> gs_h;
+};
+
+// Octree with one table per level, boxes in Morton order (host copy).
+struct Tree {
+  int D = 0;                                 // leaf level (leaf width 1/2)
+  std::vector<int64_t> perm;                 // sorted position -> original index
+  std::vector<double> pts;                   // sorted points, N x 3
+  struct Lv {
+    std::vector<int64_t> key;                // Morton key at this level, ascending
+    std::vector<int64_t> cx, cy, cz;         // integer box coordinates
+    std::vector<int64_t> start, end;         // sorted point range
+    std::vector<int64_t> parent, octant;     // parent index at level l-1, octant in it
+    std::vector<int64_t> cbeg, cend;         // children range at level l+1
+  };
+  std::vector<Lv> lv;
+  // index of the box with coordinates (x, y, z) at level l, or -1
+  int64_t find(int l, int64_t x, int64_t y, int64_t z) const;
+};
+
+struct ApplyState;
+void destroy_apply_state(ApplyState* s);
+void run_apply(dfmm_plan_s& P, const void* f, void* u, int nrhs, hipStream_t st);
+void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
+                const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);
+
+}  // namespace dfmm
+
+struct dfmm_plan_s {
+  int device = 0;
+  int64_t N = 0;
+  double K = 0.0;
+  int D = 0;       // leaf level
+  int w_top = 0;
+  double plan_seconds = 0.0;
+  dfmm_info info{};
+  // host copies of structures for export
+  std::vector<int64_t> perm;
+  std::vector<std::vector<int64_t>> boxes;   // per level: nb x 5
+  std::vector<std::vector<int64_t>> pairs;   // per level: np x 5 sorted (B, A)
+  std::vector<int64_t> near;                 // np x 2
+  std::vector<std::vector<int64_t>> out_slots, in_slots;  // per level: ns x 2
+  // device
+  dfmm::DevBuf pthi, ptlo;       // float4[N] sorted points (hi, lo split)
+  dfmm::DevBuf perm_d;           // int32[N]
+  dfmm::DevBuf leaf_start;       // int32[nleaf + 1]
+  dfmm::DevBuf leaf_center;      // float4[nleaf]
+  dfmm::DevBuf near_start, near_src;  // CSR over leaves
+  int max_leaf_pts = 0;
+  dfmm::LFLevel lf;
+  std::vector<dfmm::HFLevel> hf;  // index e (log2 w), 0 .. e_top
+  // apply workspace (owned; see apply.hip)
+  struct dfmm::ApplyState* ws = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<double> stage_ms;
+};

@@ -1,0 +1,500 @@
+// Plan construction: octree, interaction lists, wedges, needed directions and
+// translation tables (Section 2.2, Algorithm 1), resident on the device.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <thread>
+#include <tuple>
+
+#include "geometry.hpp"
+#include "internal.hpp"
+
+namespace dfmm {
+
+void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T);
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F&& fn) {
+  unsigned hc = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hc ? hc : 1, 16));
+  nt = std::min<int64_t>(nt, n);
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int64_t i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+// G(x, y) in float64 (zero at coincidence).
+inline void green64(double dx, double dy, double dz, double* re, double* im) {
+  double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+  if (r == 0.0) {
+    *re = *im = 0.0;
+    return;
+  }
+  *re = std::cos(2.0 * M_PI * r) / r;
+  *im = std::sin(2.0 * M_PI * r) / r;
+}
+
+int pad8(int r) { return (r + 7) / 8 * 8; }
+
+}  // namespace
+
+int64_t Tree::find(int l, int64_t x, int64_t y, int64_t z) const {
+  int64_t n = int64_t(1) << l;
+  if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return -1;
+  int64_t k = 0;
+  for (int b = 0; b < l; ++b)
+    k |= (((x >> b) & 1) << (3 * b)) | (((y >> b) & 1) << (3 * b + 1)) | (((z >> b) & 1) << (3 * b + 2));
+  const auto& K = lv[l].key;
+  auto it = std::lower_bound(K.begin(), K.end(), k);
+  if (it == K.end() || *it != k) return -1;
+  return int64_t(it - K.begin());
+}
+
+namespace {
+
+struct PairRec {
+  int64_t B, A, nx, ny, nz;
+  int din, dout;
+};
+
+// I^B for every box of level l: non-empty children of N^{parent(B)} not in N^B.
+std::vector<PairRec> level_pairs(const Tree& T, int l) {
+  std::vector<PairRec> out;
+  if (l < 1) return out;
+  int e2 = T.D - l;  // log2(2w)
+  const auto& L = T.lv[l];
+  const auto& U = T.lv[l - 1];
+  std::vector<int64_t> noff = near_offsets_e2(e2 + 1);
+  int64_t nb = int64_t(L.key.size());
+  std::vector<std::vector<PairRec>> per(nb);
+  parallel_for(nb, [&](int64_t b) {
+    int64_t p = L.parent[b];
+    std::vector<PairRec>& v = per[b];
+    for (size_t i = 0; i < noff.size(); i += 3) {
+      int64_t q = T.find(l - 1, U.cx[p] + noff[i], U.cy[p] + noff[i + 1], U.cz[p] + noff[i + 2]);
+      if (q < 0) continue;
+      for (int64_t a = U.cbeg[q]; a < U.cend[q]; ++a) {
+        int64_t nx = L.cx[a] - L.cx[b], ny = L.cy[a] - L.cy[b], nz = L.cz[a] - L.cz[b];
+        if (is_near_e2(nx, ny, nz, e2)) continue;
+        PairRec r{b, a, nx, ny, nz, -1, -1};
+        if (e2 >= 1) {
+          int64_t w = int64_t(1) << (e2 - 1);
+          r.din = direction(nx, ny, nz, w);
+          r.dout = direction(-nx, -ny, -nz, w);
+        }
+        v.push_back(r);
+      }
+    }
+    std::sort(v.begin(), v.end(), [](const PairRec& x, const PairRec& y) { return x.A < y.A; });
+  });
+  for (auto& v : per) out.insert(out.end(), v.begin(), v.end());
+  return out;
+}
+
+struct SlotIndex {
+  std::map<std::pair<int64_t, int>, int64_t> idx;
+  std::vector<std::pair<int64_t, int>> list;
+  void build(const std::set<std::pair<int64_t, int>>& s) {
+    list.assign(s.begin(), s.end());
+    for (size_t i = 0; i < list.size(); ++i) idx[list[i]] = int64_t(i);
+  }
+  int64_t at(int64_t b, int d) const {
+    auto it = idx.find({b, d});
+    return it == idx.end() ? -1 : it->second;
+  }
+};
+
+std::vector<float> skel_points4(const Skel& s, int R) {
+  std::vector<float> v(size_t(4) * R, 0.0f);
+  for (int i = 0; i < s.r; ++i)
+    for (int k = 0; k < 3; ++k) v[4 * i + k] = float(s.b[3 * i + k]);
+  return v;
+}
+
+}  // namespace
+
+void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
+                const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx) {
+  auto t0 = std::chrono::steady_clock::now();
+  P.N = N;
+  P.K = K;
+  Tree T;
+  build_tree_device(P, points, N, K, T);
+  const int D = T.D;
+  P.D = D;
+  dfmm_info& info = P.info;
+  std::memset(&info, 0, sizeof(info));
+  info.N = N;
+  info.K = K;
+  info.depth = D;
+
+  // ---- exports of the tree --------------------------------------------------
+  P.perm = T.perm;
+  P.boxes.assign(D + 1, {});
+  for (int l = 0; l <= D; ++l) {
+    const auto& L = T.lv[l];
+    auto& v = P.boxes[l];
+    for (size_t b = 0; b < L.key.size(); ++b) {
+      v.insert(v.end(), {L.cx[b], L.cy[b], L.cz[b], L.start[b], L.end[b]});
+    }
+    info.boxes[l] = int64_t(L.key.size());
+  }
+
+  // ---- interaction lists on every level -------------------------------------
+  std::vector<std::vector<PairRec>> pairs(D + 1);
+  P.pairs.assign(D + 1, {});
+  int l_top = -1;
+  for (int l = 1; l <= D; ++l) {
+    pairs[l] = level_pairs(T, l);
+    auto& v = P.pairs[l];
+    for (auto& r : pairs[l]) v.insert(v.end(), {r.B, r.A, int64_t(r.din), int64_t(r.dout), 0});
+    info.pairs[l] = int64_t(pairs[l].size());
+    std::set<std::tuple<int64_t, int64_t, int64_t>> offs;
+    for (auto& r : pairs[l]) offs.insert({r.nx, r.ny, r.nz});
+    info.offsets[l] = int64_t(offs.size());
+    if (l < D && !pairs[l].empty() && l_top < 0) l_top = l;
+  }
+  int e_top = l_top >= 0 ? (D - 1 - l_top) : -1;
+  P.w_top = e_top >= 0 ? (1 << e_top) : 0;
+  info.w_top = P.w_top;
+  info.nlevels_hf = e_top + 1;
+  const OpSetImpl& ops = *get_ops(ctx, std::max(1, P.w_top));
+  if (e_top >= 0 && (1 << e_top) > ops.w_hi)
+    throw Error{DFMM_EUNSUPPORTED, "tree needs HF width " + std::to_string(1 << e_top) +
+                                       " but the operator set stops at " + std::to_string(ops.w_hi)};
+
+  // ---- near-field lists -------------------------------------------------------
+  const auto& LL = T.lv[D];
+  int64_t nleaf = int64_t(LL.key.size());
+  std::vector<int32_t> near_start(nleaf + 1, 0), near_src;
+  {
+    std::vector<int64_t> noff = near_offsets_e2(0);
+    for (int64_t b = 0; b < nleaf; ++b) {
+      std::vector<int64_t> v;
+      for (size_t i = 0; i < noff.size(); i += 3) {
+        int64_t a = T.find(D, LL.cx[b] + noff[i], LL.cy[b] + noff[i + 1], LL.cz[b] + noff[i + 2]);
+        if (a >= 0) v.push_back(a);
+      }
+      std::sort(v.begin(), v.end());
+      for (int64_t a : v) {
+        near_src.push_back(int32_t(a));
+        P.near.push_back(b);
+        P.near.push_back(a);
+        info.near_point_pairs += (LL.end[b] - LL.start[b]) * (LL.end[a] - LL.start[a]);
+      }
+      near_start[b + 1] = int32_t(near_src.size());
+    }
+    info.near_pairs = int64_t(near_src.size());
+  }
+  P.near_start.upload(near_start);
+  P.near_src.upload(near_src);
+
+  // ---- needed directions (top-down closure) ----------------------------------
+  P.out_slots.assign(D + 1, {});
+  P.in_slots.assign(D + 1, {});
+  std::vector<SlotIndex> OS(D + 1), IS(D + 1);
+  if (e_top >= 0) {
+    for (int l = l_top; l < D; ++l) {
+      int64_t w = int64_t(1) << (D - 1 - l);
+      std::set<std::pair<int64_t, int>> outs, ins;
+      for (auto& r : pairs[l]) {
+        outs.insert({r.A, r.dout});
+        ins.insert({r.B, r.din});
+      }
+      if (l > l_top) {
+        const auto& U = T.lv[l - 1];
+        for (auto& s : OS[l - 1].list) {
+          int dd = direction_down(s.second, 2 * w);
+          for (int64_t c = U.cbeg[s.first]; c < U.cend[s.first]; ++c) outs.insert({c, dd});
+        }
+        for (auto& s : IS[l - 1].list) {
+          int dd = direction_down(s.second, 2 * w);
+          for (int64_t c = U.cbeg[s.first]; c < U.cend[s.first]; ++c) ins.insert({c, dd});
+        }
+      }
+      OS[l].build(outs);
+      IS[l].build(ins);
+      for (auto& s : OS[l].list) P.out_slots[l].insert(P.out_slots[l].end(), {s.first, int64_t(s.second)});
+      for (auto& s : IS[l].list) P.in_slots[l].insert(P.in_slots[l].end(), {s.first, int64_t(s.second)});
+      info.out_slots[l] = int64_t(OS[l].list.size());
+      info.in_slots[l] = int64_t(IS[l].list.size());
+    }
+  }
+
+  // ---- LF level tables ------------------------------------------------------------
+  const Skel& sl = ops.lf;
+  int Rlf = pad8(sl.r);
+  P.lf.R = Rlf;
+  P.lf.r = sl.r;
+  P.lf.nleaf = nleaf;
+  info.rank[D] = Rlf;
+  {
+    std::vector<float> a4(size_t(4) * Rlf, 0.0f);
+    std::vector<double> a64(size_t(4) * Rlf, 0.0), D64(size_t(2) * Rlf * Rlf, 0.0);
+    for (int i = 0; i < sl.r; ++i)
+      for (int k = 0; k < 3; ++k) {
+        a4[4 * i + k] = float(sl.a[3 * i + k]);
+        a64[4 * i + k] = sl.a[3 * i + k];
+      }
+    for (int q = 0; q < sl.r; ++q)
+      for (int p = 0; p < sl.r; ++p) {
+        D64[2 * (size_t(q) * Rlf + p)] = sl.D[2 * (size_t(q) * sl.r + p)];
+        D64[2 * (size_t(q) * Rlf + p) + 1] = sl.D[2 * (size_t(q) * sl.r + p) + 1];
+      }
+    P.lf.a.upload(a4);
+    P.lf.a64.upload(a64);
+    P.lf.D64.upload(D64);
+  }
+
+  // grouped M2L tables for one level: pairs -> groups by offset, T tables, CSR
+  auto build_m2l = [&](const std::vector<PairRec>& pr, double w, int R,
+                       const std::vector<const Skel*>& skin, const std::vector<const Skel*>& skout,
+                       const SlotIndex* osl, const SlotIndex* isl, int64_t nin, DevBuf& Tb,
+                       DevBuf& gs, DevBuf& ps, DevBuf& rs, DevBuf& ri, int64_t& ngroups,
+                       int& max_group, double& flops, std::vector<int32_t>& gs_host) {
+    std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<int64_t>> g;
+    for (size_t i = 0; i < pr.size(); ++i) g[{pr[i].nx, pr[i].ny, pr[i].nz}].push_back(int64_t(i));
+    ngroups = int64_t(g.size());
+    std::vector<int32_t> gstart(1, 0), psrc, pos_of(pr.size());
+    std::vector<std::tuple<int64_t, int64_t, int64_t>> keys;
+    std::vector<int64_t> rep;
+    max_group = 0;
+    flops = 0.0;
+    for (auto& kv : g) {
+      keys.push_back(kv.first);
+      rep.push_back(kv.second.front());
+      for (int64_t i : kv.second) {
+        const PairRec& r = pr[i];
+        pos_of[i] = int32_t(psrc.size());
+        psrc.push_back(int32_t(osl ? osl->at(r.A, r.dout) : r.A));
+        const Skel* si = skin[r.din < 0 ? 0 : r.din];
+        const Skel* so = skout[r.dout < 0 ? 0 : r.dout];
+        flops += 8.0 * si->r * so->r;
+      }
+      max_group = std::max<int>(max_group, int(kv.second.size()));
+      gstart.push_back(int32_t(psrc.size()));
+    }
+    // reduction CSR per in-slot (or leaf)
+    std::vector<std::vector<int32_t>> per(nin);
+    for (size_t i = 0; i < pr.size(); ++i) {
+      const PairRec& r = pr[i];
+      int64_t s = isl ? isl->at(r.B, r.din) : r.B;
+      per[s].push_back(pos_of[i]);
+    }
+    std::vector<int32_t> rstart(1, 0), ridx;
+    for (auto& v : per) {
+      std::sort(v.begin(), v.end());
+      ridx.insert(ridx.end(), v.begin(), v.end());
+      rstart.push_back(int32_t(ridx.size()));
+    }
+    // translation of outgoing check potentials: G(b^{l_in}, n w + b^{l_out}) D^{l_out}
+    std::vector<float> Tt(size_t(2) * R * R * ngroups, 0.0f);
+    parallel_for(ngroups, [&](int64_t gi) {
+      const PairRec& r = pr[rep[gi]];
+      const Skel* si = skin[r.din < 0 ? 0 : r.din];
+      const Skel* so = skout[r.dout < 0 ? 0 : r.dout];
+      double sx = double(std::get<0>(keys[gi])) * w, sy = double(std::get<1>(keys[gi])) * w,
+             sz = double(std::get<2>(keys[gi])) * w;
+      std::vector<double> G(size_t(2) * so->r);
+      float* t = &Tt[size_t(2) * R * R * gi];
+      for (int q = 0; q < si->r; ++q) {
+        for (int p = 0; p < so->r; ++p)
+          green64(si->b[3 * q] - (sx + so->b[3 * p]), si->b[3 * q + 1] - (sy + so->b[3 * p + 1]),
+                  si->b[3 * q + 2] - (sz + so->b[3 * p + 2]), &G[2 * p], &G[2 * p + 1]);
+        for (int j = 0; j < so->r; ++j) {
+          double re = 0.0, im = 0.0;
+          for (int p = 0; p < so->r; ++p) {
+            double gr = G[2 * p], gi2 = G[2 * p + 1];
+            double dr = so->D[2 * (size_t(p) * so->r + j)], di = so->D[2 * (size_t(p) * so->r + j) + 1];
+            re += gr * dr - gi2 * di;
+            im += gr * di + gi2 * dr;
+          }
+          t[2 * (q * R + j)] = float(re);
+          t[2 * (q * R + j) + 1] = float(im);
+        }
+      }
+    });
+    Tb.upload(Tt);
+    gs.upload(gstart);
+    gs_host = gstart;
+    ps.upload(psrc);
+    rs.upload(rstart);
+    ri.upload(ridx);
+  };
+
+  {
+    std::vector<const Skel*> s1{&sl};
+    P.lf.npairs = int64_t(pairs[D].size());
+    build_m2l(pairs[D], 0.5, Rlf, s1, s1, nullptr, nullptr, nleaf, P.lf.T, P.lf.grp_start,
+              P.lf.pair_src, P.lf.red_start, P.lf.red_idx, P.lf.ngroups, P.lf.max_group, P.lf.flops,
+              P.lf.gs_h);
+    info.flops_m2l_lf = P.lf.flops;
+  }
+
+  // ---- HF levels ----------------------------------------------------------------
+  P.hf.clear();
+  P.hf.resize(e_top + 1);
+  for (int e = e_top; e >= 0; --e) {
+    HFLevel& H = P.hf[e];
+    int l = D - 1 - e;
+    int64_t w = int64_t(1) << e;
+    H.l = l;
+    H.e = e;
+    const auto& sk = ops.hf[e];
+    int rmax = 0;
+    for (auto& s : sk) rmax = std::max(rmax, s.r);
+    H.R = pad8(rmax);
+    info.rank[l] = H.R;
+    std::vector<const Skel*> child_sk;
+    if (e == 0) {
+      H.Rc = Rlf;
+      child_sk.assign(1, &sl);
+    } else {
+      int rc = 0;
+      for (auto& s : ops.hf[e - 1]) rc = std::max(rc, s.r);
+      H.Rc = pad8(rc);
+      for (auto& s : ops.hf[e - 1]) child_sk.push_back(&s);
+    }
+    H.nout = int64_t(OS[l].list.size());
+    H.nin = int64_t(IS[l].list.size());
+    H.npairs = int64_t(pairs[l].size());
+    // Per (dir, octant): upward G(a^{w,l} - delta_o, b^c) D^c (R x Rc) maps the
+    // child's outgoing check potentials to the parent's; downward
+    // G(b^c + delta_o, a^{w,l}) (D^{w,l})^T (Rc x R) maps the parent's incoming
+    // check potentials to the child's (c = the child skeleton of wedge l).
+    int ndir = int(6 * w * w);
+    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * H.Rc, 0.0f), Md(Mu.size(), 0.0f);
+    std::vector<char> dir_used(ndir, 0);
+    for (auto& s : OS[l].list) dir_used[s.second] = 1;
+    for (auto& s : IS[l].list) dir_used[s.second] = 1;
+    double wc = double(w) / 2.0;
+    parallel_for(int64_t(ndir) * 8, [&](int64_t id) {
+      int d = int(id / 8), o = int(id % 8);
+      if (!dir_used[d]) return;
+      const Skel& s = sk[d];
+      const Skel& c = e == 0 ? sl : *child_sk[direction_down(d, w)];
+      double dx = ((o & 1) - 0.5) * wc, dy = (((o >> 1) & 1) - 0.5) * wc, dz = (((o >> 2) & 1) - 0.5) * wc;
+      // G[p][j] = G(a_p - delta, b_j)  (s.r x c.r)
+      std::vector<double> G(size_t(2) * s.r * c.r);
+      for (int p = 0; p < s.r; ++p)
+        for (int j = 0; j < c.r; ++j)
+          green64(s.a[3 * p] - dx - c.b[3 * j], s.a[3 * p + 1] - dy - c.b[3 * j + 1],
+                  s.a[3 * p + 2] - dz - c.b[3 * j + 2], &G[2 * (size_t(p) * c.r + j)],
+                  &G[2 * (size_t(p) * c.r + j) + 1]);
+      float* up = &Mu[size_t(2) * id * H.R * H.Rc];
+      for (int p = 0; p < s.r; ++p)
+        for (int k = 0; k < c.r; ++k) {  // (G D^c)[p][k]
+          double re = 0.0, im = 0.0;
+          for (int j = 0; j < c.r; ++j) {
+            double gr = G[2 * (size_t(p) * c.r + j)], gi = G[2 * (size_t(p) * c.r + j) + 1];
+            double dr = c.D[2 * (size_t(j) * c.r + k)], di = c.D[2 * (size_t(j) * c.r + k) + 1];
+            re += gr * dr - gi * di;
+            im += gr * di + gi * dr;
+          }
+          up[2 * (size_t(p) * H.Rc + k)] = float(re);
+          up[2 * (size_t(p) * H.Rc + k) + 1] = float(im);
+        }
+      float* dn = &Md[size_t(2) * id * H.R * H.Rc];
+      for (int j = 0; j < c.r; ++j)
+        for (int q = 0; q < s.r; ++q) {  // (G^T D^T)[j][q] = sum_p G[p][j] D[q][p]
+          double re = 0.0, im = 0.0;
+          for (int p = 0; p < s.r; ++p) {
+            double gr = G[2 * (size_t(p) * c.r + j)], gi = G[2 * (size_t(p) * c.r + j) + 1];
+            double dr = s.D[2 * (size_t(q) * s.r + p)], di = s.D[2 * (size_t(q) * s.r + p) + 1];
+            re += gr * dr - gi * di;
+            im += gr * di + gi * dr;
+          }
+          dn[2 * (size_t(j) * H.R + q)] = float(re);
+          dn[2 * (size_t(j) * H.R + q) + 1] = float(im);
+        }
+    });
+    H.Mup.upload(Mu);
+    H.Mdn.upload(Md);
+    // M2M children per out-slot
+    {
+      std::vector<int32_t> ch(size_t(8) * H.nout, -1), op(H.nout);
+      const auto& L = T.lv[l];
+      const auto& C = T.lv[l + 1];
+      for (int64_t i = 0; i < H.nout; ++i) {
+        auto [b, d] = OS[l].list[i];
+        op[i] = d * 8;
+        for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c) {
+          int o = int(C.octant[c]);
+          ch[8 * i + o] = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
+        }
+      }
+      H.m2m_child.upload(ch);
+      H.m2m_op.upload(op);
+    }
+    // L2L: child in-slots <- parent in-slots
+    {
+      const auto& C = T.lv[l + 1];
+      if (e == 0) {
+        H.l2l_terms = 6;
+        H.nchild_in = nleaf;
+        std::vector<int32_t> par(size_t(6) * nleaf, -1), op(size_t(6) * nleaf, -1);
+        for (int64_t c = 0; c < nleaf; ++c) {
+          int64_t p = C.parent[c];
+          for (int d = 0; d < 6; ++d) {
+            int64_t s = IS[l].at(p, d);
+            if (s >= 0) {
+              par[6 * c + d] = int32_t(s);
+              op[6 * c + d] = d * 8 + int(C.octant[c]);
+            }
+          }
+        }
+        H.l2l_par.upload(par);
+        H.l2l_op.upload(op);
+      } else {
+        H.l2l_terms = 4;
+        H.nchild_in = int64_t(IS[l + 1].list.size());
+        std::vector<int32_t> par(size_t(4) * H.nchild_in, -1), op(size_t(4) * H.nchild_in, -1);
+        int64_t w2 = w;  // parent width; child width w/2 has (w/2) cells per face edge
+        int64_t wc_i = w / 2;
+        for (int64_t i = 0; i < H.nchild_in; ++i) {
+          auto [c, dc] = IS[l + 1].list[i];
+          int64_t p = C.parent[c];
+          int64_t face = dc / (wc_i * wc_i), rem = dc % (wc_i * wc_i);
+          int64_t ci = rem / wc_i, cj = rem % wc_i;
+          int t = 0;
+          for (int di = 0; di < 2; ++di)
+            for (int dj = 0; dj < 2; ++dj, ++t) {
+              int d = int((face * w2 + 2 * ci + di) * w2 + 2 * cj + dj);
+              int64_t s = IS[l].at(p, d);
+              if (s >= 0) {
+                par[4 * i + t] = int32_t(s);
+                op[4 * i + t] = d * 8 + int(C.octant[c]);
+              }
+            }
+        }
+        H.l2l_par.upload(par);
+        H.l2l_op.upload(op);
+      }
+    }
+    // M2L
+    std::vector<const Skel*> sp;
+    for (auto& s : sk) sp.push_back(&s);
+    build_m2l(pairs[l], double(w), H.R, sp, sp, &OS[l], &IS[l], H.nin, H.T, H.grp_start,
+              H.pair_src, H.red_start, H.red_idx, H.ngroups, H.max_group, H.flops, H.gs_h);
+    info.flops_m2l_hf += H.flops;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  P.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
+  info.plan_seconds = P.plan_seconds;
+}
+
+}  // namespace dfmm

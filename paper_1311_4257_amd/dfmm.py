@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libdfmm (the C ABI declared in include/dfmm.h).
+
+Argument marshalling only: every step of the matvec runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  If the shared
+library has not been built, importing this module raises ImportError -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libdfmm.so not built ({LIB_PATH}); run __graft_entry__.build()")
+
+_lib = C.CDLL(LIB_PATH)
+
+EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
+
+ABI_FUNCTIONS = [
+    "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
+    "dfmm_opset_set", "dfmm_opset_get", "dfmm_opset_info", "dfmm_opset_save", "dfmm_opset_load",
+    "dfmm_opset_destroy", "dfmm_options_default", "dfmm_plan", "dfmm_plan_ex", "dfmm_apply",
+    "dfmm_destroy", "dfmm_plan_info", "dfmm_export", "dfmm_set_timing", "dfmm_stage_times",
+]
+
+
+class Options(C.Structure):
+    _fields_ = [("eps", C.c_double), ("opset", C.c_void_p), ("cache_dir", C.c_char_p),
+                ("device", C.c_int), ("reserved", C.c_int * 7)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("K", C.c_double), ("depth", C.c_int), ("w_top", C.c_int),
+                ("nlevels_hf", C.c_int), ("boxes", C.c_int64 * 32), ("pairs", C.c_int64 * 32),
+                ("offsets", C.c_int64 * 32), ("out_slots", C.c_int64 * 32),
+                ("in_slots", C.c_int64 * 32), ("rank", C.c_int * 32), ("near_pairs", C.c_int64),
+                ("near_point_pairs", C.c_int64), ("flops_m2l_hf", C.c_double),
+                ("flops_m2l_lf", C.c_double), ("plan_seconds", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_sig = {
+    "dfmm_status_string": (C.c_char_p, [C.c_int]),
+    "dfmm_last_error": (C.c_char_p, []),
+    "dfmm_opset_build": (C.c_int, [C.c_double, C.c_int, C.c_char_p, C.POINTER(_P)]),
+    "dfmm_opset_create": (C.c_int, [C.c_double, C.c_int, C.POINTER(_P)]),
+    "dfmm_opset_set": (C.c_int, [_P, C.c_double, C.c_int, C.c_int, _D, _D, _D]),
+    "dfmm_opset_get": (C.c_int, [_P, C.c_double, C.c_int, C.POINTER(C.c_int), _D, _D, _D]),
+    "dfmm_opset_info": (C.c_int, [_P, _D, C.POINTER(C.c_int)]),
+    "dfmm_opset_save": (C.c_int, [_P, C.c_char_p]),
+    "dfmm_opset_load": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
+    "dfmm_opset_destroy": (None, [_P]),
+    "dfmm_options_default": (None, [C.POINTER(Options)]),
+    "dfmm_plan": (C.c_int, [_D, C.c_int64, C.c_double, C.c_double, C.POINTER(_P)]),
+    "dfmm_plan_ex": (C.c_int, [_D, C.c_int64, C.c_double, C.POINTER(Options), C.POINTER(_P)]),
+    "dfmm_apply": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "dfmm_destroy": (None, [_P]),
+    "dfmm_plan_info": (C.c_int, [_P, C.POINTER(Info)]),
+    "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "dfmm_set_timing": (C.c_int, [_P, C.c_int]),
+    "dfmm_stage_times": (C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class DfmmError(RuntimeError):
+    def __init__(self, status: int):
+        self.status = status
+        name = _lib.dfmm_status_string(status).decode()
+        detail = _lib.dfmm_last_error().decode()
+        super().__init__(f"{name}: {detail}")
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise DfmmError(status)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+class OpSet:
+    """Directional skeletons (a, b, D) of Eq. 2 for widths 1/2 (LF) and 1 .. w_hi."""
+
+    def __init__(self, handle):
+        self._h = _P(handle)
+
+    @classmethod
+    def build(cls, tau: float, w_hi: int, cache_dir: str | None = None) -> "OpSet":
+        h = _P()
+        _check(_lib.dfmm_opset_build(tau, w_hi, cache_dir.encode() if cache_dir else None, C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def create(cls, tau: float, w_hi: int) -> "OpSet":
+        h = _P()
+        _check(_lib.dfmm_opset_create(tau, w_hi, C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str) -> "OpSet":
+        h = _P()
+        _check(_lib.dfmm_opset_load(path.encode(), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str) -> None:
+        _check(_lib.dfmm_opset_save(self._h, path.encode()))
+
+    def set(self, w: float, d: int, a, b, D) -> None:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        Dm = np.ascontiguousarray(np.asarray(D, dtype=np.complex128)).view(np.float64)
+        r = a.shape[0]
+        _check(_lib.dfmm_opset_set(self._h, float(w), int(d), r, _dptr(a), _dptr(b), _dptr(Dm)))
+
+    def get(self, w: float, d: int):
+        r = C.c_int()
+        _check(_lib.dfmm_opset_get(self._h, float(w), int(d), C.byref(r), None, None, None))
+        n = r.value
+        a = np.empty((n, 3))
+        b = np.empty((n, 3))
+        D = np.empty((n, n), dtype=np.complex128)
+        _check(_lib.dfmm_opset_get(self._h, float(w), int(d), C.byref(r), _dptr(a), _dptr(b),
+                                   D.view(np.float64).ctypes.data_as(_D)))
+        return a, b, D
+
+    def info(self):
+        tau = C.c_double()
+        w = C.c_int()
+        _check(_lib.dfmm_opset_info(self._h, C.byref(tau), C.byref(w)))
+        return tau.value, w.value
+
+    def close(self) -> None:
+        if self._h:
+            _lib.dfmm_opset_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A resident plan for one point set: dfmm_plan / dfmm_plan_ex."""
+
+    def __init__(self, points, K: float, eps: float = 1e-4, opset: OpSet | None = None,
+                 cache_dir: str | None = None, device: int = -1):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must be (N, 3)")
+        opt = Options()
+        _lib.dfmm_options_default(C.byref(opt))
+        opt.eps = eps
+        opt.opset = opset._h.value if opset is not None else None
+        self._cache = cache_dir.encode() if cache_dir else None
+        opt.cache_dir = self._cache
+        opt.device = device
+        h = _P()
+        _check(_lib.dfmm_plan_ex(_dptr(pts), pts.shape[0], float(K), C.byref(opt), C.byref(h)))
+        self._h = h
+        self.N = pts.shape[0]
+        self.K = K
+
+    def apply(self, f, u=None, stream=None):
+        """u = A f for a (nrhs, N) complex64 CUDA tensor f (or (N,)); returns u."""
+        import torch
+
+        one = f.dim() == 1
+        f2 = f.reshape(1, -1) if one else f
+        if f2.dtype != torch.complex64 or not f2.is_cuda or not f2.is_contiguous():
+            raise ValueError("f must be a contiguous complex64 CUDA tensor")
+        if f2.shape[1] != self.N:
+            raise ValueError("f has the wrong number of points")
+        if u is None:
+            u = torch.empty_like(f2)
+        if stream is None:
+            stream = torch.cuda.current_stream(f2.device)
+        _check(_lib.dfmm_apply(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u.data_ptr()),
+                               f2.shape[0], C.c_void_p(stream.cuda_stream)))
+        return u.reshape(-1) if one else u
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(_lib.dfmm_plan_info(self._h, C.byref(inf)))
+        return inf
+
+    def export(self, what: int, level: int = 0) -> np.ndarray:
+        n = C.c_size_t()
+        _check(_lib.dfmm_export(self._h, what, level, None, C.byref(n)))
+        buf = np.empty(n.value // 8, dtype=np.int64)
+        _check(_lib.dfmm_export(self._h, what, level, buf.ctypes.data_as(C.c_void_p), C.byref(n)))
+        width = {EXPORT_PERM: 1, EXPORT_BOXES: 5, EXPORT_PAIRS: 5, EXPORT_NEAR: 2,
+                 EXPORT_OUT_SLOTS: 2, EXPORT_IN_SLOTS: 2}[what]
+        return buf if width == 1 else buf.reshape(-1, width)
+
+    def set_timing(self, on: bool = True) -> None:
+        _check(_lib.dfmm_set_timing(self._h, 1 if on else 0))
+
+    def stage_times(self) -> list:
+        out = (C.c_double * 16)()
+        n = C.c_int()
+        _check(_lib.dfmm_stage_times(self._h, out, 16, C.byref(n)))
+        return list(out[: n.value])
+
+    def close(self) -> None:
+        if self._h:
+            _lib.dfmm_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def status_string(s: int) -> str:
+    return _lib.dfmm_status_string(s).decode()

@@ -1,0 +1,120 @@
+"""GPU parity: libdfmm through its C ABI against the CPU float64 oracle.
+
+* Structures (tree, lists, wedges, needed slots) must match the oracle bit for bit.
+* With the oracle's own skeletons injected (dfmm_opset_set), the GPU matvec must
+  reproduce the oracle's FMM element by element to float32 rounding.
+* With the library's own skeletons, the matvec must meet eps against the
+  float64 direct sum of Eq. 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle.fmm import fmm_apply
+from oracle.kernel import direct_sum, rel_l2
+from oracle.tree import build_structure
+from paper_1311_4257_amd import workloads
+from tests.helpers import inject, oracle_opset
+
+pytestmark = pytest.mark.gpu
+
+
+def _dfmm():
+    from paper_1311_4257_amd import dfmm
+
+    return dfmm
+
+
+def _to_dev(f, cuda):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(f.astype(np.complex64))).to(cuda)
+
+
+def _compare_structure(plan, st):
+    dfmm = _dfmm()
+    tr = st.tree
+    assert np.array_equal(plan.export(dfmm.EXPORT_PERM), tr.perm)
+    for l in range(tr.D + 1):
+        lv = tr.levels[l]
+        bx = plan.export(dfmm.EXPORT_BOXES, l)
+        assert np.array_equal(bx[:, :3], lv.coords), l
+        assert np.array_equal(bx[:, 3], lv.start) and np.array_equal(bx[:, 4], lv.end), l
+    for l, pl in st.lists.items():
+        pr = plan.export(dfmm.EXPORT_PAIRS, l)
+        assert len(pr) == len(pl.tgt), l
+        if len(pr):
+            assert np.array_equal(pr[:, 0], pl.tgt) and np.array_equal(pr[:, 1], pl.src), l
+            assert np.array_equal(pr[:, 2], pl.dir_in) and np.array_equal(pr[:, 3], pl.dir_out), l
+    nr = plan.export(dfmm.EXPORT_NEAR)
+    assert np.array_equal(nr[:, 0], st.near.tgt) and np.array_equal(nr[:, 1], st.near.src)
+    for l in st.out_slots:
+        assert np.array_equal(plan.export(dfmm.EXPORT_OUT_SLOTS, l), st.out_slots[l]), l
+        assert np.array_equal(plan.export(dfmm.EXPORT_IN_SLOTS, l), st.in_slots[l]), l
+
+
+@pytest.mark.parametrize("name,N", [("sphere4", 4096), ("sphere16", 16384)])
+def test_structure_bit_exact(cuda, name, N):
+    pts, _, cfg = workloads.make_config(name, N=N)
+    st = build_structure(pts, cfg["K"])
+    ops = inject(oracle_opset(1e-3, max(1, st.w_top)))
+    plan = _dfmm().Plan(pts, cfg["K"], opset=ops, device=0)
+    _compare_structure(plan, st)
+    info = plan.info()
+    assert info.w_top == st.w_top
+
+
+def test_injected_skeletons_match_oracle_fmm(cuda):
+    """Same skeletons on both sides: the GPU pass equals the oracle pass to float32 rounding."""
+    pts, f, cfg = workloads.make_config("sphere4")
+    st = build_structure(pts, cfg["K"])
+    oops = oracle_opset(1e-4, 1)
+    u_orc = fmm_apply(st, oops, f)
+    plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oops), device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy().astype(np.complex128)
+    err = rel_l2(u, u_orc)
+    worst = np.max(np.abs(u - u_orc)) / np.max(np.abs(u_orc))
+    print(f"injected sphere4: rel L2 {err:.2e}  max {worst:.2e}")
+    assert err < 5e-6
+    assert worst < 5e-6
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_sphere4_vs_direct_sum(cuda, eps, tmp_path):
+    pts, f, cfg = workloads.make_config("sphere4")
+    plan = _dfmm().Plan(pts, cfg["K"], eps=eps, cache_dir=str(tmp_path), device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    err = rel_l2(u, direct_sum(pts, f))
+    print(f"sphere4 eps={eps:g}: rel L2 vs direct sum {err:.2e}, ranks {list(plan.info().rank)[:4]}")
+    assert err <= eps
+
+
+def test_nrhs_batch_equals_single(cuda):
+    pts, _, cfg = workloads.make_config("sphere4", N=2048)
+    f = workloads.densities(len(pts), 5, seed=7)
+    plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oracle_opset(1e-3, 1)), device=0)
+    ub = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    for j in range(5):
+        u1 = plan.apply(_to_dev(f[j:j + 1], cuda)).cpu().numpy()
+        assert np.array_equal(u1[0], ub[j]), j
+
+
+def test_repeat_is_bitwise_deterministic(cuda):
+    pts, f, cfg = workloads.make_config("sphere4", N=2048)
+    plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oracle_opset(1e-3, 1)), device=0)
+    fd = _to_dev(f, cuda)
+    a = plan.apply(fd).cpu().numpy()
+    b = plan.apply(fd).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_sphere16_full_size_sampled_targets(cuda, tmp_path):
+    """The benchmark workload (K = 16 sphere, N = 65,536, eps = 1e-4) on 2,048 sampled targets."""
+    pts, f, cfg = workloads.make_config("sphere16")
+    plan = _dfmm().Plan(pts, cfg["K"], eps=cfg["eps"], cache_dir=str(tmp_path), device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    tg = workloads.sample_targets(len(pts), cfg["n_check"], cfg["check_seed"])
+    err = rel_l2(u[:, tg], direct_sum(pts, f, tg))
+    print(f"sphere16: rel L2 vs direct sum on {len(tg)} targets {err:.2e}")
+    assert err <= cfg["eps"]
