@@ -1,0 +1,99 @@
+"""The C ABI on the CPU: the library loads, exports every symbol declared in
+include/dfmm.h, rejects bad input before touching a device, and builds its
+float64 skeletons (host code) to the Eq. 2 accuracy."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dfmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfmm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1311_4257_amd import dfmm
+
+    lib = ctypes.CDLL(dfmm.LIB_PATH)
+    names = _declared()
+    assert "dfmm_plan" in names and "dfmm_apply" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dfmm.ABI_FUNCTIONS)
+
+
+def test_bad_inputs_rejected_on_the_host():
+    from paper_1311_4257_amd import dfmm
+
+    good = np.zeros((4, 3))
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 3.0)                       # K not a power of two
+    with pytest.raises(dfmm.DfmmError, match="EDOMAIN"):
+        dfmm.Plan(np.array([[3.0, 0.0, 0.0]]), 4.0)   # |p| > K/2
+    with pytest.raises(dfmm.DfmmError, match="EDOMAIN"):
+        dfmm.Plan(np.array([[np.nan, 0.0, 0.0]]), 4.0)
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 4.0, eps=0.5)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(np.zeros((0, 3)), 4.0)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.OpSet.build(1e-4, 3)                  # w_hi not a power of two
+
+
+def test_library_skeletons_meet_eq2_on_fresh_samples(tmp_path):
+    from oracle import operators as O
+    from paper_1311_4257_amd import dfmm
+
+    tau = 1e-3
+    s = dfmm.OpSet.build(tau, 1, str(tmp_path))
+    s2 = dfmm.OpSet.build(tau, 1, str(tmp_path))   # second call reads the cache
+    rng = np.random.default_rng(5)
+    offs = O.region_offsets(1.0)
+    dirs = np.array([O.direction(n, 1) for n in offs.tolist()])
+    ranks = []
+    for d in range(6):
+        a, b, D = s.get(1.0, d)
+        a2, b2, D2 = s2.get(1.0, d)
+        assert np.array_equal(a, a2) and np.array_equal(D, D2)
+        ranks.append(len(b))
+        assert np.all(np.abs(b) <= 0.5 + 1e-12)        # equivalent points inside the box
+        X = O._sample_boxes(rng, offs[dirs == d] * 1.0, 1.0, 600)
+        Y = rng.random((300, 3)) - 0.5
+        assert O.heldout_error(O.Skeleton(a=a, b=b, D=D), X, Y) < 10 * tau, d
+    a, b, D = s.get(0.5, 0)
+    X = O._sample_boxes(rng, O.region_offsets(0.5) * 0.5, 0.5, 600)
+    Y = (rng.random((300, 3)) - 0.5) * 0.5
+    assert O.heldout_error(O.Skeleton(a=a, b=b, D=D), X, Y) < 10 * tau
+    # the oracle's ranks at the same tau are a cross-check (same criterion, own samples)
+    from tests.helpers import oracle_opset
+
+    orc = oracle_opset(tau, 1)
+    assert abs(max(ranks) - orc.rank(1)) <= 0.15 * orc.rank(1)
+
+
+def test_opset_roundtrip_and_injection(tmp_path):
+    from paper_1311_4257_amd import dfmm
+
+    s = dfmm.OpSet.create(1e-3, 1)
+    rng = np.random.default_rng(1)
+    for w, nd in [(1.0, 6), (0.5, 1)]:
+        for d in range(nd):
+            r = 5 + d
+            s.set(w, d, rng.random((r, 3)), rng.random((r, 3)),
+                  rng.random((r, r)) + 1j * rng.random((r, r)))
+    p = str(tmp_path / "ops.bin")
+    s.save(p)
+    t = dfmm.OpSet.load(p)
+    for w, nd in [(1.0, 6), (0.5, 1)]:
+        for d in range(nd):
+            for x, y in zip(s.get(w, d), t.get(w, d)):
+                assert np.array_equal(x, y)
+    assert t.info() == (1e-3, 1)
