@@ -165,12 +165,19 @@ enum {
 };
 int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes);
 
-/* Per-stage device times (milliseconds) of the last apply on this plan, when
- * stage timing was enabled with dfmm_set_timing(plan, 1).  Stages, in order:
- * 0 permute-in, 1 S2M, 2 HF-M2M, 3 HF-M2L, 4 HF-L2L, 5 LF-M2L, 6 L2T,
- * 7 near field, 8 permute-out.  n receives the count written (<= cap). */
-int dfmm_set_timing(dfmm_plan_t plan, int enable);
-int dfmm_stage_times(dfmm_plan_t plan, double* ms, int cap, int* n);
+/* Stage timing with HIP events recorded on the apply stream after every
+ * launch (no host synchronisation inside dfmm_apply).  dfmm_set_timing(plan, n)
+ * enables recording for up to n following applies (n = 0 disables and frees
+ * the events).  dfmm_stage_times waits for the recorded work, writes per stage
+ * the summed milliseconds and the number of launches over all recorded
+ * applies, and restarts the recording.  Stages, in order:
+ *   0 permute-in, 1 S2M, 2 HF-M2M, 3 HF-M2L (grouped GEMM), 4 HF-M2L reduction,
+ *   5 HF-L2L, 6 LF-M2L (grouped GEMM), 7 LF-M2L reduction,
+ *   8 leaf evaluation (L2T + near field + permute-out), 9 zero fill.
+ * *n receives the number of stages written (<= cap). */
+enum { DFMM_NUM_STAGES = 10 };
+int dfmm_set_timing(dfmm_plan_t plan, int applies);
+int dfmm_stage_times(dfmm_plan_t plan, double* ms, int64_t* launches, int cap, int* n);
 
 #ifdef __cplusplus
 }

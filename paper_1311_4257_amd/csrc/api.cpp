@@ -303,6 +303,8 @@ void dfmm_destroy(dfmm_plan_t plan) {
   if (hipGetDevice(&cur) == hipSuccess && cur != plan->device) (void)hipSetDevice(plan->device);
   destroy_apply_state(plan->ws);
   plan->ws = nullptr;
+  delete plan->timer;
+  plan->timer = nullptr;
   delete plan;
   if (cur != 0) (void)hipSetDevice(cur);
 }
@@ -340,18 +342,32 @@ int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes)
   });
 }
 
-int dfmm_set_timing(dfmm_plan_t plan, int enable) {
-  if (!plan) return fail(DFMM_EINVAL, "null plan");
-  plan->timing = enable != 0;
-  return DFMM_OK;
+int dfmm_set_timing(dfmm_plan_t plan, int applies) {
+  return guarded([&]() {
+    if (!plan) return fail(DFMM_EINVAL, "null plan");
+    if (applies < 0 || applies > 100000) return fail(DFMM_EINVAL, "applies must be in [0, 100000]");
+    delete plan->timer;
+    plan->timer = nullptr;
+    if (applies > 0) plan->timer = new StageTimer(applies);
+    return int(DFMM_OK);
+  });
 }
 
-int dfmm_stage_times(dfmm_plan_t plan, double* ms, int cap, int* n) {
-  if (!plan || !n) return fail(DFMM_EINVAL, "null argument");
-  int k = int(std::min<size_t>(plan->stage_ms.size(), size_t(cap < 0 ? 0 : cap)));
-  for (int i = 0; i < k; ++i) ms[i] = plan->stage_ms[i];
-  *n = k;
-  return DFMM_OK;
+int dfmm_stage_times(dfmm_plan_t plan, double* ms, int64_t* launches, int cap, int* n) {
+  return guarded([&]() {
+    if (!plan || !n || !ms || !launches) return fail(DFMM_EINVAL, "null argument");
+    if (!plan->timer) return fail(DFMM_EINVAL, "timing is not enabled on this plan");
+    double t[ST_COUNT];
+    int64_t c[ST_COUNT];
+    plan->timer->collect(t, c);
+    int k = std::min(cap < 0 ? 0 : cap, int(ST_COUNT));
+    for (int i = 0; i < k; ++i) {
+      ms[i] = t[i];
+      launches[i] = c[i];
+    }
+    *n = k;
+    return int(DFMM_OK);
+  });
 }
 
 }  // extern "C"

@@ -29,14 +29,17 @@ __device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
 }
 
-// G for a separation (dx, dy, dz) in float32: e^{2 pi i r} / r, 0 at r = 0.
-__device__ __forceinline__ float2 green32(float dx, float dy, float dz) {
-  float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  if (r2 == 0.0f) return make_float2(0.0f, 0.0f);
-  float ri = rsqrtf(r2);
-  float r = r2 * ri;
+// G for a separation given in float64: the distance and the phase reduction
+// r - rint(r) are done in float64 (the phase error stays ~2e-7 rad however far
+// apart the points are), sin/cos of the reduced phase and 1/r in float32.
+__device__ __forceinline__ float2 green_d(double dx, double dy, double dz) {
+  double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  if (r2 == 0.0) return make_float2(0.0f, 0.0f);
+  double r = sqrt(r2);
+  float t = float(r - rint(r));
   float s, c;
-  sincospif(2.0f * r, &s, &c);
+  sincospif(2.0f * t, &s, &c);
+  float ri = rsqrtf(float(r2));
   return make_float2(c * ri, s * ri);
 }
 
@@ -52,130 +55,212 @@ __global__ void k_permute_in(const float2* __restrict__ f, float2* __restrict__ 
   fs[i] = f[int64_t(k) * N + perm[s]];
 }
 
-// ---- leaf S2M: outgoing check potentials at c_B + a_p ---------------------------
-// One block per leaf; threads over check points.  LDS holds a chunk of the
-// leaf's points (local coordinates) and densities.  The check-to-equivalent
-// matrix D_LF is folded into the operators that read these potentials.
+// ---- per-point leaf weights (plan time, float64) -----------------------------------
+// For sorted point j in leaf B (centre c):
+//   V[j][p] = G(c + a_p, x_j)                       (S2M: check potential weights)
+//   W[j][q] = sum_p G(x_j, c + a_p) D_LF[q][p]      (L2T: incoming check potentials
+//                                                    at b_q -> potential at x_j)
+// W is formed in float64 because the incoming equivalent charges D^T U are
+// large and cancel; the product is a well-scaled interpolation weight that
+// float32 holds without loss.  One block per leaf, points in sequence.
+constexpr int LW_BS = 64;
+__global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict__ pts, const int* __restrict__ lstart,
+                                                         const float4* __restrict__ lcen,
+                                                         const double4* __restrict__ a_lf,
+                                                         const double2* __restrict__ DT, int R, int Ra,
+                                                         float2* __restrict__ V, float2* __restrict__ W) {
+  extern __shared__ double2 gs[];  // Ra
+  const int b = blockIdx.x;
+  const float4 c = lcen[b];
+  for (int j = lstart[b]; j < lstart[b + 1]; ++j) {
+    const double x = pts[3 * int64_t(j)] - double(c.x);
+    const double y = pts[3 * int64_t(j) + 1] - double(c.y);
+    const double z = pts[3 * int64_t(j) + 2] - double(c.z);
+    __syncthreads();
+    for (int p = threadIdx.x; p < R; p += LW_BS) {
+      double2 gv = make_double2(0.0, 0.0);
+      if (p < Ra) {
+        const double4 ap = a_lf[p];
+        const double dx = x - ap.x, dy = y - ap.y, dz = z - ap.z;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double sn, cs;
+        sincospi(2.0 * r, &sn, &cs);
+        gv = make_double2(cs / r, sn / r);
+        gs[p] = gv;
+      }
+      V[int64_t(j) * R + p] = make_float2(float(gv.x), float(gv.y));
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < R; q += LW_BS) {
+      double wr = 0.0, wi = 0.0;
+      for (int p = 0; p < Ra; ++p) {
+        const double2 gv = gs[p], d = DT[int64_t(p) * R + q];
+        wr += gv.x * d.x - gv.y * d.y;
+        wi += gv.x * d.y + gv.y * d.x;
+      }
+      W[int64_t(j) * R + q] = make_float2(float(wr), float(wi));
+    }
+  }
+}
+
+// ---- leaf S2M: outgoing check potentials chk[p] = sum_j V[j][p] f_j ----------------
+// One block per leaf, threads over check points (the weights of consecutive
+// check points are contiguous).  D_LF is folded into the operators that read
+// these potentials.
 constexpr int S2M_BS = 128;
-__global__ void __launch_bounds__(S2M_BS) k_s2m(const float4* __restrict__ phi, const float4* __restrict__ plo,
-                                                 const int* __restrict__ lstart, const float4* __restrict__ lcen,
-                                                 const float2* __restrict__ fs, const float4* __restrict__ a_lf,
-                                                 int R, int Ra, int nrhs, float2* __restrict__ clf) {
-  __shared__ float4 xs[S2M_BS];
-  __shared__ float2 fv[S2M_BS * RC];
+__global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, const float2* __restrict__ V,
+                                                 const float2* __restrict__ fs, int R, int nrhs,
+                                                 float2* __restrict__ clf) {
   const int b = blockIdx.x;
   const int s0 = lstart[b], s1 = lstart[b + 1];
-  const float4 c = lcen[b];
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int nk = min(RC, nrhs - k0);
-    for (int p0 = 0; p0 < R; p0 += S2M_BS) {
-      int p = p0 + threadIdx.x;
+    for (int p = threadIdx.x; p < R; p += S2M_BS) {
       float2 acc[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
-      float4 ap = p < Ra ? a_lf[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int j0 = s0; j0 < s1; j0 += S2M_BS) {
-        __syncthreads();
-        int j = j0 + threadIdx.x;
-        if (j < s1) {
-          float4 h = phi[j], l = plo[j];
-          xs[threadIdx.x] = make_float4((h.x - c.x) + l.x, (h.y - c.y) + l.y, (h.z - c.z) + l.z, 0.f);
-          for (int k = 0; k < nk; ++k) fv[threadIdx.x * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
-        }
-        __syncthreads();
-        int nj = min(S2M_BS, s1 - j0);
-        if (p < Ra) {
-          for (int t = 0; t < nj; ++t) {
-            float4 x = xs[t];
-            float2 g = green32(ap.x - x.x, ap.y - x.y, ap.z - x.z);
+      for (int j = s0; j < s1; ++j) {
+        const float2 v = V[int64_t(j) * R + p];
 #pragma unroll
-            for (int k = 0; k < RC; ++k)
-              if (k < nk) cfma(acc[k], g, fv[t * RC + k]);
+        for (int k = 0; k < RC; ++k)
+          if (k < nk) cfma(acc[k], v, fs[int64_t(j) * nrhs + k0 + k]);
+      }
+      for (int k = 0; k < nk; ++k) clf[(int64_t(b) * nrhs + k0 + k) * R + p] = acc[k];
+    }
+  }
+}
+
+// ---- grouped gather GEMM on MFMA: Y[vdst] = sum_t A[op_t] X[vsrc_t] --------------
+// The complex product y = A x is done as a real product on interleaved data:
+// real row 2q (re) of A is (Re A[q][p], -Im A[q][p]) per column pair (2p, 2p+1)
+// and row 2q+1 (im) is (Im, Re); x and y stay in their natural interleaved
+// layout.  One workgroup (4 waves) computes all 2M real rows of NT*16 vector
+// columns; wave w owns the 16-row M-tiles w, w+4, ... of its M-slice
+// (blockIdx.y of gridDim.y slices: tile m belongs to slice (m / 4) % slices,
+// which adds workgroups when a launch has few column chunks).  The K dimension is
+// split into four quarters, one per group of 16 lanes (MFMA k index), so a
+// lane reads four consecutive k values of its quarter with one 16-byte load
+// from LDS (B) and from the fragment-ordered operator (A).  The column block
+// of each term sits in LDS, [column][k] with a row stride S = 4 (mod 32) floats.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int GG_BS = 256;
+
+__host__ __device__ inline int gg_stride(int K) {
+  int s = 2 * K;
+  return s + ((4 - (s % 32)) + 32) % 32;
+}
+
+template <int MT, int NT>
+__global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, int M, int K, int T,
+                                                  const int* __restrict__ gops, const int* __restrict__ gv0,
+                                                  const int* __restrict__ vsrc, const int* __restrict__ vdst,
+                                                  const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
+                                                  int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
+  extern __shared__ float4 xs[];
+  constexpr int NC = NT * 16;
+  const int S = gg_stride(K);           // floats per LDS column
+  const int S4 = S / 4;
+  const int Q4 = K / 8;                 // float4 steps per K quarter (K/2 real k per quarter)
+  const int nM = M / 8;                 // 16-row real M-tiles
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j = lane & 15, kr = lane >> 4;
+  const int slice = blockIdx.y, nslice = gridDim.y;
+  const int g = chunk_grp[blockIdx.x];
+  const int64_t c0 = chunk_c0[blockIdx.x];
+  const int vbeg = gv0[g];
+  const int64_t ncol = int64_t(gv0[g + 1] - vbeg) * nrhs;
+  const int nc = int(min<int64_t>(NC, ncol - c0));
+  const int64_t opsz = int64_t(M) * K / 2;  // float4 per operator
+
+  v4f acc[MT][NT];
+#pragma unroll
+  for (int mm = 0; mm < MT; ++mm)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[mm][n] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = 0; t < T; ++t) {
+    const int op = gops[g * T + t];
+    if (op < 0) continue;
+    __syncthreads();
+    // stage the source vectors of this term: column c -> X[(src * nrhs + k) * K]
+    const int per_col = K / 2;  // float4 per column
+    for (int idx = threadIdx.x; idx < NC * per_col; idx += GG_BS) {
+      int col = idx / per_col, q4 = idx % per_col;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (col < nc) {
+        int64_t cc = c0 + col;
+        int vv = vbeg + int(cc / nrhs);
+        int k = int(cc % nrhs);
+        int src = vsrc[int64_t(vv) * T + t];
+        if (src >= 0) v = reinterpret_cast<const float4*>(X + (int64_t(src) * nrhs + k) * K)[q4];
+      }
+      xs[col * S4 + q4] = v;
+    }
+    __syncthreads();
+    const float4* Aop = A + int64_t(op) * opsz;
+    // register double buffering: the A and B fragments of step s4 + 1 are in
+    // flight while the MFMAs of step s4 run
+    float4 ca[MT], cb[NT];
+#pragma unroll
+    for (int mm = 0; mm < MT; ++mm) {
+      const int m = wave + 4 * (slice + nslice * mm);
+      ca[mm] = m < nM ? Aop[((int64_t(m) * Q4) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) cb[n] = xs[(n * 16 + j) * S4 + kr * Q4];
+    for (int s4 = 0; s4 < Q4; ++s4) {
+      const int sn = s4 + 1 < Q4 ? s4 + 1 : s4;
+      float4 na[MT], nb[NT];
+#pragma unroll
+      for (int mm = 0; mm < MT; ++mm) {
+        const int m = wave + 4 * (slice + nslice * mm);
+        na[mm] = m < nM ? Aop[((int64_t(m) * Q4 + sn) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int n = 0; n < NT; ++n) nb[n] = xs[(n * 16 + j) * S4 + kr * Q4 + sn];
+#pragma unroll
+      for (int mm = 0; mm < MT; ++mm) {
+        const int m = wave + 4 * (slice + nslice * mm);
+        if (m < nM) {
+          const float4 c = ca[mm];
+          float a0, a1, a2, a3;
+          if (j & 1) {
+            a0 = c.y; a1 = c.x; a2 = c.w; a3 = c.z;
+          } else {
+            a0 = c.x; a1 = -c.y; a2 = c.z; a3 = -c.w;
+          }
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, cb[n].x, acc[mm][n], 0, 0, 0);
+            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, cb[n].y, acc[mm][n], 0, 0, 0);
+            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, cb[n].z, acc[mm][n], 0, 0, 0);
+            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, cb[n].w, acc[mm][n], 0, 0, 0);
           }
         }
       }
-      if (p < R)
-        for (int k = 0; k < nk; ++k) clf[(int64_t(b) * R + p) * nrhs + k0 + k] = acc[k];
+#pragma unroll
+      for (int mm = 0; mm < MT; ++mm) ca[mm] = na[mm];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) cb[n] = nb[n];
     }
   }
-}
-
-// ---- HF-M2M: F[slot] = sum_o M[dir, o] Fchild[child_o] ------------------------
-constexpr int M2M_BS = 128;
-__global__ void __launch_bounds__(M2M_BS) k_m2m(const int* __restrict__ child, const int* __restrict__ opb,
-                                                 const float2* __restrict__ M, const float2* __restrict__ Fc,
-                                                 int R, int Rc, int nrhs, float2* __restrict__ F) {
-  extern __shared__ float2 xs[];  // 8 * Rc * RC
-  const int64_t i = blockIdx.x;
-  const int base = opb[i];
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int nk = min(RC, nrhs - k0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < 8 * Rc * RC; t += M2M_BS) {
-      int o = t / (Rc * RC), rem = t % (Rc * RC), p = rem / RC, k = rem % RC;
-      int c = child[8 * i + o];
-      xs[t] = (c >= 0 && k < nk) ? Fc[(int64_t(c) * Rc + p) * nrhs + k0 + k] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < R; q += M2M_BS) {
-      float2 acc[RC];
+  // lane holds real rows 4*kr .. 4*kr+3 of each M-tile = complex rows 2kr, 2kr+1
 #pragma unroll
-      for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
-      for (int o = 0; o < 8; ++o) {
-        if (child[8 * i + o] < 0) continue;
-        const float2* Mo = M + (int64_t(base + o) * R + q) * Rc;
-        const float2* xo = xs + o * Rc * RC;
-        for (int p = 0; p < Rc; ++p) {
-          float2 m = Mo[p];
+  for (int n = 0; n < NT; ++n) {
+    const int col = n * 16 + j;
+    if (col >= nc) continue;
+    int64_t cc = c0 + col;
+    int vv = vbeg + int(cc / nrhs);
+    int k = int(cc % nrhs);
+    float2* y = Y + (int64_t(vdst[vv]) * nrhs + k) * M;
 #pragma unroll
-          for (int k = 0; k < RC; ++k) cfma(acc[k], m, xo[p * RC + k]);
-        }
+    for (int mm = 0; mm < MT; ++mm) {
+      const int m = wave + 4 * (slice + nslice * mm);
+      if (m < nM) {
+        v4f a = acc[mm][n];
+        reinterpret_cast<float4*>(y + 8 * m + 2 * kr)[0] = make_float4(a[0], a[1], a[2], a[3]);
       }
-      for (int k = 0; k < nk; ++k) F[(i * R + q) * nrhs + k0 + k] = acc[k];
-    }
-  }
-}
-
-// ---- M2L grouped by offset: Y[pos] = T[g] F[src[pos]] ---------------------------
-// One block per (group, chunk of 64 columns); a column is (pair, rhs).  The
-// source vectors of the chunk sit in LDS as [row][column]; T is read from
-// global memory (one row per wave step, uniform across the wave).
-constexpr int M2L_BS = 256;
-constexpr int M2L_COLS = 32;
-__global__ void __launch_bounds__(M2L_BS) k_m2l(const int* __restrict__ gstart, const int* __restrict__ src,
-                                                 const float2* __restrict__ T, const float2* __restrict__ F,
-                                                 int R, int nrhs, const int* __restrict__ chunk_grp,
-                                                 const int* __restrict__ chunk_col0, float2* __restrict__ Y) {
-  extern __shared__ float2 xs[];  // R * M2L_COLS
-  const int g = chunk_grp[blockIdx.x];
-  const int64_t c0 = chunk_col0[blockIdx.x];
-  const int64_t p0 = gstart[g], p1 = gstart[g + 1];
-  const int64_t ncol = (p1 - p0) * nrhs;
-  const int nc = int(min<int64_t>(M2L_COLS, ncol - c0));
-  for (int t = threadIdx.x; t < R * M2L_COLS; t += M2L_BS) {
-    int row = t / M2L_COLS, col = t % M2L_COLS;
-    float2 v = make_float2(0.f, 0.f);
-    if (col < nc) {
-      int64_t cc = c0 + col;
-      int64_t pos = p0 + cc / nrhs;
-      int k = int(cc % nrhs);
-      v = F[(int64_t(src[pos]) * R + row) * nrhs + k];
-    }
-    xs[t] = v;
-  }
-  __syncthreads();
-  const int col = threadIdx.x % M2L_COLS;
-  const int rb = threadIdx.x / M2L_COLS;
-  const float2* Tg = T + int64_t(g) * R * R;
-  for (int q = rb; q < R; q += M2L_BS / M2L_COLS) {
-    float2 acc = make_float2(0.f, 0.f);
-    const float2* Tq = Tg + int64_t(q) * R;
-    for (int p = 0; p < R; ++p) cfma(acc, Tq[p], xs[p * M2L_COLS + col]);
-    if (col < nc) {
-      int64_t cc = c0 + col;
-      int64_t pos = p0 + cc / nrhs;
-      int k = int(cc % nrhs);
-      Y[(pos * R + q) * nrhs + k] = acc;
     }
   }
 }
@@ -196,150 +281,86 @@ __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri,
   U[t] = acc;
 }
 
-// ---- HF-L2L: Uc[child] = sum_t Mdn[op_t] U[par_t] ----------------------------------
-constexpr int L2L_BS = 128;
-__global__ void __launch_bounds__(L2L_BS) k_l2l(const int* __restrict__ par, const int* __restrict__ op,
-                                                 int terms, const float2* __restrict__ M,
-                                                 const float2* __restrict__ U, int R, int Rc, int nrhs,
-                                                 float2* __restrict__ Uc) {
-  extern __shared__ float2 xs[];  // terms * R * RC
-  const int64_t i = blockIdx.x;
-  for (int k0 = 0; k0 < nrhs; k0 += RC) {
-    const int nk = min(RC, nrhs - k0);
-    __syncthreads();
-    for (int t = threadIdx.x; t < terms * R * RC; t += L2L_BS) {
-      int tt = t / (R * RC), rem = t % (R * RC), s = rem / RC, k = rem % RC;
-      int pp = par[i * terms + tt];
-      xs[t] = (pp >= 0 && k < nk) ? U[(int64_t(pp) * R + s) * nrhs + k0 + k] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < Rc; q += L2L_BS) {
-      float2 acc[RC];
-#pragma unroll
-      for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
-      for (int tt = 0; tt < terms; ++tt) {
-        int o = op[i * terms + tt];
-        if (o < 0) continue;
-        const float2* Mo = M + (int64_t(o) * Rc + q) * R;  // row q of Mdn[o] (Rc x R)
-        const float2* xo = xs + tt * R * RC;
-        for (int s = 0; s < R; ++s) {
-          float2 m = Mo[s];
-#pragma unroll
-          for (int k = 0; k < RC; ++k) cfma(acc[k], m, xo[s * RC + k]);
-        }
-      }
-      for (int k = 0; k < nk; ++k) Uc[(i * Rc + q) * nrhs + k0 + k] = acc[k];
-    }
-  }
-}
-
 // ---- leaf evaluation: L2T plus the near-field sum, written in user order ----------
-// One block per leaf, one thread per target point (looping if the leaf holds
-// more points than threads).  L2T runs in float64: g = D_LF^T U_LF[leaf] (the
-// incoming equivalent charges at c + a_p, large and mutually cancelling) and
-// the kernel values G(x, c + a_p).  The near-field sum evaluates G in float32
-// on hi/lo point differences and accumulates in float64.
+// One wave per leaf.  Lane = (target t = lane % 16, slice s = lane / 16): the
+// wave takes the leaf's targets 16 at a time and every lane sums over a quarter
+// of the sources (rows q of the L2T weights W, points of the adjacent leaves
+// for the near field); the four partial sums of a target are combined with
+// lane shuffles.  The near field forms point differences from the hi/lo parts
+// in float64 (green_d) and accumulates in float64.
 constexpr int EV_BS = 64;
-__device__ __forceinline__ void green64(double dx, double dy, double dz, double& re, double& im) {
-  double r = sqrt(dx * dx + dy * dy + dz * dz);
-  double s, c;
-  sincospi(2.0 * r, &s, &c);
-  double ri = 1.0 / r;
-  re = c * ri;
-  im = s * ri;
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, 64);
 }
 
 __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ phi, const float4* __restrict__ plo,
-                                                      const int* __restrict__ lstart, const float4* __restrict__ lcen,
+                                                      const int* __restrict__ lstart,
                                                       const int* __restrict__ nstart, const int* __restrict__ nsrc,
-                                                      const float2* __restrict__ fs, const double4* __restrict__ a_lf,
-                                                      const double2* __restrict__ Dm, const float2* __restrict__ ulf,
-                                                      int R, int Ra, int nrhs, int64_t N, const int* __restrict__ perm,
-                                                      float2* __restrict__ u) {
-  __shared__ float4 sh[EV_BS], sl[EV_BS];
-  __shared__ float2 fv[EV_BS * RC];
-  extern __shared__ double2 g[];  // R * RC
+                                                      const float2* __restrict__ fs, const float2* __restrict__ W,
+                                                      const float2* __restrict__ ulf, int R, int nrhs, int64_t N,
+                                                      const int* __restrict__ perm, float2* __restrict__ u) {
   const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int tl = lane & 15, sl = lane >> 4;
   const int s0 = lstart[b], s1 = lstart[b + 1];
-  const float4 c = lcen[b];
+  const int n0 = nstart[b], n1 = nstart[b + 1];
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int nk = min(RC, nrhs - k0);
-    __syncthreads();
-    for (int p = threadIdx.x; p < R; p += EV_BS) {
-      double gr[RC], gi[RC];
-#pragma unroll
-      for (int k = 0; k < RC; ++k) gr[k] = gi[k] = 0.0;
-      for (int q = 0; q < R; ++q) {
-        double2 d = Dm[q * R + p];  // (D^T)[p][q]
-#pragma unroll
-        for (int k = 0; k < RC; ++k)
-          if (k < nk) {
-            float2 v = ulf[(int64_t(b) * R + q) * nrhs + k0 + k];
-            gr[k] += d.x * double(v.x) - d.y * double(v.y);
-            gi[k] += d.x * double(v.y) + d.y * double(v.x);
-          }
-      }
-      for (int k = 0; k < RC; ++k) g[p * RC + k] = make_double2(gr[k], gi[k]);
-    }
-    __syncthreads();
-    for (int t0 = s0; t0 < s1; t0 += EV_BS) {
-      const int t = t0 + threadIdx.x;
+    for (int t0 = s0; t0 < s1; t0 += 16) {
+      const int t = t0 + tl;
       const bool act = t < s1;
-      float4 th = act ? phi[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 tl = act ? plo[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int tt = act ? t : s0;
+      const float4 th = phi[tt], tq = plo[tt];
       double ar[RC], ai[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) ar[k] = ai[k] = 0.0;
-      // L2T in float64
+      // L2T: sum_q W[t][q] U_LF[leaf][k][q] over this lane's quarter of q
       {
-        double lx = (double(th.x) - double(c.x)) + double(tl.x);
-        double ly = (double(th.y) - double(c.y)) + double(tl.y);
-        double lz = (double(th.z) - double(c.z)) + double(tl.z);
-        for (int p = 0; p < Ra; ++p) {  // padded check points carry g = 0
-          double4 ap = a_lf[p];
-          double re, im;
-          green64(lx - ap.x, ly - ap.y, lz - ap.z, re, im);
+        float2 acc[RC];
 #pragma unroll
-          for (int k = 0; k < RC; ++k) {
-            double2 gg = g[p * RC + k];
-            ar[k] += re * gg.x - im * gg.y;
-            ai[k] += re * gg.y + im * gg.x;
-          }
+        for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
+        for (int q = sl; q < R; q += 4) {
+          const float2 w = W[int64_t(tt) * R + q];
+#pragma unroll
+          for (int k = 0; k < RC; ++k)
+            if (k < nk) cfma(acc[k], w, ulf[(int64_t(b) * nrhs + k0 + k) * R + q]);
+        }
+#pragma unroll
+        for (int k = 0; k < RC; ++k) {
+          ar[k] = acc[k].x;
+          ai[k] = acc[k].y;
         }
       }
-      // near field over adjacent leaves (self included)
-      for (int a = nstart[b]; a < nstart[b + 1]; ++a) {
+      // near field over this lane's quarter of each adjacent leaf's points
+      for (int a = n0; a < n1; ++a) {
         const int A = nsrc[a];
-        const int q0 = lstart[A], q1 = lstart[A + 1];
-        for (int j0 = q0; j0 < q1; j0 += EV_BS) {
-          __syncthreads();
-          int j = j0 + threadIdx.x;
-          if (j < q1) {
-            sh[threadIdx.x] = phi[j];
-            sl[threadIdx.x] = plo[j];
-            for (int k = 0; k < nk; ++k) fv[threadIdx.x * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
-          }
-          __syncthreads();
-          const int nj = min(EV_BS, q1 - j0);
-          for (int jj = 0; jj < nj; ++jj) {
-            float4 h = sh[jj], l = sl[jj];
-            float dx = (th.x - h.x) + (tl.x - l.x);
-            float dy = (th.y - h.y) + (tl.y - l.y);
-            float dz = (th.z - h.z) + (tl.z - l.z);
-            float2 gg = green32(dx, dy, dz);
+        const int q1 = lstart[A + 1];
+        for (int j = lstart[A] + sl; j < q1; j += 4) {
+          const float4 h = phi[j], l = plo[j];
+          const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
+          const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
+          const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
+          const float2 gg = green_d(dx, dy, dz);
 #pragma unroll
-            for (int k = 0; k < RC; ++k) {
-              if (k < nk) {
-                float2 fk = fv[jj * RC + k];
-                ar[k] += double(gg.x * fk.x - gg.y * fk.y);
-                ai[k] += double(gg.x * fk.y + gg.y * fk.x);
-              }
+          for (int k = 0; k < RC; ++k) {
+            if (k < nk) {
+              const float2 fk = fs[int64_t(j) * nrhs + k0 + k];
+              ar[k] += double(gg.x * fk.x - gg.y * fk.y);
+              ai[k] += double(gg.x * fk.y + gg.y * fk.x);
             }
           }
         }
       }
-      if (act) {
-        int64_t o = perm[t];
+#pragma unroll
+      for (int k = 0; k < RC; ++k) {
+        ar[k] += shfl_xor_d(ar[k], 16);
+        ai[k] += shfl_xor_d(ai[k], 16);
+        ar[k] += shfl_xor_d(ar[k], 32);
+        ai[k] += shfl_xor_d(ai[k], 32);
+      }
+      if (act && sl == 0) {
+        const int64_t o = perm[t];
         for (int k = 0; k < nk; ++k) u[int64_t(k0 + k) * N + o] = make_float2(float(ar[k]), float(ai[k]));
       }
     }
@@ -351,42 +372,103 @@ __global__ void k_zero(float2* __restrict__ p, int64_t n) {
   if (i < n) p[i] = make_float2(0.f, 0.f);
 }
 
-struct Chunks {
-  DevBuf grp, col0;
-  int64_t n = 0;
-};
 
 }  // namespace
 
-// Column chunks of the grouped M2L for a given nrhs (host-side bookkeeping).
-static void make_chunks(const std::vector<int32_t>& gstart, int nrhs, std::vector<int32_t>& grp,
-                        std::vector<int32_t>& col0) {
+// Work chunks of a grouped GEMM for a given nrhs: (group, first column) per workgroup.
+static void make_chunks(const GGemm& G, int nrhs, int NC, std::vector<int32_t>& grp, std::vector<int32_t>& col0) {
   grp.clear();
   col0.clear();
-  for (size_t g = 0; g + 1 < gstart.size(); ++g) {
-    int64_t ncol = int64_t(gstart[g + 1] - gstart[g]) * nrhs;
-    for (int64_t c = 0; c < ncol; c += M2L_COLS) {
+  for (int64_t g = 0; g < G.ngroups; ++g) {
+    int64_t ncol = int64_t(G.v0_h[g + 1] - G.v0_h[g]) * nrhs;
+    for (int64_t c = 0; c < ncol; c += NC) {
       grp.push_back(int32_t(g));
       col0.push_back(int32_t(c));
     }
   }
 }
 
+struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
+  const GGemm* G = nullptr;
+  int nt = 4;          // 16-column tiles per workgroup
+  int slices = 1;      // M-slices (grid y)
+  int64_t nchunks = 0;
+  DevBuf grp, col0;
+};
+
 struct ApplyState {
   int nrhs = 0;
   std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
   DevBuf fs, flf, ulf, Y;
-  DevBuf lf_cg, lf_cc;
-  int64_t lf_nch = 0;
-  std::vector<std::unique_ptr<DevBuf>> cg, cc;
-  std::vector<int64_t> nch;
-  std::vector<hipEvent_t> ev;
-  ~ApplyState() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-  }
+  std::vector<Launch> m2m, l2l, m2l;          // per HF level
+  Launch lf_m2l;
 };
 
 void destroy_apply_state(ApplyState* s) { delete s; }
+
+static void prepare(Launch& L, const GGemm& G, int nrhs) {
+  L.G = &G;
+  // narrow tiles when the average group holds few columns
+  double avg = G.ngroups ? double(G.nvec) * nrhs / double(G.ngroups) : 0.0;
+  L.nt = avg < 40.0 ? 2 : 4;
+  std::vector<int32_t> grp, col0;
+  make_chunks(G, nrhs, L.nt * 16, grp, col0);
+  L.nchunks = int64_t(grp.size());
+  // few chunks: split the M-tiles over more workgroups (at least ~4 per CU)
+  int nM = G.M / 8;
+  int max_slices = std::max(1, (nM + 3) / 4);
+  L.slices = 1;
+  while (L.slices < max_slices && L.nchunks * L.slices < 1024) ++L.slices;
+  L.grp.upload(grp);
+  L.col0.upload(col0);
+}
+
+template <int MT>
+static void launch_mt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  const GGemm& G = *L.G;
+  size_t lds = sizeof(float) * size_t(gg_stride(G.K)) * size_t(L.nt * 16);
+  if (L.nt == 4) {
+    static bool attr = false;
+    if (!attr) {
+      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, 4>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_ggemm<MT, 4>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st, G.A.as<float4>(), G.M,
+                       G.K, G.T, G.ops.as<int>(), G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(),
+                       L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
+  } else {
+    static bool attr = false;
+    if (!attr) {
+      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, 2>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_ggemm<MT, 2>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st, G.A.as<float4>(), G.M,
+                       G.K, G.T, G.ops.as<int>(), G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(),
+                       L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
+  }
+}
+
+static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  if (L.nchunks == 0) return;
+  const GGemm& G = *L.G;
+  int nM = G.M / 8;
+  int per = 4 * L.slices;
+  int mt = (nM + per - 1) / per;
+  if (size_t(gg_stride(G.K)) * size_t(L.nt * 16) * sizeof(float) > 160 * 1024 || mt > 8)
+    throw Error{DFMM_EUNSUPPORTED, "skeleton rank too large for the GEMM kernel"};
+  switch (mt) {
+    case 1: launch_mt<1>(L, nrhs, X, Y, st); break;
+    case 2: launch_mt<2>(L, nrhs, X, Y, st); break;
+    case 3: launch_mt<3>(L, nrhs, X, Y, st); break;
+    case 4: launch_mt<4>(L, nrhs, X, Y, st); break;
+    case 5: launch_mt<5>(L, nrhs, X, Y, st); break;
+    case 6: launch_mt<6>(L, nrhs, X, Y, st); break;
+    case 7: launch_mt<7>(L, nrhs, X, Y, st); break;
+    default: launch_mt<8>(L, nrhs, X, Y, st); break;
+  }
+}
 
 static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   if (S.nrhs == nrhs) return;
@@ -398,9 +480,6 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   int64_t ymax = P.lf.npairs * P.lf.R;
   S.F.clear();
   S.U.clear();
-  S.cg.clear();
-  S.cc.clear();
-  S.nch.clear();
   for (auto& H : P.hf) {
     S.F.emplace_back(new DevBuf());
     S.U.emplace_back(new DevBuf());
@@ -409,19 +488,18 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
     ymax = std::max<int64_t>(ymax, H.npairs * H.R);
   }
   S.Y.alloc(sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs);
-  std::vector<int32_t> grp, col0;
+  S.m2m.clear();
+  S.l2l.clear();
+  S.m2l.clear();
+  S.m2m.resize(P.hf.size());
+  S.l2l.resize(P.hf.size());
+  S.m2l.resize(P.hf.size());
   for (size_t e = 0; e < P.hf.size(); ++e) {
-    make_chunks(P.hf[e].gs_h, nrhs, grp, col0);
-    S.cg.emplace_back(new DevBuf());
-    S.cc.emplace_back(new DevBuf());
-    S.cg.back()->upload(grp);
-    S.cc.back()->upload(col0);
-    S.nch.push_back(int64_t(grp.size()));
+    prepare(S.m2m[e], P.hf[e].m2m, nrhs);
+    prepare(S.l2l[e], P.hf[e].l2l, nrhs);
+    prepare(S.m2l[e], P.hf[e].m2l, nrhs);
   }
-  make_chunks(P.lf.gs_h, nrhs, grp, col0);
-  S.lf_cg.upload(grp);
-  S.lf_cc.upload(col0);
-  S.lf_nch = int64_t(grp.size());
+  prepare(S.lf_m2l, P.lf.m2l, nrhs);
 }
 
 void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t st) {
@@ -434,85 +512,123 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   const int64_t nleaf = P.lf.nleaf;
   const int Rl = P.lf.R;
   const int e_top = int(P.hf.size()) - 1;
-  bool timing = P.timing;
-  if (timing && S.ev.empty()) {
-    S.ev.resize(10);
-    for (auto& e : S.ev) DFMM_HIP(hipEventCreate(&e));
-  }
-  auto mark = [&](int i) {
-    if (timing) DFMM_HIP(hipEventRecord(S.ev[i], st));
+  StageTimer* tm = P.timer;
+  if (tm && !tm->begin_apply(st)) tm = nullptr;
+  auto mark = [&](int stage) {
+    if (tm) tm->mark(stage, st);
   };
-  mark(0);
   hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, f, S.fs.as<float2>(),
                      P.perm_d.as<int>(), N, nrhs);
-  mark(1);
-  hipLaunchKernelGGL(k_s2m, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.pthi.as<float4>(), P.ptlo.as<float4>(),
-                     P.leaf_start.as<int>(), P.leaf_center.as<float4>(), S.fs.as<float2>(), P.lf.a.as<float4>(), Rl,
-                     P.lf.r, nrhs, S.flf.as<float2>());
-  mark(2);
+  mark(ST_PERMUTE);
+  hipLaunchKernelGGL(k_s2m, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
+                     P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+  mark(ST_S2M);
   // HF-M2M, fine to coarse
   for (int e = 0; e <= e_top; ++e) {
-    HFLevel& H = P.hf[e];
-    if (H.nout == 0) continue;
     const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
-    hipLaunchKernelGGL(k_m2m, dim3(unsigned(H.nout)), dim3(M2M_BS), sizeof(float2) * 8 * H.Rc * RC, st,
-                       H.m2m_child.as<int>(), H.m2m_op.as<int>(), H.Mup.as<float2>(), Fc, H.R, H.Rc, nrhs,
-                       S.F[e]->as<float2>());
+    launch_gemm(S.m2m[e], nrhs, Fc, S.F[e]->as<float2>(), st);
+    mark(ST_M2M);
   }
-  mark(3);
-  // HF-M2L then HF-L2L, coarse to fine
+  // HF-M2L (+ reduction) then HF-L2L, coarse to fine
   if (e_top >= 0) {
     HFLevel& H = P.hf[e_top];
     int64_t n = std::max<int64_t>(1, H.nin) * H.R * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.U[e_top]->as<float2>(), n);
+    mark(ST_ZERO);
   }
   for (int e = e_top; e >= 0; --e) {
     HFLevel& H = P.hf[e];
-    if (S.nch[e] > 0) {
-      hipLaunchKernelGGL(k_m2l, dim3(unsigned(S.nch[e])), dim3(M2L_BS), sizeof(float2) * H.R * M2L_COLS, st,
-                         H.grp_start.as<int>(), H.pair_src.as<int>(), H.T.as<float2>(), S.F[e]->as<float2>(), H.R,
-                         nrhs, S.cg[e]->as<int>(), S.cc[e]->as<int>(), S.Y.as<float2>());
+    if (S.m2l[e].nchunks > 0) {
+      launch_gemm(S.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
+      mark(ST_M2L);
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
                          H.red_idx.as<int>(), S.Y.as<float2>(), H.nin, RN, S.U[e]->as<float2>());
+      mark(ST_REDUCE);
     }
     float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
-    int64_t nchild = H.nchild_in;
-    if (nchild > 0)
-      hipLaunchKernelGGL(k_l2l, dim3(unsigned(nchild)), dim3(L2L_BS), sizeof(float2) * H.l2l_terms * H.R * RC, st,
-                         H.l2l_par.as<int>(), H.l2l_op.as<int>(), H.l2l_terms, H.Mdn.as<float2>(),
-                         S.U[e]->as<float2>(), H.R, H.Rc, nrhs, Uc);
+    launch_gemm(S.l2l[e], nrhs, S.U[e]->as<float2>(), Uc, st);
+    mark(ST_L2L);
   }
   if (e_top < 0) {
     int64_t n = nleaf * Rl * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.ulf.as<float2>(), n);
+    mark(ST_ZERO);
   }
-  mark(4);
   // LF-M2L
-  if (S.lf_nch > 0) {
-    hipLaunchKernelGGL(k_m2l, dim3(unsigned(S.lf_nch)), dim3(M2L_BS), sizeof(float2) * Rl * M2L_COLS, st,
-                       P.lf.grp_start.as<int>(), P.lf.pair_src.as<int>(), P.lf.T.as<float2>(), S.flf.as<float2>(),
-                       Rl, nrhs, S.lf_cg.as<int>(), S.lf_cc.as<int>(), S.Y.as<float2>());
+  if (S.lf_m2l.nchunks > 0) {
+    launch_gemm(S.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
+    mark(ST_LF_M2L);
     int RN = Rl * nrhs;
     hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
                        P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, S.ulf.as<float2>());
+    mark(ST_LF_REDUCE);
   }
-  mark(5);
-  hipLaunchKernelGGL(k_leaf_eval, dim3(unsigned(nleaf)), dim3(EV_BS), sizeof(double2) * Rl * RC, st,
-                     P.pthi.as<float4>(), P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(),
-                     P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(), P.lf.a64.as<double4>(),
-                     P.lf.D64.as<double2>(), S.ulf.as<float2>(), Rl, P.lf.r, nrhs, N, P.perm_d.as<int>(), u);
-  mark(6);
+  hipLaunchKernelGGL(k_leaf_eval, dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(), P.ptlo.as<float4>(),
+                     P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(),
+                     P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u);
+  mark(ST_LEAF);
   DFMM_HIP(hipGetLastError());
-  if (timing) {
-    DFMM_HIP(hipEventSynchronize(S.ev[6]));
-    P.stage_ms.assign(6, 0.0);
-    for (int i = 0; i < 6; ++i) {
-      float ms = 0.f;
-      DFMM_HIP(hipEventElapsedTime(&ms, S.ev[i], S.ev[i + 1]));
-      P.stage_ms[i] = ms;
-    }
+}
+
+// ---- plan-time leaf weights ---------------------------------------------------------
+void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT) {
+  DevBuf dp, dt;
+  dp.upload(sorted_pts);
+  dt.upload(DT);
+  const int R = P.lf.R;
+  P.lf.V.alloc(sizeof(float2) * size_t(P.N) * R);
+  P.lf.W.alloc(sizeof(float2) * size_t(P.N) * R);
+  hipLaunchKernelGGL(k_leaf_weights, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
+                     dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
+                     dt.as<double2>(), R, P.lf.r, P.lf.V.as<float2>(), P.lf.W.as<float2>());
+  DFMM_HIP(hipGetLastError());
+  DFMM_HIP(hipDeviceSynchronize());
+}
+
+// ---- stage timer -------------------------------------------------------------------
+bool StageTimer::begin_apply(hipStream_t st) {
+  if (used + kPerApply > pool.size()) return false;
+  apply_begin.push_back(used);
+  DFMM_HIP(hipEventRecord(pool[used], st));
+  tags.push_back(-1);
+  ++used;
+  return true;
+}
+
+void StageTimer::mark(int stage, hipStream_t st) {
+  if (used >= pool.size()) return;
+  DFMM_HIP(hipEventRecord(pool[used], st));
+  tags.push_back(stage);
+  ++used;
+}
+
+void StageTimer::collect(double* ms, int64_t* launches) {
+  for (int i = 0; i < ST_COUNT; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
   }
+  if (used == 0) return;
+  DFMM_HIP(hipEventSynchronize(pool[used - 1]));
+  for (size_t i = 1; i < used; ++i) {
+    if (tags[i] < 0) continue;  // first event of an apply
+    float t = 0.f;
+    DFMM_HIP(hipEventElapsedTime(&t, pool[i - 1], pool[i]));
+    ms[tags[i]] += t;
+    launches[tags[i]] += 1;
+  }
+  used = 0;
+  tags.clear();
+  apply_begin.clear();
+}
+
+StageTimer::StageTimer(int applies) {
+  pool.resize(size_t(applies) * kPerApply);
+  for (auto& e : pool) DFMM_HIP(hipEventCreate(&e));
+}
+
+StageTimer::~StageTimer() {
+  for (auto e : pool) (void)hipEventDestroy(e);
 }
 
 }  // namespace dfmm

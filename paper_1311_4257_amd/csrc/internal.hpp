@@ -93,32 +93,41 @@ struct DevBuf {
   }
 };
 
+// ---- grouped gather GEMM (the MFMA engine of M2M, M2L and L2L) ---------------
+// Vectors are complex64, one per (slot, rhs), stored [slot][rhs][row].  A
+// launch computes, for every vector column v of every group g,
+//   Y[vdst[v]] = sum_{t < T} A[ops[g T + t]] X[vsrc[v T + t]]
+// (a term with source -1 contributes nothing).  Each operator is an M x K
+// complex matrix (M, K multiples of 8) stored in MFMA fragment order, see
+// pack_operator().
+struct GGemm {
+  int M = 0, K = 0, T = 1;
+  int64_t ngroups = 0, nvec = 0, nops = 0;
+  DevBuf A;                  // float4[nops][M K / 2]
+  DevBuf ops;                // int32[ngroups][T]
+  DevBuf v0;                 // int32[ngroups + 1]: vector range of each group
+  DevBuf vsrc;               // int32[nvec][T]
+  DevBuf vdst;               // int32[nvec]
+  std::vector<int32_t> v0_h; // host copy of v0 (work chunking)
+};
+
+// Pack an M x K complex matrix (row-major, interleaved float64) into the
+// fragment order read by the GEMM kernel.
+void pack_operator(const double* Tc, int M, int K, float* out);
+
 // ---- one HF level of the plan -------------------------------------------------
 struct HFLevel {
   int l = 0;      // tree level
   int e = 0;      // log2 of the width
   int R = 0;      // padded skeleton size (multiple of 8)
   int Rc = 0;     // padded skeleton size of the child level (LF at e = 0)
-  int64_t nout = 0, nin = 0, npairs = 0, ngroups = 0;
+  int64_t nout = 0, nin = 0, npairs = 0, ngroups = 0, nchild_in = 0;
   double flops = 0.0;  // 8 r_in r_out over pairs (unpadded ranks)
-  // M2M: out-slot -> its 8 child out-slots (or LF leaves at e = 0), -1 if absent
-  DevBuf m2m_child;    // int32[nout][8]
-  DevBuf m2m_op;       // int32[nout]: base operator index (dir * 8) of the slot
-  DevBuf Mup;          // float2[ndir * 8][R][Rc]: G(a^{w,l} - delta_o, b^c) D^c
-  DevBuf Mdn;          // float2[ndir * 8][Rc][R]: G(b^c + delta_o, a^{w,l}) (D^{w,l})^T
-  // L2L: child in-slot (next level, or LF leaf at e = 0) <- parent in-slots
-  int l2l_terms = 0;   // 4 (HF child) or 6 (LF child)
-  int64_t nchild_in = 0;
-  DevBuf l2l_par;      // int32[nchild_in][terms]: parent in-slot or -1
-  DevBuf l2l_op;       // int32[nchild_in][terms]: operator index (dir * 8 + octant) or -1
-  // M2L grouped by offset
-  DevBuf T;            // float2[ngroups][R][R]
-  DevBuf grp_start;    // int32[ngroups + 1] into the grouped pair order
-  DevBuf pair_src;     // int32[npairs]: out-slot of the source (grouped order)
-  DevBuf red_start;    // int32[nin + 1]: CSR of grouped pair positions per in-slot
+  GGemm m2m;           // out-slots <- child out-slots (8 octant terms)
+  GGemm l2l;           // child in-slots <- parent in-slots (4 wedge terms, 6 at the LF hand-off)
+  GGemm m2l;           // pair outputs <- source out-slots, grouped by offset
+  DevBuf red_start;    // int32[nin + 1]: CSR of pair outputs per in-slot
   DevBuf red_idx;      // int32[npairs]
-  int max_group = 0;
-  std::vector<int32_t> gs_h;  // host copy of grp_start
 };
 
 struct LFLevel {
@@ -127,11 +136,11 @@ struct LFLevel {
   int64_t nleaf = 0, npairs = 0, ngroups = 0;
   double flops = 0.0;
   DevBuf a;            // float4[R]  check points a_LF (box frame)
-  DevBuf a64;          // double4[R] the same in float64 (for L2T)
-  DevBuf D64;          // double2[R][R] D_LF, row-major, float64 (for L2T)
-  DevBuf T, grp_start, pair_src, red_start, red_idx;
-  int max_group = 0;
-  std::vector<int32_t> gs_h;
+  DevBuf a64;          // double4[R] the same in float64
+  DevBuf V;            // float2[N][R]: S2M weights G(c + a_p, x_j) per sorted point
+  DevBuf W;            // float2[N][R]: L2T weights sum_p G(x_j, c + a_p) D_LF[q][p]
+  GGemm m2l;
+  DevBuf red_start, red_idx;
 };
 
 // Octree with one table per level, boxes in Morton order (host copy).
@@ -153,7 +162,27 @@ struct Tree {
 
 struct ApplyState;
 void destroy_apply_state(ApplyState* s);
+
+// Stages reported by dfmm_stage_times (same order as in include/dfmm.h).
+enum { ST_PERMUTE = 0, ST_S2M, ST_M2M, ST_M2L, ST_REDUCE, ST_L2L, ST_LF_M2L, ST_LF_REDUCE, ST_LEAF,
+       ST_ZERO, ST_COUNT };
+
+// HIP events recorded on the apply stream after every launch, for a bounded
+// number of applies; no host synchronisation until collect().
+struct StageTimer {
+  static constexpr size_t kPerApply = 64;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> tags;            // stage of the interval that ends at each event (-1: apply start)
+  std::vector<size_t> apply_begin;
+  size_t used = 0;
+  explicit StageTimer(int applies);
+  ~StageTimer();
+  bool begin_apply(hipStream_t st);
+  void mark(int stage, hipStream_t st);
+  void collect(double* ms, int64_t* launches);  // sums per stage, then resets
+};
 void run_apply(dfmm_plan_s& P, const void* f, void* u, int nrhs, hipStream_t st);
+void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT);
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                 const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);
 
@@ -184,7 +213,6 @@ struct dfmm_plan_s {
   std::vector<dfmm::HFLevel> hf;  // index e (log2 w), 0 .. e_top
   // apply workspace (owned; see apply.hip)
   struct dfmm::ApplyState* ws = nullptr;
-  // timing
-  bool timing = false;
-  std::vector<double> stage_ms;
+  // stage timing (null when disabled)
+  dfmm::StageTimer* timer = nullptr;
 };

@@ -64,6 +64,25 @@ int64_t Tree::find(int l, int64_t x, int64_t y, int64_t z) const {
   return int64_t(it - K.begin());
 }
 
+// Fragment order of an M x K complex operator for the MFMA kernel: for M-tile
+// m (8 complex rows), step s4 (K / 8 of them), row-in-tile ql (8) and K quarter
+// kr (4), one float4 holds the two complex entries (q, p0) and (q, p0 + 1) with
+// q = 8 m + ql and p0 = kr K / 4 + 2 s4.
+void pack_operator(const double* Tc, int M, int K, float* out) {
+  int nm = M / 8, ns = K / 8;
+  for (int m = 0; m < nm; ++m)
+    for (int s4 = 0; s4 < ns; ++s4)
+      for (int ql = 0; ql < 8; ++ql)
+        for (int kr = 0; kr < 4; ++kr) {
+          int q = 8 * m + ql, p0 = kr * (K / 4) + 2 * s4;
+          float* o = out + 4 * ((((size_t(m) * ns + s4) * 8 + ql) * 4) + kr);
+          o[0] = float(Tc[2 * (size_t(q) * K + p0)]);
+          o[1] = float(Tc[2 * (size_t(q) * K + p0) + 1]);
+          o[2] = float(Tc[2 * (size_t(q) * K + p0 + 1)]);
+          o[3] = float(Tc[2 * (size_t(q) * K + p0 + 1) + 1]);
+        }
+}
+
 namespace {
 
 struct PairRec {
@@ -117,13 +136,6 @@ struct SlotIndex {
     return it == idx.end() ? -1 : it->second;
   }
 };
-
-std::vector<float> skel_points4(const Skel& s, int R) {
-  std::vector<float> v(size_t(4) * R, 0.0f);
-  for (int i = 0; i < s.r; ++i)
-    for (int k = 0; k < 3; ++k) v[4 * i + k] = float(s.b[3 * i + k]);
-  return v;
-}
 
 }  // namespace
 
@@ -244,56 +256,51 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   info.rank[D] = Rlf;
   {
     std::vector<float> a4(size_t(4) * Rlf, 0.0f);
-    std::vector<double> a64(size_t(4) * Rlf, 0.0), D64(size_t(2) * Rlf * Rlf, 0.0);
+    std::vector<double> a64(size_t(4) * Rlf, 0.0), DT(size_t(2) * Rlf * Rlf, 0.0);
     for (int i = 0; i < sl.r; ++i)
       for (int k = 0; k < 3; ++k) {
         a4[4 * i + k] = float(sl.a[3 * i + k]);
         a64[4 * i + k] = sl.a[3 * i + k];
       }
     for (int q = 0; q < sl.r; ++q)
-      for (int p = 0; p < sl.r; ++p) {
-        D64[2 * (size_t(q) * Rlf + p)] = sl.D[2 * (size_t(q) * sl.r + p)];
-        D64[2 * (size_t(q) * Rlf + p) + 1] = sl.D[2 * (size_t(q) * sl.r + p) + 1];
+      for (int p = 0; p < sl.r; ++p) {  // DT[p][q] = D[q][p]
+        DT[2 * (size_t(p) * Rlf + q)] = sl.D[2 * (size_t(q) * sl.r + p)];
+        DT[2 * (size_t(p) * Rlf + q) + 1] = sl.D[2 * (size_t(q) * sl.r + p) + 1];
       }
     P.lf.a.upload(a4);
     P.lf.a64.upload(a64);
-    P.lf.D64.upload(D64);
+    build_leaf_weights(P, T.pts, DT);
   }
 
-  // grouped M2L tables for one level: pairs -> groups by offset, T tables, CSR
+  // M2L of one level: pairs grouped by offset n; one operator per group,
+  // G(b^{l_in}, n w + b^{l_out}) D^{l_out} (maps outgoing check potentials of A to
+  // incoming check potentials of B); the pair outputs are summed per in-slot.
   auto build_m2l = [&](const std::vector<PairRec>& pr, double w, int R,
-                       const std::vector<const Skel*>& skin, const std::vector<const Skel*>& skout,
-                       const SlotIndex* osl, const SlotIndex* isl, int64_t nin, DevBuf& Tb,
-                       DevBuf& gs, DevBuf& ps, DevBuf& rs, DevBuf& ri, int64_t& ngroups,
-                       int& max_group, double& flops, std::vector<int32_t>& gs_host) {
+                       const std::vector<const Skel*>& skin, const SlotIndex* osl, const SlotIndex* isl,
+                       int64_t nin, GGemm& G, DevBuf& rs, DevBuf& ri, int64_t& ngroups, double& flops) {
     std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<int64_t>> g;
     for (size_t i = 0; i < pr.size(); ++i) g[{pr[i].nx, pr[i].ny, pr[i].nz}].push_back(int64_t(i));
     ngroups = int64_t(g.size());
-    std::vector<int32_t> gstart(1, 0), psrc, pos_of(pr.size());
+    std::vector<int32_t> v0(1, 0), vsrc, opsv, pos_of(pr.size());
     std::vector<std::tuple<int64_t, int64_t, int64_t>> keys;
     std::vector<int64_t> rep;
-    max_group = 0;
     flops = 0.0;
     for (auto& kv : g) {
       keys.push_back(kv.first);
       rep.push_back(kv.second.front());
+      opsv.push_back(int32_t(keys.size() - 1));
       for (int64_t i : kv.second) {
         const PairRec& r = pr[i];
-        pos_of[i] = int32_t(psrc.size());
-        psrc.push_back(int32_t(osl ? osl->at(r.A, r.dout) : r.A));
-        const Skel* si = skin[r.din < 0 ? 0 : r.din];
-        const Skel* so = skout[r.dout < 0 ? 0 : r.dout];
-        flops += 8.0 * si->r * so->r;
+        pos_of[i] = int32_t(vsrc.size());
+        vsrc.push_back(int32_t(osl ? osl->at(r.A, r.dout) : r.A));
+        flops += 8.0 * skin[r.din < 0 ? 0 : r.din]->r * skin[r.dout < 0 ? 0 : r.dout]->r;
       }
-      max_group = std::max<int>(max_group, int(kv.second.size()));
-      gstart.push_back(int32_t(psrc.size()));
+      v0.push_back(int32_t(vsrc.size()));
     }
-    // reduction CSR per in-slot (or leaf)
     std::vector<std::vector<int32_t>> per(nin);
     for (size_t i = 0; i < pr.size(); ++i) {
       const PairRec& r = pr[i];
-      int64_t s = isl ? isl->at(r.B, r.din) : r.B;
-      per[s].push_back(pos_of[i]);
+      per[isl ? isl->at(r.B, r.din) : r.B].push_back(pos_of[i]);
     }
     std::vector<int32_t> rstart(1, 0), ridx;
     for (auto& v : per) {
@@ -301,16 +308,16 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       ridx.insert(ridx.end(), v.begin(), v.end());
       rstart.push_back(int32_t(ridx.size()));
     }
-    // translation of outgoing check potentials: G(b^{l_in}, n w + b^{l_out}) D^{l_out}
-    std::vector<float> Tt(size_t(2) * R * R * ngroups, 0.0f);
+    std::vector<int32_t> vdst(vsrc.size());
+    for (size_t i = 0; i < vdst.size(); ++i) vdst[i] = int32_t(i);
+    std::vector<float> At(size_t(2) * R * R * ngroups, 0.0f);
     parallel_for(ngroups, [&](int64_t gi) {
       const PairRec& r = pr[rep[gi]];
       const Skel* si = skin[r.din < 0 ? 0 : r.din];
-      const Skel* so = skout[r.dout < 0 ? 0 : r.dout];
+      const Skel* so = skin[r.dout < 0 ? 0 : r.dout];
       double sx = double(std::get<0>(keys[gi])) * w, sy = double(std::get<1>(keys[gi])) * w,
              sz = double(std::get<2>(keys[gi])) * w;
-      std::vector<double> G(size_t(2) * so->r);
-      float* t = &Tt[size_t(2) * R * R * gi];
+      std::vector<double> G(size_t(2) * so->r), T(size_t(2) * R * R, 0.0);
       for (int q = 0; q < si->r; ++q) {
         for (int p = 0; p < so->r; ++p)
           green64(si->b[3 * q] - (sx + so->b[3 * p]), si->b[3 * q + 1] - (sy + so->b[3 * p + 1]),
@@ -323,15 +330,24 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi2 * di;
             im += gr * di + gi2 * dr;
           }
-          t[2 * (q * R + j)] = float(re);
-          t[2 * (q * R + j) + 1] = float(im);
+          T[2 * (size_t(q) * R + j)] = re;
+          T[2 * (size_t(q) * R + j) + 1] = im;
         }
       }
+      pack_operator(T.data(), R, R, &At[size_t(2) * R * R * gi]);
     });
-    Tb.upload(Tt);
-    gs.upload(gstart);
-    gs_host = gstart;
-    ps.upload(psrc);
+    G.M = R;
+    G.K = R;
+    G.T = 1;
+    G.ngroups = ngroups;
+    G.nvec = int64_t(vsrc.size());
+    G.nops = ngroups;
+    G.A.upload(At);
+    G.ops.upload(opsv);
+    G.v0.upload(v0);
+    G.v0_h = v0;
+    G.vsrc.upload(vsrc);
+    G.vdst.upload(vdst);
     rs.upload(rstart);
     ri.upload(ridx);
   };
@@ -339,9 +355,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   {
     std::vector<const Skel*> s1{&sl};
     P.lf.npairs = int64_t(pairs[D].size());
-    build_m2l(pairs[D], 0.5, Rlf, s1, s1, nullptr, nullptr, nleaf, P.lf.T, P.lf.grp_start,
-              P.lf.pair_src, P.lf.red_start, P.lf.red_idx, P.lf.ngroups, P.lf.max_group, P.lf.flops,
-              P.lf.gs_h);
+    build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nleaf, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
+              P.lf.ngroups, P.lf.flops);
     info.flops_m2l_lf = P.lf.flops;
   }
 
@@ -362,7 +377,6 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<const Skel*> child_sk;
     if (e == 0) {
       H.Rc = Rlf;
-      child_sk.assign(1, &sl);
     } else {
       int rc = 0;
       for (auto& s : ops.hf[e - 1]) rc = std::max(rc, s.r);
@@ -372,6 +386,9 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     H.nout = int64_t(OS[l].list.size());
     H.nin = int64_t(IS[l].list.size());
     H.npairs = int64_t(pairs[l].size());
+    const auto& L = T.lv[l];
+    const auto& C = T.lv[l + 1];
+
     // Per (dir, octant): upward G(a^{w,l} - delta_o, b^c) D^c (R x Rc) maps the
     // child's outgoing check potentials to the parent's; downward
     // G(b^c + delta_o, a^{w,l}) (D^{w,l})^T (Rc x R) maps the parent's incoming
@@ -388,14 +405,13 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       const Skel& s = sk[d];
       const Skel& c = e == 0 ? sl : *child_sk[direction_down(d, w)];
       double dx = ((o & 1) - 0.5) * wc, dy = (((o >> 1) & 1) - 0.5) * wc, dz = (((o >> 2) & 1) - 0.5) * wc;
-      // G[p][j] = G(a_p - delta, b_j)  (s.r x c.r)
       std::vector<double> G(size_t(2) * s.r * c.r);
       for (int p = 0; p < s.r; ++p)
         for (int j = 0; j < c.r; ++j)
           green64(s.a[3 * p] - dx - c.b[3 * j], s.a[3 * p + 1] - dy - c.b[3 * j + 1],
                   s.a[3 * p + 2] - dz - c.b[3 * j + 2], &G[2 * (size_t(p) * c.r + j)],
                   &G[2 * (size_t(p) * c.r + j) + 1]);
-      float* up = &Mu[size_t(2) * id * H.R * H.Rc];
+      std::vector<double> up(size_t(2) * H.R * H.Rc, 0.0), dn(size_t(2) * H.Rc * H.R, 0.0);
       for (int p = 0; p < s.r; ++p)
         for (int k = 0; k < c.r; ++k) {  // (G D^c)[p][k]
           double re = 0.0, im = 0.0;
@@ -405,10 +421,9 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          up[2 * (size_t(p) * H.Rc + k)] = float(re);
-          up[2 * (size_t(p) * H.Rc + k) + 1] = float(im);
+          up[2 * (size_t(p) * H.Rc + k)] = re;
+          up[2 * (size_t(p) * H.Rc + k) + 1] = im;
         }
-      float* dn = &Md[size_t(2) * id * H.R * H.Rc];
       for (int j = 0; j < c.r; ++j)
         for (int q = 0; q < s.r; ++q) {  // (G^T D^T)[j][q] = sum_p G[p][j] D[q][p]
           double re = 0.0, im = 0.0;
@@ -418,78 +433,113 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          dn[2 * (size_t(j) * H.R + q)] = float(re);
-          dn[2 * (size_t(j) * H.R + q) + 1] = float(im);
+          dn[2 * (size_t(j) * H.R + q)] = re;
+          dn[2 * (size_t(j) * H.R + q) + 1] = im;
         }
+      pack_operator(up.data(), H.R, H.Rc, &Mu[size_t(2) * id * H.R * H.Rc]);
+      pack_operator(dn.data(), H.Rc, H.R, &Md[size_t(2) * id * H.R * H.Rc]);
     });
-    H.Mup.upload(Mu);
-    H.Mdn.upload(Md);
-    // M2M children per out-slot
+
+    // M2M: one group per wedge l; vectors = out-slots of that wedge; 8 octant terms
     {
-      std::vector<int32_t> ch(size_t(8) * H.nout, -1), op(H.nout);
-      const auto& L = T.lv[l];
-      const auto& C = T.lv[l + 1];
-      for (int64_t i = 0; i < H.nout; ++i) {
-        auto [b, d] = OS[l].list[i];
-        op[i] = d * 8;
-        for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c) {
-          int o = int(C.octant[c]);
-          ch[8 * i + o] = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
+      GGemm& G = H.m2m;
+      std::vector<std::vector<int32_t>> by_dir(ndir);
+      for (int64_t i = 0; i < H.nout; ++i) by_dir[OS[l].list[i].second].push_back(int32_t(i));
+      std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv;
+      for (int d = 0; d < ndir; ++d) {
+        if (by_dir[d].empty()) continue;
+        for (int o = 0; o < 8; ++o) opsv.push_back(d * 8 + o);
+        for (int32_t i : by_dir[d]) {
+          int64_t b = OS[l].list[i].first;
+          int32_t src[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+          for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c)
+            src[C.octant[c]] = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
+          vsrc.insert(vsrc.end(), src, src + 8);
+          vdst.push_back(i);
         }
+        v0.push_back(int32_t(vdst.size()));
       }
-      H.m2m_child.upload(ch);
-      H.m2m_op.upload(op);
+      G.M = H.R;
+      G.K = H.Rc;
+      G.T = 8;
+      G.ngroups = int64_t(v0.size()) - 1;
+      G.nvec = int64_t(vdst.size());
+      G.nops = int64_t(ndir) * 8;
+      G.A.upload(Mu);
+      G.ops.upload(opsv);
+      G.v0.upload(v0);
+      G.v0_h = v0;
+      G.vsrc.upload(vsrc);
+      G.vdst.upload(vdst);
     }
-    // L2L: child in-slots <- parent in-slots
+    // L2L: child in-slots grouped by (child wedge, octant); terms = the parent
+    // wedges that map down to the child wedge (4), or all 6 at the LF hand-off.
     {
-      const auto& C = T.lv[l + 1];
+      GGemm& G = H.l2l;
+      std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv;
       if (e == 0) {
-        H.l2l_terms = 6;
         H.nchild_in = nleaf;
-        std::vector<int32_t> par(size_t(6) * nleaf, -1), op(size_t(6) * nleaf, -1);
-        for (int64_t c = 0; c < nleaf; ++c) {
-          int64_t p = C.parent[c];
-          for (int d = 0; d < 6; ++d) {
-            int64_t s = IS[l].at(p, d);
-            if (s >= 0) {
-              par[6 * c + d] = int32_t(s);
-              op[6 * c + d] = d * 8 + int(C.octant[c]);
-            }
+        for (int o = 0; o < 8; ++o) {
+          std::vector<int32_t> kids;
+          for (int64_t c = 0; c < nleaf; ++c)
+            if (C.octant[c] == o) kids.push_back(int32_t(c));
+          if (kids.empty()) continue;
+          for (int d = 0; d < 6; ++d) opsv.push_back(d * 8 + o);
+          for (int32_t c : kids) {
+            int64_t p = C.parent[c];
+            for (int d = 0; d < 6; ++d) vsrc.push_back(int32_t(IS[l].at(p, d)));
+            vdst.push_back(c);
           }
+          v0.push_back(int32_t(vdst.size()));
         }
-        H.l2l_par.upload(par);
-        H.l2l_op.upload(op);
+        G.T = 6;
       } else {
-        H.l2l_terms = 4;
-        H.nchild_in = int64_t(IS[l + 1].list.size());
-        std::vector<int32_t> par(size_t(4) * H.nchild_in, -1), op(size_t(4) * H.nchild_in, -1);
-        int64_t w2 = w;  // parent width; child width w/2 has (w/2) cells per face edge
         int64_t wc_i = w / 2;
+        int nd_c = int(6 * wc_i * wc_i);
+        H.nchild_in = int64_t(IS[l + 1].list.size());
+        std::vector<std::vector<int32_t>> by(size_t(nd_c) * 8);
         for (int64_t i = 0; i < H.nchild_in; ++i) {
           auto [c, dc] = IS[l + 1].list[i];
-          int64_t p = C.parent[c];
-          int64_t face = dc / (wc_i * wc_i), rem = dc % (wc_i * wc_i);
-          int64_t ci = rem / wc_i, cj = rem % wc_i;
-          int t = 0;
-          for (int di = 0; di < 2; ++di)
-            for (int dj = 0; dj < 2; ++dj, ++t) {
-              int d = int((face * w2 + 2 * ci + di) * w2 + 2 * cj + dj);
-              int64_t s = IS[l].at(p, d);
-              if (s >= 0) {
-                par[4 * i + t] = int32_t(s);
-                op[4 * i + t] = d * 8 + int(C.octant[c]);
-              }
-            }
+          by[size_t(dc) * 8 + C.octant[c]].push_back(int32_t(i));
         }
-        H.l2l_par.upload(par);
-        H.l2l_op.upload(op);
+        for (int dc = 0; dc < nd_c; ++dc)
+          for (int o = 0; o < 8; ++o) {
+            auto& v = by[size_t(dc) * 8 + o];
+            if (v.empty()) continue;
+            int64_t face = dc / (wc_i * wc_i), rem = dc % (wc_i * wc_i);
+            int64_t ci = rem / wc_i, cj = rem % wc_i;
+            int dpar[4];
+            int t = 0;
+            for (int di = 0; di < 2; ++di)
+              for (int dj = 0; dj < 2; ++dj) dpar[t++] = int((face * w + 2 * ci + di) * w + 2 * cj + dj);
+            for (int tt = 0; tt < 4; ++tt) opsv.push_back(dpar[tt] * 8 + o);
+            for (int32_t i : v) {
+              int64_t c = IS[l + 1].list[i].first;
+              int64_t p = C.parent[c];
+              for (int tt = 0; tt < 4; ++tt) vsrc.push_back(int32_t(IS[l].at(p, dpar[tt])));
+              vdst.push_back(i);
+            }
+            v0.push_back(int32_t(vdst.size()));
+          }
+        G.T = 4;
       }
+      G.M = H.Rc;
+      G.K = H.R;
+      G.ngroups = int64_t(v0.size()) - 1;
+      G.nvec = int64_t(vdst.size());
+      G.nops = int64_t(ndir) * 8;
+      G.A.upload(Md);
+      G.ops.upload(opsv);
+      G.v0.upload(v0);
+      G.v0_h = v0;
+      G.vsrc.upload(vsrc);
+      G.vdst.upload(vdst);
     }
     // M2L
     std::vector<const Skel*> sp;
     for (auto& s : sk) sp.push_back(&s);
-    build_m2l(pairs[l], double(w), H.R, sp, sp, &OS[l], &IS[l], H.nin, H.T, H.grp_start,
-              H.pair_src, H.red_start, H.red_idx, H.ngroups, H.max_group, H.flops, H.gs_h);
+    build_m2l(pairs[l], double(w), H.R, sp, &OS[l], &IS[l], H.nin, H.m2l, H.red_start, H.red_idx, H.ngroups,
+              H.flops);
     info.flops_m2l_hf += H.flops;
   }
   auto t1 = std::chrono::steady_clock::now();

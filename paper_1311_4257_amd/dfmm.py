@@ -20,6 +20,9 @@ if not os.path.exists(LIB_PATH):
 
 _lib = C.CDLL(LIB_PATH)
 
+STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2l", "lf_reduce",
+          "leaf_eval", "zero"]
+
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
 
 ABI_FUNCTIONS = [
@@ -66,7 +69,7 @@ _sig = {
     "dfmm_plan_info": (C.c_int, [_P, C.POINTER(Info)]),
     "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
     "dfmm_set_timing": (C.c_int, [_P, C.c_int]),
-    "dfmm_stage_times": (C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
+    "dfmm_stage_times": (C.c_int, [_P, _D, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -207,14 +210,17 @@ class Plan:
                  EXPORT_OUT_SLOTS: 2, EXPORT_IN_SLOTS: 2}[what]
         return buf if width == 1 else buf.reshape(-1, width)
 
-    def set_timing(self, on: bool = True) -> None:
-        _check(_lib.dfmm_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, applies: int) -> None:
+        """Record stage events for up to ``applies`` following applies (0 = off)."""
+        _check(_lib.dfmm_set_timing(self._h, int(applies)))
 
-    def stage_times(self) -> list:
-        out = (C.c_double * 16)()
+    def stage_times(self) -> dict:
+        """Summed ms and launch counts per stage over the recorded applies."""
+        ms = (C.c_double * 16)()
+        cnt = (C.c_int64 * 16)()
         n = C.c_int()
-        _check(_lib.dfmm_stage_times(self._h, out, 16, C.byref(n)))
-        return list(out[: n.value])
+        _check(_lib.dfmm_stage_times(self._h, ms, cnt, 16, C.byref(n)))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES[: n.value])}
 
     def close(self) -> None:
         if self._h:
