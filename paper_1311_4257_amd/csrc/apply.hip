@@ -265,14 +265,14 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, i
   }
 }
 
-// ---- U[slot] += sum of Y over the pairs of the slot ------------------------------
+// ---- U[slot] (+)= sum of Y over the pairs of the slot -------------------------------
 __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri, const float2* __restrict__ Y,
-                         int64_t nslot, int RN, float2* __restrict__ U) {
+                         int64_t nslot, int RN, int accumulate, float2* __restrict__ U) {
   int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= nslot * RN) return;
   int64_t s = t / RN;
   int e = int(t % RN);
-  float2 acc = U[t];
+  float2 acc = accumulate ? U[t] : make_float2(0.f, 0.f);
   for (int j = rs[s]; j < rs[s + 1]; ++j) {
     float2 y = Y[int64_t(ri[j]) * RN + e];
     acc.x += y.x;
@@ -486,6 +486,8 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
     S.F.back()->alloc(sizeof(float2) * std::max<int64_t>(1, H.nout) * H.R * nrhs);
     S.U.back()->alloc(sizeof(float2) * std::max<int64_t>(1, H.nin) * H.R * nrhs);
     ymax = std::max<int64_t>(ymax, H.npairs * H.R);
+    ymax = std::max<int64_t>(ymax, H.m2m_npairs * H.R);
+    ymax = std::max<int64_t>(ymax, H.l2l_npairs * H.Rc);
   }
   S.Y.alloc(sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs);
   S.m2m.clear();
@@ -525,8 +527,13 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   mark(ST_S2M);
   // HF-M2M, fine to coarse
   for (int e = 0; e <= e_top; ++e) {
+    HFLevel& H = P.hf[e];
     const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
-    launch_gemm(S.m2m[e], nrhs, Fc, S.F[e]->as<float2>(), st);
+    launch_gemm(S.m2m[e], nrhs, Fc, S.Y.as<float2>(), st);
+    int RN = H.R * nrhs;
+    if (H.nout > 0)
+      hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nout * RN, 256)), dim3(256), 0, st, H.m2m_rs.as<int>(),
+                         H.m2m_ri.as<int>(), S.Y.as<float2>(), H.nout, RN, 0, S.F[e]->as<float2>());
     mark(ST_M2M);
   }
   // HF-M2L (+ reduction) then HF-L2L, coarse to fine
@@ -543,11 +550,15 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
       mark(ST_M2L);
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
-                         H.red_idx.as<int>(), S.Y.as<float2>(), H.nin, RN, S.U[e]->as<float2>());
+                         H.red_idx.as<int>(), S.Y.as<float2>(), H.nin, RN, 1, S.U[e]->as<float2>());
       mark(ST_REDUCE);
     }
     float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
-    launch_gemm(S.l2l[e], nrhs, S.U[e]->as<float2>(), Uc, st);
+    launch_gemm(S.l2l[e], nrhs, S.U[e]->as<float2>(), S.Y.as<float2>(), st);
+    int RNc = H.Rc * nrhs;
+    if (H.nchild_in > 0)
+      hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nchild_in * RNc, 256)), dim3(256), 0, st, H.l2l_rs.as<int>(),
+                         H.l2l_ri.as<int>(), S.Y.as<float2>(), H.nchild_in, RNc, 0, Uc);
     mark(ST_L2L);
   }
   if (e_top < 0) {
@@ -561,7 +572,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
     mark(ST_LF_M2L);
     int RN = Rl * nrhs;
     hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
-                       P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, S.ulf.as<float2>());
+                       P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, 1, S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
   hipLaunchKernelGGL(k_leaf_eval, dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(), P.ptlo.as<float4>(),

@@ -123,8 +123,12 @@ struct HFLevel {
   int Rc = 0;     // padded skeleton size of the child level (LF at e = 0)
   int64_t nout = 0, nin = 0, npairs = 0, ngroups = 0, nchild_in = 0;
   double flops = 0.0;  // 8 r_in r_out over pairs (unpadded ranks)
-  GGemm m2m;           // out-slots <- child out-slots (8 octant terms)
-  GGemm l2l;           // child in-slots <- parent in-slots (4 wedge terms, 6 at the LF hand-off)
+  GGemm m2m;           // (parent out-slot, child) pair outputs, grouped by (wedge, octant)
+  DevBuf m2m_rs, m2m_ri;  // CSR of pair outputs per out-slot
+  int64_t m2m_npairs = 0;
+  GGemm l2l;           // (child in-slot, parent in-slot) pair outputs, grouped by (wedge, octant)
+  DevBuf l2l_rs, l2l_ri;  // CSR of pair outputs per child in-slot (or leaf at e = 0)
+  int64_t l2l_npairs = 0;
   GGemm m2l;           // pair outputs <- source out-slots, grouped by offset
   DevBuf red_start;    // int32[nin + 1]: CSR of pair outputs per in-slot
   DevBuf red_idx;      // int32[npairs]

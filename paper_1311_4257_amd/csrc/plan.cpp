@@ -440,100 +440,85 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       pack_operator(dn.data(), H.Rc, H.R, &Md[size_t(2) * id * H.R * H.Rc]);
     });
 
-    // M2M: one group per wedge l; vectors = out-slots of that wedge; 8 octant terms
-    {
-      GGemm& G = H.m2m;
-      std::vector<std::vector<int32_t>> by_dir(ndir);
-      for (int64_t i = 0; i < H.nout; ++i) by_dir[OS[l].list[i].second].push_back(int32_t(i));
+    // HF-M2M and HF-L2L as pair lists: one pair per (parent slot, child), grouped
+    // by the (wedge, octant) operator it uses; the GEMM writes one output per
+    // pair and a reduction sums the pairs of each destination slot.
+    auto finish_pairs = [&](GGemm& G, std::vector<std::vector<std::pair<int32_t, int32_t>>>& by_op, int M,
+                            int K, int64_t nops, int64_t ndst, DevBuf& rs, DevBuf& ri, int64_t& npairs) {
+      // by_op[op] = list of (source vector, destination slot)
       std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv;
-      for (int d = 0; d < ndir; ++d) {
-        if (by_dir[d].empty()) continue;
-        for (int o = 0; o < 8; ++o) opsv.push_back(d * 8 + o);
-        for (int32_t i : by_dir[d]) {
-          int64_t b = OS[l].list[i].first;
-          int32_t src[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-          for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c)
-            src[C.octant[c]] = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
-          vsrc.insert(vsrc.end(), src, src + 8);
-          vdst.push_back(i);
+      std::vector<std::vector<int32_t>> per(ndst);
+      for (int64_t op = 0; op < int64_t(by_op.size()); ++op) {
+        if (by_op[op].empty()) continue;
+        opsv.push_back(int32_t(op));
+        for (auto& sd : by_op[op]) {
+          per[sd.second].push_back(int32_t(vsrc.size()));
+          vsrc.push_back(sd.first);
+          vdst.push_back(int32_t(vdst.size()));
         }
-        v0.push_back(int32_t(vdst.size()));
+        v0.push_back(int32_t(vsrc.size()));
       }
-      G.M = H.R;
-      G.K = H.Rc;
-      G.T = 8;
+      std::vector<int32_t> rstart(1, 0), ridx;
+      for (auto& v : per) {
+        ridx.insert(ridx.end(), v.begin(), v.end());
+        rstart.push_back(int32_t(ridx.size()));
+      }
+      G.M = M;
+      G.K = K;
+      G.T = 1;
       G.ngroups = int64_t(v0.size()) - 1;
-      G.nvec = int64_t(vdst.size());
-      G.nops = int64_t(ndir) * 8;
-      G.A.upload(Mu);
+      G.nvec = int64_t(vsrc.size());
+      G.nops = nops;
       G.ops.upload(opsv);
       G.v0.upload(v0);
       G.v0_h = v0;
       G.vsrc.upload(vsrc);
       G.vdst.upload(vdst);
-    }
-    // L2L: child in-slots grouped by (child wedge, octant); terms = the parent
-    // wedges that map down to the child wedge (4), or all 6 at the LF hand-off.
+      rs.upload(rstart);
+      ri.upload(ridx);
+      npairs = G.nvec;
+    };
     {
-      GGemm& G = H.l2l;
-      std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv;
+      std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op(size_t(ndir) * 8);
+      for (int64_t i = 0; i < H.nout; ++i) {
+        auto [b, d] = OS[l].list[i];
+        for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c) {
+          int32_t src = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
+          by_op[size_t(d) * 8 + C.octant[c]].push_back({src, int32_t(i)});
+        }
+      }
+      H.m2m.A.upload(Mu);
+      finish_pairs(H.m2m, by_op, H.R, H.Rc, int64_t(ndir) * 8, H.nout, H.m2m_rs, H.m2m_ri, H.m2m_npairs);
+    }
+    {
+      std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op(size_t(ndir) * 8);
       if (e == 0) {
         H.nchild_in = nleaf;
-        for (int o = 0; o < 8; ++o) {
-          std::vector<int32_t> kids;
-          for (int64_t c = 0; c < nleaf; ++c)
-            if (C.octant[c] == o) kids.push_back(int32_t(c));
-          if (kids.empty()) continue;
-          for (int d = 0; d < 6; ++d) opsv.push_back(d * 8 + o);
-          for (int32_t c : kids) {
-            int64_t p = C.parent[c];
-            for (int d = 0; d < 6; ++d) vsrc.push_back(int32_t(IS[l].at(p, d)));
-            vdst.push_back(c);
+        for (int64_t c = 0; c < nleaf; ++c) {
+          int64_t p = C.parent[c];
+          for (int d = 0; d < 6; ++d) {
+            int64_t sidx = IS[l].at(p, d);
+            if (sidx >= 0) by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(c)});
           }
-          v0.push_back(int32_t(vdst.size()));
         }
-        G.T = 6;
       } else {
         int64_t wc_i = w / 2;
-        int nd_c = int(6 * wc_i * wc_i);
         H.nchild_in = int64_t(IS[l + 1].list.size());
-        std::vector<std::vector<int32_t>> by(size_t(nd_c) * 8);
         for (int64_t i = 0; i < H.nchild_in; ++i) {
           auto [c, dc] = IS[l + 1].list[i];
-          by[size_t(dc) * 8 + C.octant[c]].push_back(int32_t(i));
-        }
-        for (int dc = 0; dc < nd_c; ++dc)
-          for (int o = 0; o < 8; ++o) {
-            auto& v = by[size_t(dc) * 8 + o];
-            if (v.empty()) continue;
-            int64_t face = dc / (wc_i * wc_i), rem = dc % (wc_i * wc_i);
-            int64_t ci = rem / wc_i, cj = rem % wc_i;
-            int dpar[4];
-            int t = 0;
-            for (int di = 0; di < 2; ++di)
-              for (int dj = 0; dj < 2; ++dj) dpar[t++] = int((face * w + 2 * ci + di) * w + 2 * cj + dj);
-            for (int tt = 0; tt < 4; ++tt) opsv.push_back(dpar[tt] * 8 + o);
-            for (int32_t i : v) {
-              int64_t c = IS[l + 1].list[i].first;
-              int64_t p = C.parent[c];
-              for (int tt = 0; tt < 4; ++tt) vsrc.push_back(int32_t(IS[l].at(p, dpar[tt])));
-              vdst.push_back(i);
+          int64_t p = C.parent[c];
+          int64_t face = dc / (wc_i * wc_i), rem = dc % (wc_i * wc_i);
+          int64_t ci = rem / wc_i, cj = rem % wc_i;
+          for (int di = 0; di < 2; ++di)
+            for (int dj = 0; dj < 2; ++dj) {
+              int d = int((face * w + 2 * ci + di) * w + 2 * cj + dj);
+              int64_t sidx = IS[l].at(p, d);
+              if (sidx >= 0) by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(i)});
             }
-            v0.push_back(int32_t(vdst.size()));
-          }
-        G.T = 4;
+        }
       }
-      G.M = H.Rc;
-      G.K = H.R;
-      G.ngroups = int64_t(v0.size()) - 1;
-      G.nvec = int64_t(vdst.size());
-      G.nops = int64_t(ndir) * 8;
-      G.A.upload(Md);
-      G.ops.upload(opsv);
-      G.v0.upload(v0);
-      G.v0_h = v0;
-      G.vsrc.upload(vsrc);
-      G.vdst.upload(vdst);
+      H.l2l.A.upload(Md);
+      finish_pairs(H.l2l, by_op, H.Rc, H.R, int64_t(ndir) * 8, H.nchild_in, H.l2l_rs, H.l2l_ri, H.l2l_npairs);
     }
     // M2L
     std::vector<const Skel*> sp;
