@@ -148,7 +148,7 @@ def main() -> int:
         "plan_seconds": info.plan_seconds,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pts, f, K, 0.1 * eps)
+        out["cpu_baseline"] = cpu_baseline(pts, f, K, 0.15 * eps)  # the library's tau for eps
     print(json.dumps(out))
     return 0
 

@@ -44,10 +44,23 @@ import scipy.linalg as sla
 from .kernel import green
 from .tree import direction, direction_down, near_limit4, near_sum
 
-# sample sizes (oracle's own choice; any adequate sampling gives a valid skeleton)
-N_Y = 900            # candidate equivalent points in the box
-N_OWN = 1200         # points drawn in the region's own boxes
+# sample sizes (oracle's own choice; any adequate sampling gives a valid skeleton).
+# Wider boxes have more wavelengths across them and wider far regions, and
+# tighter tolerances resolve finer detail, so both samples grow with w and 1/tau.
+N_Y = 900            # candidate equivalent points in a box of width <= 1
+N_OWN = 1200         # points drawn in the region's own boxes, per unit width
 MIN_PER_BOX = 6
+
+
+def sample_sizes(w: float, tau: float):
+    """(points in the far region's own boxes, candidate points in the box)."""
+    ww = max(1.0, float(w))
+    n_own = N_OWN * ww
+    n_y = N_Y * (1.0 + 0.35 * np.log2(ww))
+    if tau < 1e-6:
+        n_own *= 2.5
+        n_y *= 16.0 / 9.0
+    return int(round(n_own)), int(round(n_y))
 
 
 @dataclass
@@ -139,14 +152,15 @@ def build_opset(tau: float, w_hi: int, seed: int = 12345, verbose: bool = False)
         for l in range(6 * w * w):
             rng = np.random.default_rng([seed, w, l])
             own = offs[dirs == l] * float(w)
-            parts = [_sample_boxes(rng, own, float(w), N_OWN)] if len(own) else []
+            n_own, n_y = sample_sizes(w, tau)
+            parts = [_sample_boxes(rng, own, float(w), n_own)] if len(own) else []
             if 2 * w in hf:
                 dl = child_deltas(float(w))
                 for lp, s in enumerate(hf[2 * w]):
                     if direction_down(lp, 2 * w) == l:
                         parts.append((s.a[None, :, :] - dl[:, None, :]).reshape(-1, 3))
             X = np.concatenate(parts, axis=0)
-            Y = (rng.random((N_Y, 3)) - 0.5) * w
+            Y = (rng.random((n_y, 3)) - 0.5) * w
             sk.append(skeleton(X, Y, tau))
             if verbose:
                 print(f"w={w} l={l} |X|={len(X)} r={sk[-1].r}", flush=True)
@@ -155,13 +169,14 @@ def build_opset(tau: float, w_hi: int, seed: int = 12345, verbose: bool = False)
     # low-frequency level, width 1/2
     rng = np.random.default_rng([seed, 0, 0])
     offs = region_offsets(0.5) * 0.5
-    parts = [_sample_boxes(rng, offs, 0.5, N_OWN)]
+    n_own, n_y = sample_sizes(0.5, tau)
+    parts = [_sample_boxes(rng, offs, 0.5, n_own)]
     if 1 in hf:
         dl = child_deltas(0.5)
         for s in hf[1]:
             parts.append((s.a[None, :, :] - dl[:, None, :]).reshape(-1, 3))
     X = np.concatenate(parts, axis=0)
-    Y = (rng.random((N_Y, 3)) - 0.5) * 0.5
+    Y = (rng.random((n_y, 3)) - 0.5) * 0.5
     lf = skeleton(X, Y, tau)
     if verbose:
         print(f"LF |X|={len(X)} r={lf.r}", flush=True)

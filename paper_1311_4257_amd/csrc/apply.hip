@@ -19,7 +19,6 @@ namespace dfmm {
 
 namespace {
 
-constexpr int RC = 4;  // right-hand sides handled per pass of a kernel
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -40,6 +39,41 @@ __device__ __forceinline__ float2 green_d(double dx, double dy, double dz) {
   float s, c;
   sincospif(2.0f * t, &s, &c);
   float ri = rsqrtf(float(r2));
+  return make_float2(c * ri, s * ri);
+}
+
+// sin and cos of 2 pi t for |t| <= 1/2 (t in turns): quadrant q = rint(4 t),
+// f = t - q/4 (exact), x = 2 pi f in [-pi/4, pi/4]; Taylor polynomials of sin
+// (to x^9) and cos (to x^10) have truncation errors below 2e-9 there, so the
+// float32 rounding (~1e-7) dominates; the quadrant rotates the pair.
+__device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
+  const float q = rintf(4.0f * t);
+  const float f = fmaf(-0.25f, q, t);
+  const float x = f * 6.28318530717958648f;
+  const float x2 = x * x;
+  float ps = fmaf(x2, 2.7557319e-06f, -1.9841270e-04f);   // 1/9!, -1/7!
+  ps = fmaf(x2, ps, 8.3333333e-03f);                        // 1/5!
+  ps = fmaf(x2, ps, -1.6666667e-01f);                       // -1/3!
+  ps = x * fmaf(x2, ps, 1.0f);
+  float pc = fmaf(x2, -2.7557319e-07f, 2.4801587e-05f);     // -1/10!, 1/8!
+  pc = fmaf(x2, pc, -1.3888889e-03f);                       // -1/6!
+  pc = fmaf(x2, pc, 4.1666668e-02f);                        // 1/4!
+  pc = fmaf(x2, pc, -0.5f);                                 // -1/2!
+  pc = fmaf(x2, pc, 1.0f);
+  const int qi = int(q) & 3;
+  s = qi == 0 ? ps : (qi == 1 ? pc : (qi == 2 ? -ps : -pc));
+  c = qi == 0 ? pc : (qi == 1 ? -ps : (qi == 2 ? -pc : ps));
+}
+
+// G for a float32 separation: r from float32 squares, phase r - rint(r),
+// sin/cos by sincos_turns.  Phase error ~2e-7 r rad: for the eps >= 1e-5 plans.
+__device__ __forceinline__ float2 green_f(float dx, float dy, float dz) {
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  if (r2 == 0.0f) return make_float2(0.0f, 0.0f);
+  const float ri = rsqrtf(r2);
+  const float r = r2 * ri;
+  float s, c;
+  sincos_turns(r - rintf(r), s, c);
   return make_float2(c * ri, s * ri);
 }
 
@@ -108,6 +142,7 @@ __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict
 // check points are contiguous).  D_LF is folded into the operators that read
 // these potentials.
 constexpr int S2M_BS = 128;
+template <int RC>  // right-hand sides per pass
 __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, const float2* __restrict__ V,
                                                  const float2* __restrict__ fs, int R, int nrhs,
                                                  float2* __restrict__ clf) {
@@ -273,8 +308,18 @@ __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri,
   int64_t s = t / RN;
   int e = int(t % RN);
   float2 acc = accumulate ? U[t] : make_float2(0.f, 0.f);
-  for (int j = rs[s]; j < rs[s + 1]; ++j) {
-    float2 y = Y[int64_t(ri[j]) * RN + e];
+  int j = rs[s];
+  const int j1 = rs[s + 1];
+  for (; j + 4 <= j1; j += 4) {  // four loads in flight, added in order
+    const float2 y0 = Y[int64_t(ri[j]) * RN + e], y1 = Y[int64_t(ri[j + 1]) * RN + e];
+    const float2 y2 = Y[int64_t(ri[j + 2]) * RN + e], y3 = Y[int64_t(ri[j + 3]) * RN + e];
+    acc.x += y0.x; acc.y += y0.y;
+    acc.x += y1.x; acc.y += y1.y;
+    acc.x += y2.x; acc.y += y2.y;
+    acc.x += y3.x; acc.y += y3.y;
+  }
+  for (; j < j1; ++j) {
+    const float2 y = Y[int64_t(ri[j]) * RN + e];
     acc.x += y.x;
     acc.y += y.y;
   }
@@ -286,25 +331,52 @@ __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri,
 // wave takes the leaf's targets 16 at a time and every lane sums over a quarter
 // of the sources (rows q of the L2T weights W, points of the adjacent leaves
 // for the near field); the four partial sums of a target are combined with
-// lane shuffles.  The near field forms point differences from the hi/lo parts
-// in float64 (green_d) and accumulates in float64.
+// lane shuffles.  The adjacent leaves' points are staged in LDS in chunks.
+// Near-field terms accumulate in float64.  PRECISE (plans with eps < 1e-5)
+// forms the point differences from the hi/lo parts in float64 (green_d);
+// otherwise they are float32 hi/lo differences and green_f.
 constexpr int EV_BS = 64;
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }
 
+constexpr int EV_CHUNK = 256;  // source points staged in LDS at a time
+template <bool PRECISE, int RC>  // RC: right-hand sides per pass
 __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ phi, const float4* __restrict__ plo,
                                                       const int* __restrict__ lstart,
                                                       const int* __restrict__ nstart, const int* __restrict__ nsrc,
                                                       const float2* __restrict__ fs, const float2* __restrict__ W,
                                                       const float2* __restrict__ ulf, int R, int nrhs, int64_t N,
                                                       const int* __restrict__ perm, float2* __restrict__ u) {
+  __shared__ float4 sh[EV_CHUNK], sq[EV_CHUNK];
+  __shared__ float2 sf[EV_CHUNK * RC];
+  __shared__ int nb_beg[EV_BS], nb_off[EV_BS + 1];
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   const int tl = lane & 15, sl = lane >> 4;
   const int s0 = lstart[b], s1 = lstart[b + 1];
-  const int n0 = nstart[b], n1 = nstart[b + 1];
+  const int n0 = nstart[b];
+  const int nn = min(nstart[b + 1] - n0, EV_BS);  // adjacent leaves (at most 27)
+  // all neighbour ranges at once; offsets by a wave prefix sum
+  {
+    int beg = 0, cnt = 0;
+    if (lane < nn) {
+      const int A = nsrc[n0 + lane];
+      beg = lstart[A];
+      cnt = lstart[A + 1] - beg;
+    }
+    int incl = cnt;
+    for (int d = 1; d < EV_BS; d <<= 1) {
+      const int v = __shfl_up(incl, d, EV_BS);
+      if (lane >= d) incl += v;
+    }
+    nb_beg[lane] = beg;
+    nb_off[lane] = incl - cnt;
+    if (lane == EV_BS - 1) nb_off[EV_BS] = incl;
+  }
+  __syncthreads();
+  const int total = nb_off[nn];
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int nk = min(RC, nrhs - k0);
     for (int t0 = s0; t0 < s1; t0 += 16) {
@@ -313,13 +385,12 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
       const int tt = act ? t : s0;
       const float4 th = phi[tt], tq = plo[tt];
       double ar[RC], ai[RC];
-#pragma unroll
-      for (int k = 0; k < RC; ++k) ar[k] = ai[k] = 0.0;
       // L2T: sum_q W[t][q] U_LF[leaf][k][q] over this lane's quarter of q
       {
         float2 acc[RC];
 #pragma unroll
         for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
+#pragma unroll 4
         for (int q = sl; q < R; q += 4) {
           const float2 w = W[int64_t(tt) * R + q];
 #pragma unroll
@@ -332,20 +403,35 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
           ai[k] = acc[k].y;
         }
       }
-      // near field over this lane's quarter of each adjacent leaf's points
-      for (int a = n0; a < n1; ++a) {
-        const int A = nsrc[a];
-        const int q1 = lstart[A + 1];
-        for (int j = lstart[A] + sl; j < q1; j += 4) {
-          const float4 h = phi[j], l = plo[j];
-          const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
-          const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
-          const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
-          const float2 gg = green_d(dx, dy, dz);
+      // near field: the adjacent leaves' points are staged in LDS chunk by chunk
+      for (int base = 0; base < total; base += EV_CHUNK) {
+        const int fill = min(EV_CHUNK, total - base);
+        __syncthreads();
+        for (int i = lane; i < fill; i += EV_BS) {
+          const int gidx = base + i;
+          int kk = 0;
+          while (kk + 1 < nn && nb_off[kk + 1] <= gidx) ++kk;
+          const int j = nb_beg[kk] + (gidx - nb_off[kk]);
+          sh[i] = phi[j];
+          sq[i] = plo[j];
+          for (int k = 0; k < nk; ++k) sf[i * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
+        }
+        __syncthreads();
+        for (int i = sl; i < fill; i += 4) {
+          const float4 h = sh[i], l = sq[i];
+          float2 gg;
+          if (PRECISE) {
+            const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
+            const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
+            const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
+            gg = green_d(dx, dy, dz);
+          } else {
+            gg = green_f((th.x - h.x) + (tq.x - l.x), (th.y - h.y) + (tq.y - l.y), (th.z - h.z) + (tq.z - l.z));
+          }
 #pragma unroll
           for (int k = 0; k < RC; ++k) {
             if (k < nk) {
-              const float2 fk = fs[int64_t(j) * nrhs + k0 + k];
+              const float2 fk = sf[i * RC + k];
               ar[k] += double(gg.x * fk.x - gg.y * fk.y);
               ai[k] += double(gg.x * fk.y + gg.y * fk.x);
             }
@@ -522,8 +608,12 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, f, S.fs.as<float2>(),
                      P.perm_d.as<int>(), N, nrhs);
   mark(ST_PERMUTE);
-  hipLaunchKernelGGL(k_s2m, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
-                     P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_s2m<1>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+  else
+    hipLaunchKernelGGL(k_s2m<8>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
   mark(ST_S2M);
   // HF-M2M, fine to coarse
   for (int e = 0; e <= e_top; ++e) {
@@ -575,9 +665,16 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
                        P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, 1, S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
-  hipLaunchKernelGGL(k_leaf_eval, dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(), P.ptlo.as<float4>(),
-                     P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(),
-                     P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u);
+#define DFMM_LEAF(PREC, RCV)                                                                                \
+  hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(),   \
+                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), \
+                     S.fs.as<float2>(), P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u)
+  if (P.precise) {
+    if (nrhs == 1) DFMM_LEAF(true, 1); else DFMM_LEAF(true, 8);
+  } else {
+    if (nrhs == 1) DFMM_LEAF(false, 1); else DFMM_LEAF(false, 8);
+  }
+#undef DFMM_LEAF
   mark(ST_LEAF);
   DFMM_HIP(hipGetLastError());
 }

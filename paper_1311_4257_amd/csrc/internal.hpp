@@ -198,6 +198,7 @@ struct dfmm_plan_s {
   double K = 0.0;
   int D = 0;       // leaf level
   int w_top = 0;
+  bool precise = false;  // eps < 1e-5: float64 distances in the near field
   double plan_seconds = 0.0;
   dfmm_info info{};
   // host copies of structures for export

@@ -6,10 +6,11 @@
 // The paper points to a random sampling method built on pivoted QR; the
 // steps taken here:
 //   1. draw sample sets Y (uniform in the box) and X (the far region);
-//   2. column-pivoted Householder QR of M = G(X, Y), stopped at the first
-//      rank r whose trailing Frobenius norm is <= tau ||M||_F; b = Y at the
-//      first r pivots;
-//   3. column-pivoted QR of M^T for r steps; a = X at those pivots;
+//   2. column-pivoted Householder QR of a Gaussian sketch of M = G(X, Y),
+//      stopped at the first rank r whose trailing Frobenius norm is <= tau of
+//      the total; b = Y at the first r pivots;
+//   3. column-pivoted QR of a Gaussian sketch of M^T for r steps; a = X at
+//      those pivots;
 //   4. D = G(X, b)^+ M G(a, Y)^+ (least squares through Householder QR), the
 //      middle factor that best reproduces M from the chosen rows and columns.
 // Far regions: at HF width w and wedge l, the boxes of the offsets that can
@@ -34,9 +35,22 @@ namespace dfmm {
 
 namespace {
 
-constexpr int kNY = 900;        // candidate equivalent points per box
-constexpr int kNOwn = 1200;     // samples in the own boxes of a far region
+// Sample sizes: wider boxes (more wavelengths across, wider far regions) and
+// tighter tolerances need denser samples for the skeleton to hold between them.
+constexpr double kNY = 900.0;      // candidate equivalent points, box width <= 1
+constexpr double kNOwn = 1200.0;   // far-region samples per unit width
 constexpr int kMinPerBox = 6;
+
+void sample_sizes(double w, double tau, int* n_own, int* n_y) {
+  double ww = w < 1.0 ? 1.0 : w;
+  double o = kNOwn * ww, y = kNY * (1.0 + 0.35 * std::log2(ww));
+  if (tau < 1e-6) {
+    o *= 2.5;
+    y *= 16.0 / 9.0;
+  }
+  *n_own = int(std::lround(o));
+  *n_y = int(std::lround(y));
+}
 constexpr uint64_t kSeed = 0x5eed0fd1f3a11ULL;
 
 // SplitMix64 (Steele, Lea, Flood 2014) -> uniform double in [0, 1).
@@ -243,21 +257,134 @@ std::vector<double> pick(const std::vector<double>& P, const std::vector<int>& i
   return out;
 }
 
-Skel make_skeleton(const std::vector<double>& X, const std::vector<double>& Y, double tau) {
+// C = A^H B for column-major complex A (m x p) and B (m x n); cache-blocked,
+// four independent partial sums per dot product.
+CMat gemm_hn(const CMat& A, const CMat& B) {
+  const int m = A.m, p = A.n, n = B.n;
+  CMat C(p, n);
+  constexpr int BI = 8, BJ = 8, BL = 512;
+  for (int j0 = 0; j0 < n; j0 += BJ)
+    for (int i0 = 0; i0 < p; i0 += BI)
+      for (int l0 = 0; l0 < m; l0 += BL) {
+        const int l1 = std::min(m, l0 + BL);
+        for (int j = j0; j < std::min(n, j0 + BJ); ++j) {
+          const double* bc = B.col(j);
+          for (int i = i0; i < std::min(p, i0 + BI); ++i) {
+            const double* ac = A.col(i);
+            double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+            int l = l0;
+            for (; l + 4 <= l1; l += 4)
+              for (int u = 0; u < 4; ++u) {
+                const double ar = ac[2 * (l + u)], ai = ac[2 * (l + u) + 1];
+                const double br = bc[2 * (l + u)], bi = bc[2 * (l + u) + 1];
+                sr[u] += ar * br + ai * bi;
+                si[u] += ar * bi - ai * br;
+              }
+            for (; l < l1; ++l) {
+              const double ar = ac[2 * l], ai = ac[2 * l + 1], br = bc[2 * l], bi = bc[2 * l + 1];
+              sr[0] += ar * br + ai * bi;
+              si[0] += ar * bi - ai * br;
+            }
+            C.col(j)[2 * i] += (sr[0] + sr[1]) + (sr[2] + sr[3]);
+            C.col(j)[2 * i + 1] += (si[0] + si[1]) + (si[2] + si[3]);
+          }
+        }
+      }
+  return C;
+}
+
+// Thin Householder QR of A (m x r, full column rank): returns the explicit
+// orthonormal factor Q (m x r); R (upper, r x r) is left in A's upper part with
+// its diagonal in rdiag.
+CMat thin_q(CMat& A, std::vector<double>& rdiag) {
+  const int m = A.m, r = A.n;
+  std::vector<double> beta(r);
+  rdiag.assign(2 * size_t(r), 0.0);
+  for (int j = 0; j < r; ++j) {
+    double* v = A.col(j) + 2 * j;
+    double ar, ai;
+    beta[j] = householder(v, m - j, &ar, &ai);
+    rdiag[2 * j] = ar;
+    rdiag[2 * j + 1] = ai;
+    for (int c = j + 1; c < r; ++c)
+      if (beta[j] != 0.0) apply_reflector(v, m - j, beta[j], A.col(c) + 2 * j);
+  }
+  CMat Q(m, r);
+  for (int c = 0; c < r; ++c) {
+    Q.col(c)[2 * c] = 1.0;
+    for (int j = std::min(c, r - 1); j >= 0; --j)
+      if (beta[j] != 0.0) apply_reflector(A.col(j) + 2 * j, m - j, beta[j], Q.col(c) + 2 * j);
+  }
+  return Q;
+}
+
+// Solve R X = B in place (R upper r x r stored in A's upper part, diagonal rdiag).
+void back_substitute(const CMat& A, const std::vector<double>& rdiag, CMat& B) {
+  const int r = A.n;
+  for (int c = 0; c < B.n; ++c) {
+    double* x = B.col(c);
+    for (int i = r - 1; i >= 0; --i) {
+      double sr = x[2 * i], si = x[2 * i + 1];
+      for (int j = i + 1; j < r; ++j) {
+        const double ar = A.col(j)[2 * i], ai = A.col(j)[2 * i + 1];
+        sr -= ar * x[2 * j] - ai * x[2 * j + 1];
+        si -= ar * x[2 * j + 1] + ai * x[2 * j];
+      }
+      const double dr = rdiag[2 * i], di = rdiag[2 * i + 1], den = dr * dr + di * di;
+      x[2 * i] = (sr * dr + si * di) / den;
+      x[2 * i + 1] = (si * dr - sr * di) / den;
+    }
+  }
+}
+
+// C^+ B for tall C (m x r) through its explicit thin Q: R^{-1} (Q^H B).
+CMat lstsq_q(CMat C, const CMat& B) {
+  std::vector<double> rdiag;
+  CMat Q = thin_q(C, rdiag);
+  CMat Z = gemm_hn(Q, B);
+  back_substitute(C, rdiag, Z);
+  return Z;
+}
+
+// Skeleton of Eq. 2 from the samples X (far) and Y (box):
+//   column selection: a Gaussian sketch Omega M (k x nY) of M = G(X, Y) is
+//   pivoted-QR factored (randomized column-pivoted QR: the sketch preserves
+//   column norms and angles of M up to small distortion); the rank r is the
+//   first with trailing Frobenius norm <= tau of the total;
+//   row selection: the same on a Gaussian sketch of M^T (r steps);
+//   D = G(X, b)^+ M G(a, Y)^+.
+Skel make_skeleton(const std::vector<double>& X, const std::vector<double>& Y, double tau, uint64_t seed) {
   CMat M = kernel_matrix(X, Y);
-  CMat W = M;
-  std::vector<int> pc = pivoted_qr(W, tau, 1 << 30);
+  const int m = M.m, n = M.n;
+  const int ks = std::min(n, tau < 1e-6 ? 384 : 256);
+  CMat Om(m, ks);
+  Rng rng(seed);
+  for (int c = 0; c < ks; ++c)
+    for (int i = 0; i < m; ++i) {  // Box-Muller, real Gaussian entries
+      double u1 = rng.uniform(), u2 = rng.uniform();
+      if (u1 < 1e-300) u1 = 1e-300;
+      Om.col(c)[2 * i] = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    }
+  CMat Zs = gemm_hn(Om, M);  // ks x n
+  std::vector<int> pc = pivoted_qr(Zs, tau, ks - 8);
   int r = int(pc.size());
   Skel s;
   s.r = r;
   s.b = pick(Y, pc);
-  CMat Mt = transpose(M);
-  std::vector<int> pr = pivoted_qr(Mt, -1.0, r);
+  // rows: column-pivoted QR of a Gaussian sketch of M^T (k x m), r steps
+  CMat Om2(n, ks);
+  for (int c = 0; c < ks; ++c)
+    for (int i = 0; i < n; ++i) {
+      double u1 = rng.uniform(), u2 = rng.uniform();
+      if (u1 < 1e-300) u1 = 1e-300;
+      Om2.col(c)[2 * i] = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    }
+  CMat Zr = gemm_hn(Om2, transpose(M));  // ks x m
+  std::vector<int> pr = pivoted_qr(Zr, -1.0, r);
   s.a = pick(X, pr);
+  CMat C = kernel_matrix(X, s.b);  // m x r
   // Z = G(X,b)^+ M  (r x nY);  D^H = (G(a,Y)^H)^+ Z^H
-  CMat C = kernel_matrix(X, s.b);
-  CMat Mc = M;
-  CMat Z = lstsq(C, Mc);
+  CMat Z = lstsq_q(C, M);
   CMat Ra = conj_transpose(kernel_matrix(s.a, Y));  // nY x r
   CMat Zh = conj_transpose(Z);                       // nY x r
   CMat Dh = lstsq(Ra, Zh);                           // r x r = D^H
@@ -267,13 +394,14 @@ Skel make_skeleton(const std::vector<double>& X, const std::vector<double>& Y, d
       s.D[2 * (size_t(q) * r + p)] = Dh.col(q)[2 * p];
       s.D[2 * (size_t(q) * r + p) + 1] = -Dh.col(q)[2 * p + 1];
     }
+  (void)m;
   return s;
 }
 
-void sample_boxes(Rng& rng, const std::vector<double>& centres, double w, std::vector<double>& out) {
+void sample_boxes(Rng& rng, const std::vector<double>& centres, double w, int n_total, std::vector<double>& out) {
   size_t nb = centres.size() / 3;
   if (nb == 0) return;
-  size_t k = std::max<size_t>(kMinPerBox, (kNOwn + nb - 1) / nb);
+  size_t k = std::max<size_t>(kMinPerBox, (size_t(n_total) + nb - 1) / nb);
   for (size_t b = 0; b < nb; ++b)
     for (size_t i = 0; i < k; ++i)
       for (int t = 0; t < 3; ++t) out.push_back(centres[3 * b + t] + w * (rng.uniform() - 0.5));
@@ -321,14 +449,16 @@ void build_opset(OpSetImpl& set) {
     out.assign(ndir, Skel());
     parallel_for(ndir, [&](int l) {
       Rng rng(kSeed ^ (uint64_t(e + 1) << 40) ^ (uint64_t(l) << 8));
+      int n_own, n_y;
+      sample_sizes(double(w), tau, &n_own, &n_y);
       std::vector<double> X;
-      sample_boxes(rng, own[l], double(w), X);
+      sample_boxes(rng, own[l], double(w), n_own, X);
       if (e < emax)
         for (int lp = 0; lp < int(6 * 4 * w * w); ++lp)
           if (direction_down(lp, 2 * w) == l) add_inherited(set.hf[e + 1][lp], double(w), X);
-      std::vector<double> Y(3 * kNY);
+      std::vector<double> Y(3 * size_t(n_y));
       for (auto& v : Y) v = (rng.uniform() - 0.5) * double(w);
-      out[l] = make_skeleton(X, Y, tau);
+      out[l] = make_skeleton(X, Y, tau, kSeed ^ (uint64_t(e + 7) << 48) ^ (uint64_t(l) << 16) ^ 0x9e37ULL);
     });
   }
   // low-frequency width 1/2
@@ -336,16 +466,18 @@ void build_opset(OpSetImpl& set) {
   std::vector<int64_t> offs = list_offsets_e2(0);
   std::vector<double> cen;
   for (int64_t v : offs) cen.push_back(0.5 * double(v));
+  int n_own, n_y;
+  sample_sizes(0.5, tau, &n_own, &n_y);
   std::vector<double> X;
-  sample_boxes(rng, cen, 0.5, X);
+  sample_boxes(rng, cen, 0.5, n_own, X);
   for (const Skel& p : set.hf[0]) add_inherited(p, 0.5, X);
-  std::vector<double> Y(3 * kNY);
+  std::vector<double> Y(3 * size_t(n_y));
   for (auto& v : Y) v = (rng.uniform() - 0.5) * 0.5;
-  set.lf = make_skeleton(X, Y, tau);
+  set.lf = make_skeleton(X, Y, tau, kSeed ^ 0x1f1f1f1fULL);
 }
 
 // ---- file format ----------------------------------------------------------
-// "DFMMOPS1", float64 tau, int32 w_hi, int32 count, then `count` skeletons in
+// "DFMMOPS2", float64 tau, int32 w_hi, int32 count, then `count` skeletons in
 // the order w = 1 (dirs 0..5), w = 2 (0..23), ..., w_hi, then the LF skeleton;
 // each: int32 r, float64 a[3r], float64 b[3r], float64 D[2 r r] (row-major
 // complex).  Little-endian.
@@ -356,7 +488,7 @@ bool save_opset(const OpSetImpl& set, const std::string& path) {
   if (!f) return false;
   bool ok = true;
   auto W = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
-  W("DFMMOPS1", 8);
+  W("DFMMOPS2", 8);
   W(&set.tau, 8);
   int32_t whi = set.w_hi, cnt = 1;
   for (auto& v : set.hf) cnt += int32_t(v.size());
@@ -385,7 +517,7 @@ bool load_opset(OpSetImpl& set, const std::string& path) {
   auto R = [&](void* p, size_t n) { ok = ok && std::fread(p, 1, n, f) == n; };
   char magic[8];
   R(magic, 8);
-  ok = ok && std::memcmp(magic, "DFMMOPS1", 8) == 0;
+  ok = ok && std::memcmp(magic, "DFMMOPS2", 8) == 0;
   int32_t whi = 0, cnt = 0;
   R(&set.tau, 8);
   R(&whi, 4);
