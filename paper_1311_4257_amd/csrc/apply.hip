@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.hpp"
@@ -185,28 +186,29 @@ __host__ __device__ inline int gg_stride(int K) {
   return s + ((4 - (s % 32)) + 32) % 32;
 }
 
-template <int MT, int NT>
-__global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, int M, int K, int T,
+template <int MT, int NT, bool ALDS>  // ALDS: stage the operator slice in LDS first
+__global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
+                                                  const int* __restrict__ gmk, int M, int K, int T,
                                                   const int* __restrict__ gops, const int* __restrict__ gv0,
                                                   const int* __restrict__ vsrc, const int* __restrict__ vdst,
                                                   const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
                                                   int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
-  const int S = gg_stride(K);           // floats per LDS column
+  const int S = gg_stride(K);           // floats per LDS column (K = the largest K_g)
   const int S4 = S / 4;
-  const int Q4 = K / 8;                 // float4 steps per K quarter (K/2 real k per quarter)
-  const int nM = M / 8;                 // 16-row real M-tiles
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int j = lane & 15, kr = lane >> 4;
   const int slice = blockIdx.y, nslice = gridDim.y;
   const int g = chunk_grp[blockIdx.x];
+  const int Mg = gmk[2 * g], Kg = gmk[2 * g + 1];  // this group's operator size
+  const int Q4 = Kg / 8;                 // float4 steps per K quarter (K_g/2 real k per quarter)
+  const int nM = Mg / 8;                 // 16-row real M-tiles with data
   const int64_t c0 = chunk_c0[blockIdx.x];
   const int vbeg = gv0[g];
   const int64_t ncol = int64_t(gv0[g + 1] - vbeg) * nrhs;
   const int nc = int(min<int64_t>(NC, ncol - c0));
-  const int64_t opsz = int64_t(M) * K / 2;  // float4 per operator
 
   v4f acc[MT][NT];
 #pragma unroll
@@ -218,8 +220,9 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, i
     const int op = gops[g * T + t];
     if (op < 0) continue;
     __syncthreads();
-    // stage the source vectors of this term: column c -> X[(src * nrhs + k) * K]
-    const int per_col = K / 2;  // float4 per column
+    // stage the source vectors of this term: column c -> X[(src * nrhs + k) * K],
+    // its first K_g complex entries
+    const int per_col = Kg / 2;  // float4 per column
     for (int idx = threadIdx.x; idx < NC * per_col; idx += GG_BS) {
       int col = idx / per_col, q4 = idx % per_col;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -232,55 +235,68 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, i
       }
       xs[col * S4 + q4] = v;
     }
+    const float4* Aop = A + aoff[op];
+    const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
+    float4* as = xs + NC * S4;  // operator slice (ALDS): 4 consecutive M-tiles per mm
+    if (ALDS) {
+      // one coalesced bulk copy of this workgroup's M-tiles (many loads in flight)
+      for (int idx = threadIdx.x; idx < MT * 4 * tile4; idx += GG_BS) {
+        const int blk = idx / tile4, off = idx % tile4;
+        const int m = (blk & 3) + 4 * (slice + nslice * (blk >> 2));
+        as[idx] = m < nM ? Aop[int64_t(m) * tile4 + off] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
     __syncthreads();
-    const float4* Aop = A + int64_t(op) * opsz;
     // register double buffering: the A and B fragments of step s4 + 1 are in
     // flight while the MFMAs of step s4 run
+    auto afrag = [&](int mm, int step) -> float4 {
+      if (ALDS) return as[(mm * 4 + wave) * tile4 + (step * 8 + (j >> 1)) * 4 + kr];
+      const int m = wave + 4 * (slice + nslice * mm);
+      return m < nM ? Aop[((int64_t(m) * Q4 + step) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
     float4 ca[MT], cb[NT];
 #pragma unroll
-    for (int mm = 0; mm < MT; ++mm) {
-      const int m = wave + 4 * (slice + nslice * mm);
-      ca[mm] = m < nM ? Aop[((int64_t(m) * Q4) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    for (int mm = 0; mm < MT; ++mm) ca[mm] = afrag(mm, 0);
 #pragma unroll
     for (int n = 0; n < NT; ++n) cb[n] = xs[(n * 16 + j) * S4 + kr * Q4];
     for (int s4 = 0; s4 < Q4; ++s4) {
       const int sn = s4 + 1 < Q4 ? s4 + 1 : s4;
       float4 na[MT], nb[NT];
 #pragma unroll
-      for (int mm = 0; mm < MT; ++mm) {
-        const int m = wave + 4 * (slice + nslice * mm);
-        na[mm] = m < nM ? Aop[((int64_t(m) * Q4 + sn) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      for (int mm = 0; mm < MT; ++mm) na[mm] = afrag(mm, sn);
 #pragma unroll
       for (int n = 0; n < NT; ++n) nb[n] = xs[(n * 16 + j) * S4 + kr * Q4 + sn];
+      // expand the complex A fragments into the real rows (re: Re,-Im; im: Im,Re)
+      float av[MT][4];
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) {
-        const int m = wave + 4 * (slice + nslice * mm);
-        if (m < nM) {
-          const float4 c = ca[mm];
-          float a0, a1, a2, a3;
-          if (j & 1) {
-            a0 = c.y; a1 = c.x; a2 = c.w; a3 = c.z;
-          } else {
-            a0 = c.x; a1 = -c.y; a2 = c.z; a3 = -c.w;
-          }
-#pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, cb[n].x, acc[mm][n], 0, 0, 0);
-            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, cb[n].y, acc[mm][n], 0, 0, 0);
-            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, cb[n].z, acc[mm][n], 0, 0, 0);
-            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, cb[n].w, acc[mm][n], 0, 0, 0);
-          }
+        const float4 c = ca[mm];
+        if (j & 1) {
+          av[mm][0] = c.y; av[mm][1] = c.x; av[mm][2] = c.w; av[mm][3] = c.z;
+        } else {
+          av[mm][0] = c.x; av[mm][1] = -c.y; av[mm][2] = c.z; av[mm][3] = -c.w;
         }
       }
+      // consecutive MFMAs update different accumulators (no back-to-back
+      // dependence on one accumulator); tiles past nM hold zero A fragments
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int mm = 0; mm < MT; ++mm)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const float bv = u == 0 ? cb[n].x : (u == 1 ? cb[n].y : (u == 2 ? cb[n].z : cb[n].w));
+            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mm][u], bv, acc[mm][n], 0, 0, 0);
+          }
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) ca[mm] = na[mm];
 #pragma unroll
       for (int n = 0; n < NT; ++n) cb[n] = nb[n];
     }
   }
-  // lane holds real rows 4*kr .. 4*kr+3 of each M-tile = complex rows 2kr, 2kr+1
+  // lane holds real rows 4*kr .. 4*kr+3 of each M-tile = complex rows 2kr, 2kr+1;
+  // tiles between the group's M_g and the vector stride M are written as zeros
+  const int nMall = M / 8;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int col = n * 16 + j;
@@ -292,9 +308,10 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, i
 #pragma unroll
     for (int mm = 0; mm < MT; ++mm) {
       const int m = wave + 4 * (slice + nslice * mm);
-      if (m < nM) {
+      if (m < nMall) {
         v4f a = acc[mm][n];
-        reinterpret_cast<float4*>(y + 8 * m + 2 * kr)[0] = make_float4(a[0], a[1], a[2], a[3]);
+        const float4 o = m < nM ? make_float4(a[0], a[1], a[2], a[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        reinterpret_cast<float4*>(y + 8 * m + 2 * kr)[0] = o;
       }
     }
   }
@@ -478,6 +495,7 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
   const GGemm* G = nullptr;
   int nt = 4;          // 16-column tiles per workgroup
   int slices = 1;      // M-slices (grid y)
+  bool alds = false;   // operator slice staged in LDS
   int64_t nchunks = 0;
   DevBuf grp, col0;
 };
@@ -492,48 +510,66 @@ struct ApplyState {
 
 void destroy_apply_state(ApplyState* s) { delete s; }
 
-static void prepare(Launch& L, const GGemm& G, int nrhs) {
+// Chunks and grid for one (tile width, M-slices) choice.
+static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices) {
   L.G = &G;
-  // narrow tiles when the average group holds few columns
-  double avg = G.ngroups ? double(G.nvec) * nrhs / double(G.ngroups) : 0.0;
-  L.nt = avg < 40.0 ? 2 : 4;
+  L.nt = nt;
+  L.alds = false;
   std::vector<int32_t> grp, col0;
   make_chunks(G, nrhs, L.nt * 16, grp, col0);
   L.nchunks = int64_t(grp.size());
-  // few chunks: split the M-tiles over more workgroups (at least ~4 per CU)
-  int nM = G.M / 8;
-  int max_slices = std::max(1, (nM + 3) / 4);
-  L.slices = 1;
-  while (L.slices < max_slices && L.nchunks * L.slices < 1024) ++L.slices;
+  L.slices = slices;
   L.grp.upload(grp);
   L.col0.upload(col0);
 }
 
+// Default choice: narrow tiles when the average group holds few columns; few
+// chunks: split the M-tiles over more workgroups (at least ~4 per CU).
+static void prepare(Launch& L, const GGemm& G, int nrhs) {
+  double avg = G.ngroups ? double(G.nvec) * nrhs / double(G.ngroups) : 0.0;
+  int nt = avg < 40.0 ? 2 : 4;
+  int64_t nchunks = 0;
+  for (int64_t g = 0; g < G.ngroups; ++g)
+    nchunks += (int64_t(G.v0_h[g + 1] - G.v0_h[g]) * nrhs + nt * 16 - 1) / (nt * 16);
+  int nM = G.M / 8;
+  int max_slices = std::max(1, (nM + 3) / 4);
+  int slices = 1;
+  while (slices < max_slices && nchunks * slices < 1024) ++slices;
+  prepare_cfg(L, G, nrhs, nt, slices);
+}
+
+static size_t gg_lds_bytes(int K, int nt) { return sizeof(float) * size_t(gg_stride(K)) * size_t(nt * 16); }
+static size_t gg_lds_total(int K, int nt, int mt, bool alds) {
+  return gg_lds_bytes(K, nt) + (alds ? size_t(2048) * mt * (K / 8) : 0);
+}
+
+template <int MT, int NT, bool ALDS>
+static void launch_mt_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  const GGemm& G = *L.G;
+  size_t lds = gg_lds_bytes(G.K, NT) + (ALDS ? size_t(2048) * MT * (G.K / 8) : 0);
+  static bool attr = false;
+  if (!attr) {
+    DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, NT, ALDS>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_ggemm<MT, NT, ALDS>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
+                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.T, G.ops.as<int>(),
+                     G.v0.as<int>(), G.vsrc.as<int>(),
+                     G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
+}
+
+template <int MT, int NT>
+static void launch_mt_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  if (L.alds) launch_mt_nt_a<MT, NT, true>(L, nrhs, X, Y, st);
+  else launch_mt_nt_a<MT, NT, false>(L, nrhs, X, Y, st);
+}
+
 template <int MT>
 static void launch_mt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
-  const GGemm& G = *L.G;
-  size_t lds = sizeof(float) * size_t(gg_stride(G.K)) * size_t(L.nt * 16);
-  if (L.nt == 4) {
-    static bool attr = false;
-    if (!attr) {
-      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, 4>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      attr = true;
-    }
-    hipLaunchKernelGGL((k_ggemm<MT, 4>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st, G.A.as<float4>(), G.M,
-                       G.K, G.T, G.ops.as<int>(), G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(),
-                       L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
-  } else {
-    static bool attr = false;
-    if (!attr) {
-      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, 2>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      attr = true;
-    }
-    hipLaunchKernelGGL((k_ggemm<MT, 2>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st, G.A.as<float4>(), G.M,
-                       G.K, G.T, G.ops.as<int>(), G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(),
-                       L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
-  }
+  if (L.nt == 4) launch_mt_nt<MT, 4>(L, nrhs, X, Y, st);
+  else if (L.nt == 2) launch_mt_nt<MT, 2>(L, nrhs, X, Y, st);
+  else launch_mt_nt<MT, 1>(L, nrhs, X, Y, st);
 }
 
 static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
@@ -542,7 +578,7 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
   int nM = G.M / 8;
   int per = 4 * L.slices;
   int mt = (nM + per - 1) / per;
-  if (size_t(gg_stride(G.K)) * size_t(L.nt * 16) * sizeof(float) > 160 * 1024 || mt > 8)
+  if (gg_lds_total(G.K, L.nt, mt, L.alds) > size_t(160 * 1024) || mt > 8)
     throw Error{DFMM_EUNSUPPORTED, "skeleton rank too large for the GEMM kernel"};
   switch (mt) {
     case 1: launch_mt<1>(L, nrhs, X, Y, st); break;
@@ -554,6 +590,49 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
     case 7: launch_mt<7>(L, nrhs, X, Y, st); break;
     default: launch_mt<8>(L, nrhs, X, Y, st); break;
   }
+}
+
+// Tile autotuner: time every (tile width, M-slices) candidate of one launch on
+// the apply stream (its output goes to the pair scratch Y only) and keep the
+// fastest.  Runs once per plan and nrhs.
+static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  prepare(L, G, nrhs);
+  if (G.ngroups == 0) return;
+  const char* env = std::getenv("DFMM_AUTOTUNE");
+  if (env && env[0] == '0') return;
+  int nM = G.M / 8;
+  int max_slices = std::max(1, (nM + 3) / 4);
+  hipEvent_t e0, e1;
+  DFMM_HIP(hipEventCreate(&e0));
+  DFMM_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_nt = L.nt, best_sl = L.slices;
+  bool best_alds = false;
+  for (int alds = 0; alds < 2; ++alds)
+  for (int nt : {1, 2, 4})
+    for (int sl = 1; sl <= std::min(max_slices, 4); ++sl) {
+      int mt = (nM + 4 * sl - 1) / (4 * sl);
+      if (mt > 8 || gg_lds_total(G.K, nt, mt, alds != 0) > size_t(160 * 1024)) continue;
+      prepare_cfg(L, G, nrhs, nt, sl);
+      L.alds = alds != 0;
+      launch_gemm(L, nrhs, X, Y, st);  // warm-up
+      DFMM_HIP(hipEventRecord(e0, st));
+      for (int i = 0; i < 3; ++i) launch_gemm(L, nrhs, X, Y, st);
+      DFMM_HIP(hipEventRecord(e1, st));
+      DFMM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      DFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_nt = nt;
+        best_sl = sl;
+        best_alds = alds != 0;
+      }
+    }
+  DFMM_HIP(hipEventDestroy(e0));
+  DFMM_HIP(hipEventDestroy(e1));
+  prepare_cfg(L, G, nrhs, best_nt, best_sl);
+  L.alds = best_alds;
 }
 
 static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
@@ -582,18 +661,27 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   S.m2m.resize(P.hf.size());
   S.l2l.resize(P.hf.size());
   S.m2l.resize(P.hf.size());
+}
+
+// Tune the GEMM launches of the current nrhs on the apply stream.
+static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, hipStream_t st) {
+  float2* Y = S.Y.as<float2>();
   for (size_t e = 0; e < P.hf.size(); ++e) {
-    prepare(S.m2m[e], P.hf[e].m2m, nrhs);
-    prepare(S.l2l[e], P.hf[e].l2l, nrhs);
-    prepare(S.m2l[e], P.hf[e].m2l, nrhs);
+    const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
+    autotune(S.m2m[e], P.hf[e].m2m, nrhs, Fc, Y, st);
+    autotune(S.l2l[e], P.hf[e].l2l, nrhs, S.U[e]->as<float2>(), Y, st);
+    autotune(S.m2l[e], P.hf[e].m2l, nrhs, S.F[e]->as<float2>(), Y, st);
   }
-  prepare(S.lf_m2l, P.lf.m2l, nrhs);
+  autotune(S.lf_m2l, P.lf.m2l, nrhs, S.flf.as<float2>(), Y, st);
 }
 
 void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t st) {
   if (!P.ws) P.ws = new ApplyState();
   ApplyState& S = *P.ws;
-  ensure_workspace(P, nrhs, S);
+  if (S.nrhs != nrhs) {
+    ensure_workspace(P, nrhs, S);
+    tune_launches(P, nrhs, S, st);
+  }
   const float2* f = static_cast<const float2*>(fv);
   float2* u = static_cast<float2*>(uv);
   const int64_t N = P.N;

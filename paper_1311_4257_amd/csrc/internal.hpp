@@ -101,9 +101,11 @@ struct DevBuf {
 // complex matrix (M, K multiples of 8) stored in MFMA fragment order, see
 // pack_operator().
 struct GGemm {
-  int M = 0, K = 0, T = 1;
+  int M = 0, K = 0, T = 1;   // vector strides (rows of Y and of X vectors); per-group sizes <= these
   int64_t ngroups = 0, nvec = 0, nops = 0;
-  DevBuf A;                  // float4[nops][M K / 2]
+  DevBuf A;                  // operators in fragment order, op i at float4 offset aoff[i]
+  DevBuf aoff;               // int64[nops]
+  DevBuf gmk;                // int32[ngroups][2]: (M_g, K_g) of the group's operators, multiples of 8
   DevBuf ops;                // int32[ngroups][T]
   DevBuf v0;                 // int32[ngroups + 1]: vector range of each group
   DevBuf vsrc;               // int32[nvec][T]

@@ -311,13 +311,19 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<int32_t> vdst(vsrc.size());
     for (size_t i = 0; i < vdst.size(); ++i) vdst[i] = int32_t(i);
     std::vector<float> At(size_t(2) * R * R * ngroups, 0.0f);
+    std::vector<int32_t> gmk(size_t(2) * ngroups);
+    std::vector<int64_t> aoff(ngroups);
     parallel_for(ngroups, [&](int64_t gi) {
       const PairRec& r = pr[rep[gi]];
       const Skel* si = skin[r.din < 0 ? 0 : r.din];
       const Skel* so = skin[r.dout < 0 ? 0 : r.dout];
       double sx = double(std::get<0>(keys[gi])) * w, sy = double(std::get<1>(keys[gi])) * w,
              sz = double(std::get<2>(keys[gi])) * w;
-      std::vector<double> G(size_t(2) * so->r), T(size_t(2) * R * R, 0.0);
+      const int Mg = pad8(si->r), Kg = pad8(so->r);
+      gmk[2 * gi] = Mg;
+      gmk[2 * gi + 1] = Kg;
+      aoff[gi] = int64_t(gi) * R * R / 2;
+      std::vector<double> G(size_t(2) * so->r), T(size_t(2) * Mg * Kg, 0.0);
       for (int q = 0; q < si->r; ++q) {
         for (int p = 0; p < so->r; ++p)
           green64(si->b[3 * q] - (sx + so->b[3 * p]), si->b[3 * q + 1] - (sy + so->b[3 * p + 1]),
@@ -330,11 +336,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi2 * di;
             im += gr * di + gi2 * dr;
           }
-          T[2 * (size_t(q) * R + j)] = re;
-          T[2 * (size_t(q) * R + j) + 1] = im;
+          T[2 * (size_t(q) * Kg + j)] = re;
+          T[2 * (size_t(q) * Kg + j) + 1] = im;
         }
       }
-      pack_operator(T.data(), R, R, &At[size_t(2) * R * R * gi]);
+      pack_operator(T.data(), Mg, Kg, &At[size_t(2) * R * R * gi]);
     });
     G.M = R;
     G.K = R;
@@ -343,6 +349,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     G.nvec = int64_t(vsrc.size());
     G.nops = ngroups;
     G.A.upload(At);
+    G.aoff.upload(aoff);
+    G.gmk.upload(gmk);
     G.ops.upload(opsv);
     G.v0.upload(v0);
     G.v0_h = v0;
@@ -398,6 +406,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<char> dir_used(ndir, 0);
     for (auto& s : OS[l].list) dir_used[s.second] = 1;
     for (auto& s : IS[l].list) dir_used[s.second] = 1;
+    std::vector<int32_t> op_ms(size_t(ndir) * 8, 8), op_mc(size_t(ndir) * 8, 8);  // padded ranks per op
     double wc = double(w) / 2.0;
     parallel_for(int64_t(ndir) * 8, [&](int64_t id) {
       int d = int(id / 8), o = int(id % 8);
@@ -411,7 +420,10 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           green64(s.a[3 * p] - dx - c.b[3 * j], s.a[3 * p + 1] - dy - c.b[3 * j + 1],
                   s.a[3 * p + 2] - dz - c.b[3 * j + 2], &G[2 * (size_t(p) * c.r + j)],
                   &G[2 * (size_t(p) * c.r + j) + 1]);
-      std::vector<double> up(size_t(2) * H.R * H.Rc, 0.0), dn(size_t(2) * H.Rc * H.R, 0.0);
+      const int Ms = pad8(s.r), Mc = pad8(c.r);
+      op_ms[id] = Ms;
+      op_mc[id] = Mc;
+      std::vector<double> up(size_t(2) * Ms * Mc, 0.0), dn(size_t(2) * Mc * Ms, 0.0);
       for (int p = 0; p < s.r; ++p)
         for (int k = 0; k < c.r; ++k) {  // (G D^c)[p][k]
           double re = 0.0, im = 0.0;
@@ -421,8 +433,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          up[2 * (size_t(p) * H.Rc + k)] = re;
-          up[2 * (size_t(p) * H.Rc + k) + 1] = im;
+          up[2 * (size_t(p) * Mc + k)] = re;
+          up[2 * (size_t(p) * Mc + k) + 1] = im;
         }
       for (int j = 0; j < c.r; ++j)
         for (int q = 0; q < s.r; ++q) {  // (G^T D^T)[j][q] = sum_p G[p][j] D[q][p]
@@ -433,24 +445,29 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          dn[2 * (size_t(j) * H.R + q)] = re;
-          dn[2 * (size_t(j) * H.R + q) + 1] = im;
+          dn[2 * (size_t(j) * Ms + q)] = re;
+          dn[2 * (size_t(j) * Ms + q) + 1] = im;
         }
-      pack_operator(up.data(), H.R, H.Rc, &Mu[size_t(2) * id * H.R * H.Rc]);
-      pack_operator(dn.data(), H.Rc, H.R, &Md[size_t(2) * id * H.R * H.Rc]);
+      pack_operator(up.data(), Ms, Mc, &Mu[size_t(2) * id * H.R * H.Rc]);
+      pack_operator(dn.data(), Mc, Ms, &Md[size_t(2) * id * H.R * H.Rc]);
     });
 
     // HF-M2M and HF-L2L as pair lists: one pair per (parent slot, child), grouped
     // by the (wedge, octant) operator it uses; the GEMM writes one output per
     // pair and a reduction sums the pairs of each destination slot.
     auto finish_pairs = [&](GGemm& G, std::vector<std::vector<std::pair<int32_t, int32_t>>>& by_op, int M,
-                            int K, int64_t nops, int64_t ndst, DevBuf& rs, DevBuf& ri, int64_t& npairs) {
+                            int K, int64_t nops, int64_t ndst, DevBuf& rs, DevBuf& ri, int64_t& npairs,
+                            const std::vector<int32_t>& opM, const std::vector<int32_t>& opK) {
       // by_op[op] = list of (source vector, destination slot)
-      std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv;
+      std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv, gmk;
+      std::vector<int64_t> aoff(nops);
+      for (int64_t op = 0; op < nops; ++op) aoff[op] = op * int64_t(M) * K / 2;
       std::vector<std::vector<int32_t>> per(ndst);
       for (int64_t op = 0; op < int64_t(by_op.size()); ++op) {
         if (by_op[op].empty()) continue;
         opsv.push_back(int32_t(op));
+        gmk.push_back(opM[op]);
+        gmk.push_back(opK[op]);
         for (auto& sd : by_op[op]) {
           per[sd.second].push_back(int32_t(vsrc.size()));
           vsrc.push_back(sd.first);
@@ -469,6 +486,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       G.ngroups = int64_t(v0.size()) - 1;
       G.nvec = int64_t(vsrc.size());
       G.nops = nops;
+      G.aoff.upload(aoff);
+      G.gmk.upload(gmk);
       G.ops.upload(opsv);
       G.v0.upload(v0);
       G.v0_h = v0;
@@ -488,7 +507,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
         }
       }
       H.m2m.A.upload(Mu);
-      finish_pairs(H.m2m, by_op, H.R, H.Rc, int64_t(ndir) * 8, H.nout, H.m2m_rs, H.m2m_ri, H.m2m_npairs);
+      finish_pairs(H.m2m, by_op, H.R, H.Rc, int64_t(ndir) * 8, H.nout, H.m2m_rs, H.m2m_ri, H.m2m_npairs, op_ms,
+                   op_mc);
     }
     {
       std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op(size_t(ndir) * 8);
@@ -518,7 +538,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
         }
       }
       H.l2l.A.upload(Md);
-      finish_pairs(H.l2l, by_op, H.Rc, H.R, int64_t(ndir) * 8, H.nchild_in, H.l2l_rs, H.l2l_ri, H.l2l_npairs);
+      finish_pairs(H.l2l, by_op, H.Rc, H.R, int64_t(ndir) * 8, H.nchild_in, H.l2l_rs, H.l2l_ri, H.l2l_npairs,
+                   op_mc, op_ms);
     }
     // M2L
     std::vector<const Skel*> sp;
