@@ -11,13 +11,25 @@ the float64 direct sum on 2,048 sampled targets is <= eps (reported as
 ``rel_l2_err``).  The roofline entry is for the dominant kernel, the grouped
 M2L GEMM (HF and LF launches): algorithmic flops 8 r_in r_out per (pair, rhs)
 divided by the launch time measured with HIP events on the apply stream over
-the timed steps, against the FP32 matrix peak of MI355X (157.3 TFLOP/s).
+a second run of the same number of steps (the events cost a little time, so
+``value`` comes from the event-free run), against the FP32 matrix peak of
+MI355X (157.3 TFLOP/s), or against 8 TB/s when the algorithmic bytes make
+HBM the lower ceiling.
 The CPU baseline times the float64 oracle pass on a bounded sample of the
 same geometry.
+
+``--calib-copy`` adds, after the timed steps, one 256 MiB device-to-device
+copy: the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters.
+``--traffic-summary FETCH_DIR WRITE_DIR`` turns the CSV
+output of the two counter runs into the traffic record that later runs report
+(while the GEMM sources are unchanged).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -27,7 +39,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 CACHE_DIR = os.path.join(ROOT, ".dfmm_cache")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_traffic_sphere16.json")
+# the M2L launch is defined by the tile engine and the operator layout built at plan time
+GEMM_SOURCES = ["paper_1311_4257_amd/csrc/apply.hip", "paper_1311_4257_amd/csrc/plan.cpp"]
+CALIB_BYTES = 256 << 20
+
+
+def gemm_source_hash() -> str:
+    h = hashlib.sha1()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter_rows(d: str):
+    """Rows (dispatch id, kernel name, counter, value) of a rocprofv3 counter-collection CSV."""
+    files = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    rows = []
+    with open(files[0], newline="") as fh:
+        for r in csv.DictReader(fh):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
+    """Per-launch HBM bytes of the M2L launches of one apply, scaled by the copy calibration.
+
+    Both counter runs execute the same command; the M2L launches taken are those
+    after the last permute-in launch (the final apply), and the calibration is
+    the largest device-to-device copy (CALIB_BYTES read and written)."""
+    out = {"source_sha1": gemm_source_hash(), "calib_bytes": CALIB_BYTES}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = [r for r in _counter_rows(d) if r[2] == counter]
+        per = {}
+        for disp, name, _, val in rows:
+            per.setdefault(disp, [name, 0.0])[1] += val
+        disp_sorted = sorted(per.items())
+        last_perm = max(i for i, (_, (n, _)) in enumerate(disp_sorted) if "k_permute_in" in n)
+        m2l = [v for _, (n, v) in disp_sorted[last_perm:] if "k_m2l" in n]
+        copies = [v for _, (n, v) in disp_sorted if "copyBuffer" in n]
+        if not m2l or not copies:
+            raise SystemExit(f"{counter}: no M2L launch or no calibration copy found in {d}")
+        calib_kib = max(copies)
+        factor = (CALIB_BYTES / 1024.0) / calib_kib
+        out[key] = {"counter": counter, "m2l_kib": m2l, "calib_kib": calib_kib, "factor": factor,
+                    "bytes_per_launch": factor * 1024.0 * sum(m2l) / len(m2l)}
+    out["launches"] = len(out["fetch"]["m2l_kib"])
+    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    return out
 
 
 def cpu_baseline(pts, f, K, eps_tau, n_sample=16384):
@@ -68,7 +132,16 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.traffic_summary:
+        rec = traffic_summary(*args.traffic_summary)
+        os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -91,15 +164,29 @@ def main() -> int:
     for _ in range(args.warmup):
         plan.apply(fd, u, stream)
     torch.cuda.synchronize()
-    plan.set_timing(args.steps)
-    torch.cuda.synchronize()
+    # the timed steps: nothing but the applies on the stream
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.apply(fd, u, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same number of steps again with the stage events (timing-only HIP
+    # events recorded on the apply stream between launches): per-kernel durations
+    plan.set_timing(args.steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(fd, u, stream)
+    torch.cuda.synchronize()
+    ms_events = (time.perf_counter() - t2) * 1e3 / args.steps
     stages = plan.stage_times()
     plan.set_timing(0)
+    if args.calib_copy:  # counter calibration: one plain copy of known size
+        src = torch.empty(CALIB_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ms = (t1 - t0) * 1e3 / args.steps
 
     # accuracy gate against the float64 direct sum
@@ -110,8 +197,22 @@ def main() -> int:
 
     m2l_ms = stages["hf_m2l"][0] + stages["lf_m2l"][0]
     m2l_launches = stages["hf_m2l"][1] + stages["lf_m2l"][1]
+    per_apply = m2l_launches / max(1, args.steps)
     flops_apply = (info.flops_m2l_hf + info.flops_m2l_lf) * nrhs
-    achieved = flops_apply * args.steps / (m2l_ms * 1e-3) / 1e12 if m2l_ms > 0 else 0.0
+    bytes_apply = info.bytes_m2l_op + info.bytes_m2l_vec * nrhs
+    sec = m2l_ms * 1e-3 / args.steps  # M2L launch time per apply
+    # the bound is whichever ceiling is lower for these flops and bytes
+    mfma_bound = flops_apply / (PEAK_FP32_MATRIX_TFLOPS * 1e12) >= bytes_apply / (PEAK_HBM_GBS * 1e9)
+    if mfma_bound:
+        achieved, peak, unit = flops_apply / sec / 1e12, PEAK_FP32_MATRIX_TFLOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = bytes_apply / sec / 1e9, PEAK_HBM_GBS, "GB/s"
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+        if rec.get("source_sha1") == gemm_source_hash() and nrhs == 1:
+            traffic = rec["bytes_per_launch"]
     per_stage = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]}
 
     out = {
@@ -134,16 +235,19 @@ def main() -> int:
         "rel_l2_err": err,
         "accuracy_ok": bool(err <= eps),
         "stage_ms": per_stage,
+        "ms_per_step_with_stage_events": ms_events,
         "roofline": {
-            "bound": "mfma",
-            "kernel": "k_ggemm (grouped M2L, HF + LF launches)",
+            "bound": "mfma" if mfma_bound else "hbm",
+            "kernel": "k_m2l (grouped M2L GEMM, HF + LF launches)",
             "achieved": achieved,
-            "peak": PEAK_FP32_MATRIX_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MATRIX_TFLOPS,
-            "traffic": None,
-            "flops_per_apply": flops_apply,
-            "launches_per_apply": m2l_launches / max(1, args.steps),
+            "peak": peak,
+            "unit": unit,
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "launches_per_apply": per_apply,
+            "avg_launch_us": sec / max(1.0, per_apply) * 1e6,
+            "flops_per_launch": flops_apply / max(1.0, per_apply),
+            "alg_bytes_per_launch": bytes_apply / max(1.0, per_apply),
         },
         "plan_seconds": info.plan_seconds,
     }

@@ -92,7 +92,9 @@ typedef struct {
   double eps;             /* end-to-end relative L2 target; selects tau when opset is null */
   dfmm_opset_t opset;     /* skeletons to use (borrowed; must outlive the plan's creation
                              call only -- the plan copies what it needs); null = build */
-  const char* cache_dir;  /* operator-set cache directory for the build (may be null) */
+  const char* cache_dir;  /* cache directory (may be null; DFMM_CACHE_DIR is used then): operator
+                             sets, and the GEMM launch choices the first apply of each nrhs
+                             measures (dfmm_tune_*.txt, keyed by launch shapes, nrhs, device) */
   int device;             /* HIP device ordinal; -1 = current device */
   int reserved[7];
 } dfmm_options;
@@ -113,9 +115,12 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * data (interleaved float re, im), layout [nrhs][N], in the caller's original
  * point order; u is overwritten; f and u must not overlap.  Work is enqueued
  * on `stream` (a hipStream_t; null = the null stream) and the call returns
- * without waiting.  The plan owns a workspace sized for the largest nrhs seen
- * so far; a larger nrhs grows it (a synchronous allocation).  Applies on one
- * plan must not run concurrently. */
+ * without waiting.  The first apply with a new nrhs sizes the plan's workspace
+ * for it (synchronous allocation) and fixes the GEMM launch shapes: from the
+ * tuning record in the cache directory if one matches, else by timing the
+ * candidate shapes on `stream` (waits for them; DFMM_AUTOTUNE=0 takes the
+ * default shapes instead).  Later applies with the same nrhs allocate nothing
+ * and do not wait.  Applies on one plan must not run concurrently. */
 int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
 
 void dfmm_destroy(dfmm_plan_t plan);
@@ -142,6 +147,8 @@ typedef struct {
   double flops_m2l_lf;    /* 8 r r summed over leaf-level pairs, per right-hand side */
   double plan_seconds;
   int64_t device_bytes;   /* device memory held by the plan (without the apply workspace) */
+  double bytes_m2l_op;    /* M2L operators (complex64, unpadded r_in x r_out), once per offset group */
+  double bytes_m2l_vec;   /* M2L source reads + output writes, 8 (r_in + r_out) per pair, per right-hand side */
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);

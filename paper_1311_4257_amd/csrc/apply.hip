@@ -11,8 +11,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "internal.hpp"
 
@@ -187,18 +189,18 @@ __host__ __device__ inline int gg_stride(int K) {
 }
 
 template <int MT, int NT, bool ALDS>  // ALDS: stage the operator slice in LDS first
-__global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
-                                                  const int* __restrict__ gmk, int M, int K, int T,
-                                                  const int* __restrict__ gops, const int* __restrict__ gv0,
-                                                  const int* __restrict__ vsrc, const int* __restrict__ vdst,
-                                                  const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
-                                                  int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
+__device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
+                                           const int* __restrict__ gmk, int M, int K, int T,
+                                           const int* __restrict__ gops, const int* __restrict__ gv0,
+                                           const int* __restrict__ vsrc, const int* __restrict__ vdst,
+                                           const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
+                                           int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
   const int S = gg_stride(K);           // floats per LDS column (K = the largest K_g)
   const int S4 = S / 4;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, kr = lane >> 4;
   const int slice = blockIdx.y, nslice = gridDim.y;
   const int g = chunk_grp[blockIdx.x];
@@ -209,6 +211,13 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, c
   const int vbeg = gv0[g];
   const int64_t ncol = int64_t(gv0[g + 1] - vbeg) * nrhs;
   const int nc = int(min<int64_t>(NC, ncol - c0));
+  // this wave's M-tiles that hold rows of the group (a prefix of mm) and the
+  // column tiles that hold columns: MFMAs on empty tiles are skipped
+  int mcnt = 0;
+#pragma unroll
+  for (int mm = 0; mm < MT; ++mm)
+    if (wave + 4 * (slice + nslice * mm) < nM) mcnt = mm + 1;
+  const int ncnt = (nc + 15) / 16;
 
   v4f acc[MT][NT];
 #pragma unroll
@@ -278,16 +287,19 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, c
         }
       }
       // consecutive MFMAs update different accumulators (no back-to-back
-      // dependence on one accumulator); tiles past nM hold zero A fragments
+      // dependence on one accumulator)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int mm = 0; mm < MT; ++mm)
+        for (int mm = 0; mm < MT; ++mm) {
+          if (mm >= mcnt) continue;
 #pragma unroll
           for (int n = 0; n < NT; ++n) {
+            if (n >= ncnt) continue;
             const float bv = u == 0 ? cb[n].x : (u == 1 ? cb[n].y : (u == 2 ? cb[n].z : cb[n].w));
             acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mm][u], bv, acc[mm][n], 0, 0, 0);
           }
+        }
 #pragma unroll
       for (int mm = 0; mm < MT; ++mm) ca[mm] = na[mm];
 #pragma unroll
@@ -316,6 +328,26 @@ __global__ void __launch_bounds__(GG_BS) k_ggemm(const float4* __restrict__ A, c
     }
   }
 }
+
+#define DFMM_GG_PARAMS                                                                                       \
+  const float4 *__restrict__ A, const int64_t *__restrict__ aoff, const int *__restrict__ gmk, int M, int K,  \
+      int T, const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,          \
+      const int *__restrict__ vdst, const int *__restrict__ chunk_grp, const int *__restrict__ chunk_c0,       \
+      int nrhs, const float2 *__restrict__ X, float2 *__restrict__ Y
+#define DFMM_GG_ARGS A, aoff, gmk, M, K, T, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
+
+// The same tile engine under two names, so that kernel traces separate the
+// translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
+template <int MT, int NT, bool ALDS>
+__global__ void __launch_bounds__(GG_BS) k_m2l(DFMM_GG_PARAMS) {
+  ggemm_tile<MT, NT, ALDS>(DFMM_GG_ARGS);
+}
+template <int MT, int NT, bool ALDS>
+__global__ void __launch_bounds__(GG_BS) k_transfer(DFMM_GG_PARAMS) {
+  ggemm_tile<MT, NT, ALDS>(DFMM_GG_ARGS);
+}
+#undef DFMM_GG_PARAMS
+#undef DFMM_GG_ARGS
 
 // ---- U[slot] (+)= sum of Y over the pairs of the slot -------------------------------
 __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri, const float2* __restrict__ Y,
@@ -496,6 +528,7 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
   int nt = 4;          // 16-column tiles per workgroup
   int slices = 1;      // M-slices (grid y)
   bool alds = false;   // operator slice staged in LDS
+  bool m2l = false;    // translation launch (kernel name k_m2l) or tree transfer (k_transfer)
   int64_t nchunks = 0;
   DevBuf grp, col0;
 };
@@ -510,6 +543,27 @@ struct ApplyState {
 
 void destroy_apply_state(ApplyState* s) { delete s; }
 
+// The hardware hands workgroups to the 8 XCDs round-robin by linear workgroup
+// id, and each XCD has its own L2.  Chunks of one group read the same operator,
+// so the chunk table is laid out such that the workgroups that land on one XCD
+// take a contiguous range of chunks (a group's chunks share that XCD's L2).
+constexpr int kXcds = 8;
+static void xcd_order(std::vector<int32_t>& grp, std::vector<int32_t>& col0) {
+  const int64_t n = int64_t(grp.size());
+  if (n <= kXcds) return;
+  int64_t start[kXcds + 1];
+  start[0] = 0;
+  for (int x = 0; x < kXcds; ++x) start[x + 1] = start[x] + (n - x + kXcds - 1) / kXcds;  // ids b = x mod 8
+  std::vector<int32_t> g2(n), c2(n);
+  for (int64_t b = 0; b < n; ++b) {
+    const int64_t l = start[b % kXcds] + b / kXcds;
+    g2[b] = grp[l];
+    c2[b] = col0[l];
+  }
+  grp.swap(g2);
+  col0.swap(c2);
+}
+
 // Chunks and grid for one (tile width, M-slices) choice.
 static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices) {
   L.G = &G;
@@ -517,6 +571,7 @@ static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices)
   L.alds = false;
   std::vector<int32_t> grp, col0;
   make_chunks(G, nrhs, L.nt * 16, grp, col0);
+  xcd_order(grp, col0);
   L.nchunks = int64_t(grp.size());
   L.slices = slices;
   L.grp.upload(grp);
@@ -547,13 +602,15 @@ template <int MT, int NT, bool ALDS>
 static void launch_mt_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
   size_t lds = gg_lds_bytes(G.K, NT) + (ALDS ? size_t(2048) * MT * (G.K / 8) : 0);
+  auto kern = L.m2l ? &k_m2l<MT, NT, ALDS> : &k_transfer<MT, NT, ALDS>;
   static bool attr = false;
   if (!attr) {
-    DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ggemm<MT, NT, ALDS>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    for (auto k : {&k_m2l<MT, NT, ALDS>, &k_transfer<MT, NT, ALDS>})
+      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
     attr = true;
   }
-  hipLaunchKernelGGL((k_ggemm<MT, NT, ALDS>), dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
+  hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
                      G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.T, G.ops.as<int>(),
                      G.v0.as<int>(), G.vsrc.as<int>(),
                      G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
@@ -663,16 +720,92 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   S.m2l.resize(P.hf.size());
 }
 
+// ---- tuning record: the chosen (tile width, M-slices, LDS operator) per launch,
+// kept in the plan's cache directory under a key of the launch shapes, nrhs and
+// the device, so that later plans of the same shape skip the trial launches.
+static void fnv(uint64_t& h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+}
+
+static std::string tune_path(const dfmm_plan_s& P, const std::vector<const GGemm*>& gs, int nrhs) {
+  if (P.tune_dir.empty()) return std::string();
+  uint64_t h = 1469598103934665603ull;
+  hipDeviceProp_t prop;
+  DFMM_HIP(hipGetDeviceProperties(&prop, P.device));
+  fnv(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+  fnv(h, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+  fnv(h, &nrhs, sizeof(nrhs));
+  for (const GGemm* g : gs) {
+    const int64_t dims[5] = {g->M, g->K, g->T, g->ngroups, g->nvec};
+    fnv(h, dims, sizeof(dims));
+    fnv(h, g->v0_h.data(), g->v0_h.size() * sizeof(int32_t));
+  }
+  char name[64];
+  std::snprintf(name, sizeof(name), "/dfmm_tune_%016llx.txt", static_cast<unsigned long long>(h));
+  return P.tune_dir + name;
+}
+
+static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const std::vector<const GGemm*>& gs,
+                        int nrhs) {
+  if (path.empty()) return false;
+  FILE* fp = std::fopen(path.c_str(), "r");
+  if (!fp) return false;
+  int n = 0;
+  bool ok = std::fscanf(fp, "dfmm-tune 1 %d", &n) == 1 && n == int(ls.size());
+  std::vector<int> v(3 * size_t(n));
+  for (int i = 0; ok && i < n; ++i) {
+    ok = std::fscanf(fp, "%d %d %d", &v[3 * i], &v[3 * i + 1], &v[3 * i + 2]) == 3;
+    const int nt = v[3 * i], sl = v[3 * i + 1];
+    ok = ok && (nt == 1 || nt == 2 || nt == 4) && sl >= 1 && sl <= 64;
+  }
+  std::fclose(fp);
+  if (!ok) return false;
+  for (int i = 0; i < n; ++i) {
+    prepare_cfg(*ls[i], *gs[i], nrhs, v[3 * i], v[3 * i + 1]);
+    ls[i]->alds = v[3 * i + 2] != 0;
+    const int nM = gs[i]->M / 8, mt = (nM + 4 * ls[i]->slices - 1) / (4 * ls[i]->slices);
+    if (mt > 8 || gg_lds_total(gs[i]->K, ls[i]->nt, mt, ls[i]->alds) > size_t(160 * 1024)) return false;
+  }
+  return true;
+}
+
+static void save_tuning(const std::string& path, const std::vector<Launch*>& ls) {
+  if (path.empty()) return;
+  const std::string tmp = path + ".tmp";
+  FILE* fp = std::fopen(tmp.c_str(), "w");
+  if (!fp) return;  // the record is an optimisation only
+  std::fprintf(fp, "dfmm-tune 1 %d\n", int(ls.size()));
+  for (const Launch* L : ls) std::fprintf(fp, "%d %d %d\n", L->nt, L->slices, L->alds ? 1 : 0);
+  const bool ok = std::fclose(fp) == 0;
+  if (ok) std::rename(tmp.c_str(), path.c_str());
+}
+
 // Tune the GEMM launches of the current nrhs on the apply stream.
 static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, hipStream_t st) {
   float2* Y = S.Y.as<float2>();
+  std::vector<Launch*> ls;
+  std::vector<const GGemm*> gs;
+  std::vector<const float2*> xs;
   for (size_t e = 0; e < P.hf.size(); ++e) {
     const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
-    autotune(S.m2m[e], P.hf[e].m2m, nrhs, Fc, Y, st);
-    autotune(S.l2l[e], P.hf[e].l2l, nrhs, S.U[e]->as<float2>(), Y, st);
-    autotune(S.m2l[e], P.hf[e].m2l, nrhs, S.F[e]->as<float2>(), Y, st);
+    ls.insert(ls.end(), {&S.m2m[e], &S.l2l[e], &S.m2l[e]});
+    gs.insert(gs.end(), {&P.hf[e].m2m, &P.hf[e].l2l, &P.hf[e].m2l});
+    xs.insert(xs.end(), {Fc, S.U[e]->as<float2>(), S.F[e]->as<float2>()});
+    S.m2l[e].m2l = true;
   }
-  autotune(S.lf_m2l, P.lf.m2l, nrhs, S.flf.as<float2>(), Y, st);
+  ls.push_back(&S.lf_m2l);
+  gs.push_back(&P.lf.m2l);
+  xs.push_back(S.flf.as<float2>());
+  S.lf_m2l.m2l = true;
+  const std::string path = tune_path(P, gs, nrhs);
+  if (load_tuning(path, ls, gs, nrhs)) return;
+  for (size_t i = 0; i < ls.size(); ++i) autotune(*ls[i], *gs[i], nrhs, xs[i], Y, st);
+  const char* env = std::getenv("DFMM_AUTOTUNE");
+  if (!(env && env[0] == '0')) save_tuning(path, ls);
 }
 
 void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t st) {
@@ -805,6 +938,8 @@ void StageTimer::collect(double* ms, int64_t* launches) {
     launches[i] = 0;
   }
   if (used == 0) return;
+  // the events carry no system-scope fence: wait for the device, then read them
+  DFMM_HIP(hipDeviceSynchronize());
   DFMM_HIP(hipEventSynchronize(pool[used - 1]));
   for (size_t i = 1; i < used; ++i) {
     if (tags[i] < 0) continue;  // first event of an apply
@@ -820,7 +955,9 @@ void StageTimer::collect(double* ms, int64_t* launches) {
 
 StageTimer::StageTimer(int applies) {
   pool.resize(size_t(applies) * kPerApply);
-  for (auto& e : pool) DFMM_HIP(hipEventCreate(&e));
+  // timing-only events: without the system-scope release fence, recording one
+  // does not write back the L2 between the launches it separates
+  for (auto& e : pool) DFMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
 }
 
 StageTimer::~StageTimer() {

@@ -202,6 +202,7 @@ struct dfmm_plan_s {
   int w_top = 0;
   bool precise = false;  // eps < 1e-5: float64 distances in the near field
   double plan_seconds = 0.0;
+  std::string tune_dir;  // where GEMM launch choices are kept (empty: not kept)
   dfmm_info info{};
   // host copies of structures for export
   std::vector<int64_t> perm;

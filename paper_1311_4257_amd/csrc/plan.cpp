@@ -278,6 +278,10 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   auto build_m2l = [&](const std::vector<PairRec>& pr, double w, int R,
                        const std::vector<const Skel*>& skin, const SlotIndex* osl, const SlotIndex* isl,
                        int64_t nin, GGemm& G, DevBuf& rs, DevBuf& ri, int64_t& ngroups, double& flops) {
+    // algorithmic bytes of the launch: each group's operator once (complex64,
+    // unpadded), each pair's source vector read and its output written once
+    double& bytes_op = info.bytes_m2l_op;
+    double& bytes_vec = info.bytes_m2l_vec;
     std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<int64_t>> g;
     for (size_t i = 0; i < pr.size(); ++i) g[{pr[i].nx, pr[i].ny, pr[i].nz}].push_back(int64_t(i));
     ngroups = int64_t(g.size());
@@ -288,12 +292,17 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     for (auto& kv : g) {
       keys.push_back(kv.first);
       rep.push_back(kv.second.front());
+      {
+        const PairRec& r0 = pr[kv.second.front()];
+        bytes_op += 8.0 * skin[r0.din < 0 ? 0 : r0.din]->r * skin[r0.dout < 0 ? 0 : r0.dout]->r;
+      }
       opsv.push_back(int32_t(keys.size() - 1));
       for (int64_t i : kv.second) {
         const PairRec& r = pr[i];
         pos_of[i] = int32_t(vsrc.size());
         vsrc.push_back(int32_t(osl ? osl->at(r.A, r.dout) : r.A));
         flops += 8.0 * skin[r.din < 0 ? 0 : r.din]->r * skin[r.dout < 0 ? 0 : r.dout]->r;
+        bytes_vec += 8.0 * (skin[r.din < 0 ? 0 : r.din]->r + skin[r.dout < 0 ? 0 : r.dout]->r);
       }
       v0.push_back(int32_t(vsrc.size()));
     }

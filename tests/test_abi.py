@@ -97,3 +97,31 @@ def test_opset_roundtrip_and_injection(tmp_path):
             for x, y in zip(s.get(w, d), t.get(w, d)):
                 assert np.array_equal(x, y)
     assert t.info() == (1e-3, 1)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of dfmm_options and dfmm_info have the C layout (gcc on the header)."""
+    import shutil
+    import subprocess
+
+    from paper_1311_4257_amd import dfmm
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"dfmm_options": dfmm.Options, "dfmm_info": dfmm.Info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dfmm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
