@@ -248,6 +248,8 @@ def main() -> int:
             "avg_launch_us": sec / max(1.0, per_apply) * 1e6,
             "flops_per_launch": flops_apply / max(1.0, per_apply),
             "alg_bytes_per_launch": bytes_apply / max(1.0, per_apply),
+            "flops_per_level": {f"w={info.K / 2 ** l:g}": info.flops_m2l_level[l] * nrhs
+                                for l in range(info.depth + 1) if info.flops_m2l_level[l] > 0},
         },
         "plan_seconds": info.plan_seconds,
     }

@@ -149,6 +149,7 @@ typedef struct {
   int64_t device_bytes;   /* device memory held by the plan (without the apply workspace) */
   double bytes_m2l_op;    /* M2L operators (complex64, unpadded r_in x r_out), once per offset group */
   double bytes_m2l_vec;   /* M2L source reads + output writes, 8 (r_in + r_out) per pair, per right-hand side */
+  double flops_m2l_level[32]; /* flops_m2l_hf / flops_m2l_lf split by level 0..D */
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);

@@ -168,18 +168,23 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
   }
 }
 
-// ---- grouped gather GEMM on MFMA: Y[vdst] = sum_t A[op_t] X[vsrc_t] --------------
+// ---- grouped gather GEMM on MFMA: Y[vdst] = A[op] X[vsrc] ------------------------
 // The complex product y = A x is done as a real product on interleaved data:
 // real row 2q (re) of A is (Re A[q][p], -Im A[q][p]) per column pair (2p, 2p+1)
 // and row 2q+1 (im) is (Im, Re); x and y stay in their natural interleaved
-// layout.  One workgroup (4 waves) computes all 2M real rows of NT*16 vector
-// columns; wave w owns the 16-row M-tiles w, w+4, ... of its M-slice
-// (blockIdx.y of gridDim.y slices: tile m belongs to slice (m / 4) % slices,
-// which adds workgroups when a launch has few column chunks).  The K dimension is
-// split into four quarters, one per group of 16 lanes (MFMA k index), so a
-// lane reads four consecutive k values of its quarter with one 16-byte load
-// from LDS (B) and from the fragment-ordered operator (A).  The column block
-// of each term sits in LDS, [column][k] with a row stride S = 4 (mod 32) floats.
+// layout.  One workgroup (4 waves) handles NT*16 vector columns of one group
+// (one operator).  The 16-row M-tiles m of the group go to the waves as
+// m = wave + 4 (slice + slices t), t = 0, 1, ... (slice = blockIdx.y), and each
+// wave walks its tiles one after the other, so a group's own M_g sets the work
+// and no MFMA runs on an empty tile.  The K dimension of a tile is split into
+// four quarters, one per group of 16 lanes (MFMA k index): a lane reads four
+// consecutive k values of its quarter with one 16-byte load from LDS (B) and
+// from the fragment-ordered operator (A).  The column block sits in LDS,
+// [column][k] with a row stride S = 4 (mod 32) floats.  The (tile, k-step)
+// sequence of a wave is one flat loop; the operator fragments of the next GG_PD
+// steps are in flight in a register ring, and their loads are issued on every
+// step (past the end they repeat the last address) so that each wait is for
+// the oldest load only.
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int GG_BS = 256;
 
@@ -188,163 +193,221 @@ __host__ __device__ inline int gg_stride(int K) {
   return s + ((4 - (s % 32)) + 32) % 32;
 }
 
-template <int MT, int NT, bool ALDS>  // ALDS: stage the operator slice in LDS first
+template <int NT>
+struct GgDepth {
+  static constexpr int value = NT == 1 ? 8 : (NT == 2 ? 6 : 4);
+};
+
+template <int NT, bool ALDS>  // ALDS: stage the workgroup's operator tiles in LDS first
 __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
-                                           const int* __restrict__ gmk, int M, int K, int T,
+                                           const int* __restrict__ gmk, int M, int K,
                                            const int* __restrict__ gops, const int* __restrict__ gv0,
                                            const int* __restrict__ vsrc, const int* __restrict__ vdst,
                                            const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
                                            int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
-  const int S = gg_stride(K);           // floats per LDS column (K = the largest K_g)
-  const int S4 = S / 4;
+  constexpr int PD = GgDepth<NT>::value;
+  static_assert(PD % 2 == 0, "the B ring pairs slots by parity");
+  const int S4 = gg_stride(K) / 4;      // float4 per LDS column (K = the largest K_g)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, kr = lane >> 4;
-  const int slice = blockIdx.y, nslice = gridDim.y;
+  const bool odd = (j & 1) != 0;
   const int g = chunk_grp[blockIdx.x];
   const int Mg = gmk[2 * g], Kg = gmk[2 * g + 1];  // this group's operator size
-  const int Q4 = Kg / 8;                 // float4 steps per K quarter (K_g/2 real k per quarter)
-  const int nM = Mg / 8;                 // 16-row real M-tiles with data
+  const int Q4 = Kg / 8;                 // k-steps per tile (K_g / 2 real k per quarter, 4 per step)
+  const int nM = Mg / 8, nMall = M / 8;  // 16-row real M-tiles with data / in the vector stride
+  const int m0 = wave + 4 * int(blockIdx.y), mstep = 4 * int(gridDim.y);
+  const int mcnt = m0 < nM ? (nM - m0 + mstep - 1) / mstep : 0;
   const int64_t c0 = chunk_c0[blockIdx.x];
   const int vbeg = gv0[g];
   const int64_t ncol = int64_t(gv0[g + 1] - vbeg) * nrhs;
   const int nc = int(min<int64_t>(NC, ncol - c0));
-  // this wave's M-tiles that hold rows of the group (a prefix of mm) and the
-  // column tiles that hold columns: MFMAs on empty tiles are skipped
-  int mcnt = 0;
-#pragma unroll
-  for (int mm = 0; mm < MT; ++mm)
-    if (wave + 4 * (slice + nslice * mm) < nM) mcnt = mm + 1;
-  const int ncnt = (nc + 15) / 16;
 
-  v4f acc[MT][NT];
-#pragma unroll
-  for (int mm = 0; mm < MT; ++mm)
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[mm][n] = v4f{0.f, 0.f, 0.f, 0.f};
-
-  for (int t = 0; t < T; ++t) {
-    const int op = gops[g * T + t];
-    if (op < 0) continue;
-    __syncthreads();
-    // stage the source vectors of this term: column c -> X[(src * nrhs + k) * K],
-    // its first K_g complex entries
-    const int per_col = Kg / 2;  // float4 per column
-    for (int idx = threadIdx.x; idx < NC * per_col; idx += GG_BS) {
-      int col = idx / per_col, q4 = idx % per_col;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (col < nc) {
-        int64_t cc = c0 + col;
-        int vv = vbeg + int(cc / nrhs);
-        int k = int(cc % nrhs);
-        int src = vsrc[int64_t(vv) * T + t];
-        if (src >= 0) v = reinterpret_cast<const float4*>(X + (int64_t(src) * nrhs + k) * K)[q4];
-      }
-      xs[col * S4 + q4] = v;
+  // stage the source vectors: column c -> X[(src * nrhs + k) * K], its first K_g
+  // complex entries.  The column sources go through a small LDS table (one
+  // division per column); each thread then walks its elements (q4 fastest, so
+  // a wave reads long contiguous runs) with incremental indices, issuing a
+  // batch of loads before storing them.
+  const int per_col = Kg / 2;  // float4 per column
+  const float4* Aop = A + aoff[gops[g]];
+  const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
+  float4* as = xs + NC * S4;  // ALDS: the tiles of this slice, [t][wave][tile4]
+  __shared__ const float4* colsrc[NC];
+  if (threadIdx.x < NC) {
+    const int col = threadIdx.x;
+    const float4* p = nullptr;
+    if (col < nc) {
+      const int64_t cc = c0 + col;
+      const int src = vsrc[vbeg + int(cc / nrhs)];
+      if (src >= 0) p = reinterpret_cast<const float4*>(X + (int64_t(src) * nrhs + int(cc % nrhs)) * K);
     }
-    const float4* Aop = A + aoff[op];
-    const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
-    float4* as = xs + NC * S4;  // operator slice (ALDS): 4 consecutive M-tiles per mm
-    if (ALDS) {
-      // one coalesced bulk copy of this workgroup's M-tiles (many loads in flight)
-      for (int idx = threadIdx.x; idx < MT * 4 * tile4; idx += GG_BS) {
-        const int blk = idx / tile4, off = idx % tile4;
-        const int m = (blk & 3) + 4 * (slice + nslice * (blk >> 2));
-        as[idx] = m < nM ? Aop[int64_t(m) * tile4 + off] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-    __syncthreads();
-    // register double buffering: the A and B fragments of step s4 + 1 are in
-    // flight while the MFMAs of step s4 run
-    auto afrag = [&](int mm, int step) -> float4 {
-      if (ALDS) return as[(mm * 4 + wave) * tile4 + (step * 8 + (j >> 1)) * 4 + kr];
-      const int m = wave + 4 * (slice + nslice * mm);
-      return m < nM ? Aop[((int64_t(m) * Q4 + step) * 8 + (j >> 1)) * 4 + kr] : make_float4(0.f, 0.f, 0.f, 0.f);
-    };
-    float4 ca[MT], cb[NT];
+    colsrc[col] = p;
+  }
+  __syncthreads();
+  {
+    constexpr int UB = 4;  // loads in flight per thread
+    const int nel = NC * per_col;
+    const int dcol = GG_BS / per_col, dq = GG_BS % per_col;
+    int col = int(threadIdx.x) / per_col, q4 = int(threadIdx.x) % per_col;
+    for (int base = int(threadIdx.x); base < nel; base += UB * GG_BS) {
+      float4 v[UB];
+      int dst[UB];
 #pragma unroll
-    for (int mm = 0; mm < MT; ++mm) ca[mm] = afrag(mm, 0);
-#pragma unroll
-    for (int n = 0; n < NT; ++n) cb[n] = xs[(n * 16 + j) * S4 + kr * Q4];
-    for (int s4 = 0; s4 < Q4; ++s4) {
-      const int sn = s4 + 1 < Q4 ? s4 + 1 : s4;
-      float4 na[MT], nb[NT];
-#pragma unroll
-      for (int mm = 0; mm < MT; ++mm) na[mm] = afrag(mm, sn);
-#pragma unroll
-      for (int n = 0; n < NT; ++n) nb[n] = xs[(n * 16 + j) * S4 + kr * Q4 + sn];
-      // expand the complex A fragments into the real rows (re: Re,-Im; im: Im,Re)
-      float av[MT][4];
-#pragma unroll
-      for (int mm = 0; mm < MT; ++mm) {
-        const float4 c = ca[mm];
-        if (j & 1) {
-          av[mm][0] = c.y; av[mm][1] = c.x; av[mm][2] = c.w; av[mm][3] = c.z;
-        } else {
-          av[mm][0] = c.x; av[mm][1] = -c.y; av[mm][2] = c.z; av[mm][3] = -c.w;
+      for (int u = 0; u < UB; ++u) {
+        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        dst[u] = -1;
+        if (base + u * GG_BS < nel) {
+          const float4* p = colsrc[col];
+          if (p) v[u] = p[q4];
+          dst[u] = col * S4 + q4;
+        }
+        col += dcol;
+        q4 += dq;
+        if (q4 >= per_col) {
+          q4 -= per_col;
+          ++col;
         }
       }
-      // consecutive MFMAs update different accumulators (no back-to-back
-      // dependence on one accumulator)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int mm = 0; mm < MT; ++mm) {
-          if (mm >= mcnt) continue;
-#pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            if (n >= ncnt) continue;
-            const float bv = u == 0 ? cb[n].x : (u == 1 ? cb[n].y : (u == 2 ? cb[n].z : cb[n].w));
-            acc[mm][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mm][u], bv, acc[mm][n], 0, 0, 0);
-          }
-        }
-#pragma unroll
-      for (int mm = 0; mm < MT; ++mm) ca[mm] = na[mm];
-#pragma unroll
-      for (int n = 0; n < NT; ++n) cb[n] = nb[n];
+      for (int u = 0; u < UB; ++u)
+        if (dst[u] >= 0) xs[dst[u]] = v[u];
     }
   }
-  // lane holds real rows 4*kr .. 4*kr+3 of each M-tile = complex rows 2kr, 2kr+1;
-  // tiles between the group's M_g and the vector stride M are written as zeros
-  const int nMall = M / 8;
+  if (ALDS) {
+    const int tmax = nM > 4 * int(blockIdx.y) ? (nM - 4 * int(blockIdx.y) + mstep - 1) / mstep : 0;
+    const int nel = 4 * tmax * tile4;
+    const int dblk = GG_BS / tile4, doff = GG_BS % tile4;
+    int blk = int(threadIdx.x) / tile4, off = int(threadIdx.x) % tile4;
+    for (int idx = int(threadIdx.x); idx < nel; idx += GG_BS) {
+      const int m = (blk & 3) + 4 * int(blockIdx.y) + mstep * (blk >> 2);
+      as[idx] = m < nM ? Aop[int64_t(m) * tile4 + off] : make_float4(0.f, 0.f, 0.f, 0.f);
+      blk += dblk;
+      off += doff;
+      if (off >= tile4) {
+        off -= tile4;
+        ++blk;
+      }
+    }
+  }
+  __syncthreads();
+
+  // this lane's output columns
+  float2* yp[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int col = n * 16 + j;
-    if (col >= nc) continue;
-    int64_t cc = c0 + col;
-    int vv = vbeg + int(cc / nrhs);
-    int k = int(cc % nrhs);
-    float2* y = Y + (int64_t(vdst[vv]) * nrhs + k) * M;
-#pragma unroll
-    for (int mm = 0; mm < MT; ++mm) {
-      const int m = wave + 4 * (slice + nslice * mm);
-      if (m < nMall) {
-        v4f a = acc[mm][n];
-        const float4 o = m < nM ? make_float4(a[0], a[1], a[2], a[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
-        reinterpret_cast<float4*>(y + 8 * m + 2 * kr)[0] = o;
-      }
+    yp[n] = nullptr;
+    if (col < nc) {
+      const int64_t cc = c0 + col;
+      const int vv = vbeg + int(cc / nrhs);
+      yp[n] = Y + (int64_t(vdst[vv]) * nrhs + int(cc % nrhs)) * M;
     }
   }
+
+  const int total = mcnt * Q4;  // flat (tile, k-step) sequence of this wave
+  if (total > 0) {
+    // operator fragment of flat step i = (t, s): tile base + s * 32 + this lane's offset
+    const int lofs = (j >> 1) * 4 + kr;
+    const int64_t tbase0 = ALDS ? int64_t(wave) * tile4 : int64_t(m0) * tile4;
+    const int64_t tjump = ALDS ? int64_t(4) * tile4 : int64_t(mstep) * tile4;
+    const float4* abase = (ALDS ? static_cast<const float4*>(as) : Aop) + lofs;
+    const int64_t last = tbase0 + int64_t(mcnt - 1) * tjump + int64_t(Q4 - 1) * 32;
+    int ps = 0;                 // k-step of the next prefetch within its tile
+    int64_t pofs = tbase0;      // its offset
+    int pi = 0;                 // its flat index
+    auto fetch = [&]() -> float4 {
+      const float4 v = abase[pi < total ? pofs : last];
+      ++pi;
+      if (++ps == Q4) {
+        ps = 0;
+        pofs += tjump - int64_t(Q4 - 1) * 32;
+      } else {
+        pofs += 32;
+      }
+      return v;
+    };
+    float4 ring[PD];
+#pragma unroll
+    for (int p = 0; p < PD; ++p) ring[p] = fetch();
+
+    v4f acc[NT];  // consecutive MFMAs on one accumulator chain through its C operand
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+    int s = 0, t = 0;
+    // B fragments: a ring of two steps (slot p & 1 of the unrolled loop)
+    const float4* bcol = xs + j * S4 + kr * Q4;
+    const int s1 = Q4 > 1 ? 1 : 0;
+    float4 bq[2][NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      bq[0][n] = bcol[n * 16 * S4];
+      bq[1][n] = bcol[n * 16 * S4 + s1];
+    }
+    auto step = [&](const float4 c, float4 (&b)[NT]) {
+      // the complex A fragment as real rows (even row: Re, -Im; odd row: Im, Re)
+      const float av[4] = {odd ? c.y : c.x, odd ? c.x : -c.y, odd ? c.w : c.z, odd ? c.z : -c.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const float bv = u == 0 ? b[n].x : (u == 1 ? b[n].y : (u == 2 ? b[n].z : b[n].w));
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv, acc[n], 0, 0, 0);
+        }
+      int s2 = s + 2;  // the k-step two ahead, within its tile
+      if (s2 >= Q4) s2 -= Q4;
+      if (s2 >= Q4) s2 -= Q4;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) b[n] = bcol[n * 16 * S4 + s2];
+      if (++s == Q4) {  // tile done: lane holds real rows 4kr .. 4kr+3 = complex rows 2kr, 2kr+1
+        const int m = m0 + mstep * t;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const v4f a = acc[n];
+          if (yp[n]) reinterpret_cast<float4*>(yp[n] + 8 * m + 2 * kr)[0] = make_float4(a[0], a[1], a[2], a[3]);
+          acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+        s = 0;
+        ++t;
+      }
+    };
+    // each fragment's register is refilled after its step has consumed it
+    int i0 = 0;
+    for (; i0 + PD <= total; i0 += PD) {
+#pragma unroll
+      for (int p = 0; p < PD; ++p) {
+        step(ring[p], bq[p & 1]);
+        ring[p] = fetch();
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PD; ++p)
+      if (i0 + p < total) step(ring[p], bq[p & 1]);
+  }
+  // tiles between the group's M_g and the vector stride M hold zeros
+  for (int m = m0 + mstep * mcnt; m < nMall; m += mstep)
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+      if (yp[n]) reinterpret_cast<float4*>(yp[n] + 8 * m + 2 * kr)[0] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 #define DFMM_GG_PARAMS                                                                                       \
   const float4 *__restrict__ A, const int64_t *__restrict__ aoff, const int *__restrict__ gmk, int M, int K,  \
-      int T, const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,          \
+      const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,                 \
       const int *__restrict__ vdst, const int *__restrict__ chunk_grp, const int *__restrict__ chunk_c0,       \
       int nrhs, const float2 *__restrict__ X, float2 *__restrict__ Y
-#define DFMM_GG_ARGS A, aoff, gmk, M, K, T, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
+#define DFMM_GG_ARGS A, aoff, gmk, M, K, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
 
 // The same tile engine under two names, so that kernel traces separate the
 // translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
-template <int MT, int NT, bool ALDS>
+template <int NT, bool ALDS>
 __global__ void __launch_bounds__(GG_BS) k_m2l(DFMM_GG_PARAMS) {
-  ggemm_tile<MT, NT, ALDS>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS>(DFMM_GG_ARGS);
 }
-template <int MT, int NT, bool ALDS>
+template <int NT, bool ALDS>
 __global__ void __launch_bounds__(GG_BS) k_transfer(DFMM_GG_PARAMS) {
-  ggemm_tile<MT, NT, ALDS>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS>(DFMM_GG_ARGS);
 }
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
@@ -598,55 +661,50 @@ static size_t gg_lds_total(int K, int nt, int mt, bool alds) {
   return gg_lds_bytes(K, nt) + (alds ? size_t(2048) * mt * (K / 8) : 0);
 }
 
-template <int MT, int NT, bool ALDS>
-static void launch_mt_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+// dynamic LDS limit of the GEMM kernels: 160 KB less 1 KB for their static LDS
+// (the column source table)
+constexpr int kGgDynLds = 159 * 1024;
+
+// M-tiles per wave of the largest group for a given number of M-slices
+static int gg_mt(const GGemm& G, int slices) { return (G.M / 8 + 4 * slices - 1) / (4 * slices); }
+
+template <int NT, bool ALDS>
+static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
-  size_t lds = gg_lds_bytes(G.K, NT) + (ALDS ? size_t(2048) * MT * (G.K / 8) : 0);
-  auto kern = L.m2l ? &k_m2l<MT, NT, ALDS> : &k_transfer<MT, NT, ALDS>;
+  const size_t lds = gg_lds_total(G.K, NT, gg_mt(G, L.slices), ALDS);
+  auto kern = L.m2l ? &k_m2l<NT, ALDS> : &k_transfer<NT, ALDS>;
   static bool attr = false;
   if (!attr) {
-    for (auto k : {&k_m2l<MT, NT, ALDS>, &k_transfer<MT, NT, ALDS>})
+    for (auto k : {&k_m2l<NT, ALDS>, &k_transfer<NT, ALDS>})
       DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
+                                   kGgDynLds));
     attr = true;
   }
   hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
-                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.T, G.ops.as<int>(),
-                     G.v0.as<int>(), G.vsrc.as<int>(),
-                     G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs, X, Y);
+                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.ops.as<int>(),
+                     G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs,
+                     X, Y);
 }
 
-template <int MT, int NT>
-static void launch_mt_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
-  if (L.alds) launch_mt_nt_a<MT, NT, true>(L, nrhs, X, Y, st);
-  else launch_mt_nt_a<MT, NT, false>(L, nrhs, X, Y, st);
+template <int NT>
+static void launch_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  if (L.alds) launch_nt_a<NT, true>(L, nrhs, X, Y, st);
+  else launch_nt_a<NT, false>(L, nrhs, X, Y, st);
 }
 
-template <int MT>
-static void launch_mt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
-  if (L.nt == 4) launch_mt_nt<MT, 4>(L, nrhs, X, Y, st);
-  else if (L.nt == 2) launch_mt_nt<MT, 2>(L, nrhs, X, Y, st);
-  else launch_mt_nt<MT, 1>(L, nrhs, X, Y, st);
+static bool gg_fits(const GGemm& G, int nt, int slices, bool alds) {
+  return gg_lds_total(G.K, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
 }
 
 static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   if (L.nchunks == 0) return;
   const GGemm& G = *L.G;
-  int nM = G.M / 8;
-  int per = 4 * L.slices;
-  int mt = (nM + per - 1) / per;
-  if (gg_lds_total(G.K, L.nt, mt, L.alds) > size_t(160 * 1024) || mt > 8)
+  if (G.T != 1) throw Error{DFMM_EUNSUPPORTED, "grouped GEMM with more than one term per group"};
+  if (!gg_fits(G, L.nt, L.slices, L.alds))
     throw Error{DFMM_EUNSUPPORTED, "skeleton rank too large for the GEMM kernel"};
-  switch (mt) {
-    case 1: launch_mt<1>(L, nrhs, X, Y, st); break;
-    case 2: launch_mt<2>(L, nrhs, X, Y, st); break;
-    case 3: launch_mt<3>(L, nrhs, X, Y, st); break;
-    case 4: launch_mt<4>(L, nrhs, X, Y, st); break;
-    case 5: launch_mt<5>(L, nrhs, X, Y, st); break;
-    case 6: launch_mt<6>(L, nrhs, X, Y, st); break;
-    case 7: launch_mt<7>(L, nrhs, X, Y, st); break;
-    default: launch_mt<8>(L, nrhs, X, Y, st); break;
-  }
+  if (L.nt == 4) launch_nt<4>(L, nrhs, X, Y, st);
+  else if (L.nt == 2) launch_nt<2>(L, nrhs, X, Y, st);
+  else launch_nt<1>(L, nrhs, X, Y, st);
 }
 
 // Tile autotuner: time every (tile width, M-slices) candidate of one launch on
@@ -668,8 +726,7 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
   for (int alds = 0; alds < 2; ++alds)
   for (int nt : {1, 2, 4})
     for (int sl = 1; sl <= std::min(max_slices, 4); ++sl) {
-      int mt = (nM + 4 * sl - 1) / (4 * sl);
-      if (mt > 8 || gg_lds_total(G.K, nt, mt, alds != 0) > size_t(160 * 1024)) continue;
+      if (!gg_fits(G, nt, sl, alds != 0)) continue;
       prepare_cfg(L, G, nrhs, nt, sl);
       L.alds = alds != 0;
       launch_gemm(L, nrhs, X, Y, st);  // warm-up
@@ -767,8 +824,7 @@ static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const
   for (int i = 0; i < n; ++i) {
     prepare_cfg(*ls[i], *gs[i], nrhs, v[3 * i], v[3 * i + 1]);
     ls[i]->alds = v[3 * i + 2] != 0;
-    const int nM = gs[i]->M / 8, mt = (nM + 4 * ls[i]->slices - 1) / (4 * ls[i]->slices);
-    if (mt > 8 || gg_lds_total(gs[i]->K, ls[i]->nt, mt, ls[i]->alds) > size_t(160 * 1024)) return false;
+    if (!gg_fits(*gs[i], ls[i]->nt, ls[i]->slices, ls[i]->alds)) return false;
   }
   return true;
 }

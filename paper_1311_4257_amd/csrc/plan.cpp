@@ -375,6 +375,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nleaf, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
               P.lf.ngroups, P.lf.flops);
     info.flops_m2l_lf = P.lf.flops;
+    info.flops_m2l_level[D] = P.lf.flops;
   }
 
   // ---- HF levels ----------------------------------------------------------------
@@ -556,6 +557,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     build_m2l(pairs[l], double(w), H.R, sp, &OS[l], &IS[l], H.nin, H.m2l, H.red_start, H.red_idx, H.ngroups,
               H.flops);
     info.flops_m2l_hf += H.flops;
+    info.flops_m2l_level[l] = H.flops;
   }
   auto t1 = std::chrono::steady_clock::now();
   P.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
