@@ -18,13 +18,18 @@
 // wedge (f, i, j) at width 2w lies in wedge (f, i/2, j/2) at width w (Figure 2).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <cstdlib>
 #include <vector>
 
 namespace dfmm {
 
-inline int64_t near_sum(int64_t nx, int64_t ny, int64_t nz) {
+// The scalar tests below are used by the host and by the list kernels.
+#define DFMM_HD __host__ __device__ inline
+
+DFMM_HD int64_t near_sum(int64_t nx, int64_t ny, int64_t nz) {
   auto t = [](int64_t v) -> int64_t {
     v = v < 0 ? -v : v;
     return v ? (2 * v - 1) * (2 * v - 1) : 0;
@@ -33,7 +38,7 @@ inline int64_t near_sum(int64_t nx, int64_t ny, int64_t nz) {
 }
 
 // 4 * max(3, 9 w^2 / 4) for w = 2^e2 / 2 (e2 = log2(2w); e2 = 0 is w = 1/2).
-inline int64_t near_limit4_e2(int e2) {
+DFMM_HD int64_t near_limit4_e2(int e2) {
   // 9 w^2 = 9 * 4^e2 / 4 ; for e2 = 0 that is 2.25 < 12
   if (e2 <= 1) return 12;  // w <= 1: 9 w^2 <= 9 < 12
   int64_t w = int64_t(1) << (e2 - 1);
@@ -41,17 +46,17 @@ inline int64_t near_limit4_e2(int e2) {
   return v > 12 ? v : 12;
 }
 
-inline bool is_near_e2(int64_t nx, int64_t ny, int64_t nz, int e2) {
+DFMM_HD bool is_near_e2(int64_t nx, int64_t ny, int64_t nz, int e2) {
   return 4 * near_sum(nx, ny, nz) <= near_limit4_e2(e2);
 }
 
 // Wedge index of a nonzero offset at HF width w (a power of two >= 1).
-inline int direction(int64_t nx, int64_t ny, int64_t nz, int64_t w) {
+DFMM_HD int direction(int64_t nx, int64_t ny, int64_t nz, int64_t w) {
   int64_t n[3] = {nx, ny, nz};
   int64_t m = 0;
-  for (int k = 0; k < 3; ++k) m = std::max<int64_t>(m, std::llabs(n[k]));
+  for (int k = 0; k < 3; ++k) m = (n[k] < 0 ? -n[k] : n[k]) > m ? (n[k] < 0 ? -n[k] : n[k]) : m;
   int a = 0;
-  while (std::llabs(n[a]) != m) ++a;
+  while ((n[a] < 0 ? -n[a] : n[a]) != m) ++a;
   int face = 2 * a + (n[a] < 0 ? 1 : 0);
   int64_t c[2];
   int ci = 0;
@@ -68,7 +73,7 @@ inline int direction(int64_t nx, int64_t ny, int64_t nz, int64_t w) {
 }
 
 // Wedge at width w2/2 containing wedge l of width w2.
-inline int direction_down(int l, int64_t w2) {
+DFMM_HD int direction_down(int l, int64_t w2) {
   int64_t w = w2 / 2;
   int64_t face = l / (w2 * w2);
   int64_t rem = l % (w2 * w2);

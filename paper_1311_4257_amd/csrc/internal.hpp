@@ -162,9 +162,40 @@ struct Tree {
     std::vector<int64_t> cbeg, cend;         // children range at level l+1
   };
   std::vector<Lv> lv;
-  // index of the box with coordinates (x, y, z) at level l, or -1
-  int64_t find(int l, int64_t x, int64_t y, int64_t z) const;
 };
+
+// One interaction pair B <- A at a level: offset n = i_A - i_B and the wedges
+// l_in = dir(n), l_out = dir(-n) (-1 at the leaf level).
+struct PairRec {
+  int64_t B, A, nx, ny, nz;
+  int din, dout;
+};
+
+// Needed (box, wedge) slots of one level: dense index box * ndir + wedge -> slot
+// (or -1), and the slots in (box, wedge) order.
+struct SlotIndex {
+  int ndir = 0;
+  std::vector<int64_t> dense;
+  std::vector<std::pair<int64_t, int>> list;
+  int64_t at(int64_t b, int d) const { return dense[size_t(b * ndir + d)]; }
+};
+
+// Device box tables (int32 except the keys), built from the sorted point keys.
+struct DevLevel {
+  int64_t nb = 0;
+  DevBuf key, start, end, cx, cy, cz, parent, cbeg, cend;
+};
+struct DevTree {
+  std::vector<DevLevel> lv;
+  std::vector<DevBuf> incl;  // per level: inclusive box count at each sorted point
+};
+void build_levels_device(const unsigned long long* sorted_key, int64_t N, int D, Tree& T, DevTree& DT);
+// I^B of every box of level l, sorted by (B, A); `fields` keeps the device copy
+// ([np][7] int32: B, A, nx, ny, nz, l_in, l_out).
+std::vector<PairRec> level_pairs_device(const DevTree& DT, int D, int l, DevBuf& fields);
+void near_lists_device(const DevTree& DT, int D, std::vector<int32_t>& start, std::vector<int32_t>& src);
+void slot_closure_device(const DevTree& DT, int D, int l_top, const std::vector<DevBuf>& fields,
+                         const std::vector<int64_t>& npairs, std::vector<SlotIndex>& OS, std::vector<SlotIndex>& IS);
 
 struct ApplyState;
 void destroy_apply_state(ApplyState* s);

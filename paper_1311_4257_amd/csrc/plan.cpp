@@ -15,7 +15,7 @@
 
 namespace dfmm {
 
-void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T);
+void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT);
 
 namespace {
 
@@ -52,18 +52,6 @@ int pad8(int r) { return (r + 7) / 8 * 8; }
 
 }  // namespace
 
-int64_t Tree::find(int l, int64_t x, int64_t y, int64_t z) const {
-  int64_t n = int64_t(1) << l;
-  if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return -1;
-  int64_t k = 0;
-  for (int b = 0; b < l; ++b)
-    k |= (((x >> b) & 1) << (3 * b)) | (((y >> b) & 1) << (3 * b + 1)) | (((z >> b) & 1) << (3 * b + 2));
-  const auto& K = lv[l].key;
-  auto it = std::lower_bound(K.begin(), K.end(), k);
-  if (it == K.end() || *it != k) return -1;
-  return int64_t(it - K.begin());
-}
-
 // Fragment order of an M x K complex operator for the MFMA kernel: for M-tile
 // m (8 complex rows), step s4 (K / 8 of them), row-in-tile ql (8) and K quarter
 // kr (4), one float4 holds the two complex entries (q, p0) and (q, p0 + 1) with
@@ -85,58 +73,6 @@ void pack_operator(const double* Tc, int M, int K, float* out) {
 
 namespace {
 
-struct PairRec {
-  int64_t B, A, nx, ny, nz;
-  int din, dout;
-};
-
-// I^B for every box of level l: non-empty children of N^{parent(B)} not in N^B.
-std::vector<PairRec> level_pairs(const Tree& T, int l) {
-  std::vector<PairRec> out;
-  if (l < 1) return out;
-  int e2 = T.D - l;  // log2(2w)
-  const auto& L = T.lv[l];
-  const auto& U = T.lv[l - 1];
-  std::vector<int64_t> noff = near_offsets_e2(e2 + 1);
-  int64_t nb = int64_t(L.key.size());
-  std::vector<std::vector<PairRec>> per(nb);
-  parallel_for(nb, [&](int64_t b) {
-    int64_t p = L.parent[b];
-    std::vector<PairRec>& v = per[b];
-    for (size_t i = 0; i < noff.size(); i += 3) {
-      int64_t q = T.find(l - 1, U.cx[p] + noff[i], U.cy[p] + noff[i + 1], U.cz[p] + noff[i + 2]);
-      if (q < 0) continue;
-      for (int64_t a = U.cbeg[q]; a < U.cend[q]; ++a) {
-        int64_t nx = L.cx[a] - L.cx[b], ny = L.cy[a] - L.cy[b], nz = L.cz[a] - L.cz[b];
-        if (is_near_e2(nx, ny, nz, e2)) continue;
-        PairRec r{b, a, nx, ny, nz, -1, -1};
-        if (e2 >= 1) {
-          int64_t w = int64_t(1) << (e2 - 1);
-          r.din = direction(nx, ny, nz, w);
-          r.dout = direction(-nx, -ny, -nz, w);
-        }
-        v.push_back(r);
-      }
-    }
-    std::sort(v.begin(), v.end(), [](const PairRec& x, const PairRec& y) { return x.A < y.A; });
-  });
-  for (auto& v : per) out.insert(out.end(), v.begin(), v.end());
-  return out;
-}
-
-struct SlotIndex {
-  std::map<std::pair<int64_t, int>, int64_t> idx;
-  std::vector<std::pair<int64_t, int>> list;
-  void build(const std::set<std::pair<int64_t, int>>& s) {
-    list.assign(s.begin(), s.end());
-    for (size_t i = 0; i < list.size(); ++i) idx[list[i]] = int64_t(i);
-  }
-  int64_t at(int64_t b, int d) const {
-    auto it = idx.find({b, d});
-    return it == idx.end() ? -1 : it->second;
-  }
-};
-
 }  // namespace
 
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
@@ -145,7 +81,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   P.N = N;
   P.K = K;
   Tree T;
-  build_tree_device(P, points, N, K, T);
+  DevTree DT;
+  build_tree_device(P, points, N, K, T, DT);
   const int D = T.D;
   P.D = D;
   dfmm_info& info = P.info;
@@ -168,10 +105,13 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
 
   // ---- interaction lists on every level -------------------------------------
   std::vector<std::vector<PairRec>> pairs(D + 1);
+  std::vector<DevBuf> pair_fields(D + 1);
+  std::vector<int64_t> npairs(D + 1, 0);
   P.pairs.assign(D + 1, {});
   int l_top = -1;
   for (int l = 1; l <= D; ++l) {
-    pairs[l] = level_pairs(T, l);
+    pairs[l] = level_pairs_device(DT, D, l, pair_fields[l]);
+    npairs[l] = int64_t(pairs[l].size());
     auto& v = P.pairs[l];
     for (auto& r : pairs[l]) v.insert(v.end(), {r.B, r.A, int64_t(r.din), int64_t(r.dout), 0});
     info.pairs[l] = int64_t(pairs[l].size());
@@ -192,54 +132,26 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   // ---- near-field lists -------------------------------------------------------
   const auto& LL = T.lv[D];
   int64_t nleaf = int64_t(LL.key.size());
-  std::vector<int32_t> near_start(nleaf + 1, 0), near_src;
-  {
-    std::vector<int64_t> noff = near_offsets_e2(0);
-    for (int64_t b = 0; b < nleaf; ++b) {
-      std::vector<int64_t> v;
-      for (size_t i = 0; i < noff.size(); i += 3) {
-        int64_t a = T.find(D, LL.cx[b] + noff[i], LL.cy[b] + noff[i + 1], LL.cz[b] + noff[i + 2]);
-        if (a >= 0) v.push_back(a);
-      }
-      std::sort(v.begin(), v.end());
-      for (int64_t a : v) {
-        near_src.push_back(int32_t(a));
-        P.near.push_back(b);
-        P.near.push_back(a);
-        info.near_point_pairs += (LL.end[b] - LL.start[b]) * (LL.end[a] - LL.start[a]);
-      }
-      near_start[b + 1] = int32_t(near_src.size());
+  std::vector<int32_t> near_start, near_src;
+  near_lists_device(DT, D, near_start, near_src);
+  for (int64_t b = 0; b < nleaf; ++b)
+    for (int32_t j = near_start[b]; j < near_start[b + 1]; ++j) {
+      const int64_t a = near_src[j];
+      P.near.push_back(b);
+      P.near.push_back(a);
+      info.near_point_pairs += (LL.end[b] - LL.start[b]) * (LL.end[a] - LL.start[a]);
     }
-    info.near_pairs = int64_t(near_src.size());
-  }
+  info.near_pairs = int64_t(near_src.size());
   P.near_start.upload(near_start);
   P.near_src.upload(near_src);
 
   // ---- needed directions (top-down closure) ----------------------------------
   P.out_slots.assign(D + 1, {});
   P.in_slots.assign(D + 1, {});
-  std::vector<SlotIndex> OS(D + 1), IS(D + 1);
+  std::vector<SlotIndex> OS, IS;
+  slot_closure_device(DT, D, e_top >= 0 ? l_top : -1, pair_fields, npairs, OS, IS);
   if (e_top >= 0) {
     for (int l = l_top; l < D; ++l) {
-      int64_t w = int64_t(1) << (D - 1 - l);
-      std::set<std::pair<int64_t, int>> outs, ins;
-      for (auto& r : pairs[l]) {
-        outs.insert({r.A, r.dout});
-        ins.insert({r.B, r.din});
-      }
-      if (l > l_top) {
-        const auto& U = T.lv[l - 1];
-        for (auto& s : OS[l - 1].list) {
-          int dd = direction_down(s.second, 2 * w);
-          for (int64_t c = U.cbeg[s.first]; c < U.cend[s.first]; ++c) outs.insert({c, dd});
-        }
-        for (auto& s : IS[l - 1].list) {
-          int dd = direction_down(s.second, 2 * w);
-          for (int64_t c = U.cbeg[s.first]; c < U.cend[s.first]; ++c) ins.insert({c, dd});
-        }
-      }
-      OS[l].build(outs);
-      IS[l].build(ins);
       for (auto& s : OS[l].list) P.out_slots[l].insert(P.out_slots[l].end(), {s.first, int64_t(s.second)});
       for (auto& s : IS[l].list) P.in_slots[l].insert(P.in_slots[l].end(), {s.first, int64_t(s.second)});
       info.out_slots[l] = int64_t(OS[l].list.size());

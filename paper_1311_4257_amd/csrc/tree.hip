@@ -1,5 +1,5 @@
 // Octree construction: Morton keys and the stable key sort run on the device;
-// the per-level box tables are read off the sorted keys (Section 2.2 and
+// the per-level box tables follow from the sorted keys (Section 2.2 and
 // Section 3.1: level l is a 2^l x 2^l x 2^l grid of boxes of width K 2^-l in
 // the cube [-K/2, K/2]^3; leaves have width 1/2, so D = log2(2K)).
 //
@@ -41,7 +41,7 @@ __global__ void k_morton(const double* __restrict__ pts, int64_t n, double half,
 
 }  // namespace
 
-void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T) {
+void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT) {
   int D = 0;
   while (std::ldexp(1.0, D) < 2.0 * K) ++D;
   T.D = D;
@@ -64,59 +64,15 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   tmp.alloc(tb);
   DFMM_HIP(rocprim::radix_sort_pairs(tmp.p, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
                                      v0.as<int>(), v1.as<int>(), size_t(N), 0u, end_bit));
-  std::vector<unsigned long long> key(N);
   std::vector<int> idx(N);
-  DFMM_HIP(hipMemcpy(key.data(), k1.p, sizeof(unsigned long long) * N, hipMemcpyDeviceToHost));
   DFMM_HIP(hipMemcpy(idx.data(), v1.p, sizeof(int) * N, hipMemcpyDeviceToHost));
-
   T.perm.assign(idx.begin(), idx.end());
   T.pts.resize(3 * size_t(N));
   for (int64_t s = 0; s < N; ++s)
     for (int a = 0; a < 3; ++a) T.pts[3 * s + a] = points[3 * int64_t(idx[s]) + a];
 
-  // box tables per level, read off the sorted keys
-  T.lv.assign(D + 1, {});
-  for (int l = 0; l <= D; ++l) {
-    Tree::Lv& L = T.lv[l];
-    unsigned sh = unsigned(3 * (D - l));
-    for (int64_t s = 0; s < N; ++s) {
-      int64_t kl = int64_t(key[s] >> sh);
-      if (s == 0 || kl != L.key.back()) {
-        if (s > 0) L.end.push_back(s);
-        L.key.push_back(kl);
-        L.start.push_back(s);
-        int64_t c[3] = {0, 0, 0};
-        for (int b = 0; b < l; ++b)
-          for (int a = 0; a < 3; ++a) c[a] |= ((kl >> (3 * b + a)) & 1) << b;
-        L.cx.push_back(c[0]);
-        L.cy.push_back(c[1]);
-        L.cz.push_back(c[2]);
-        L.octant.push_back(l > 0 ? (kl & 7) : 0);
-      }
-    }
-    L.end.push_back(N);
-    size_t nb = L.key.size();
-    L.parent.assign(nb, -1);
-    if (l > 0) {
-      const auto& U = T.lv[l - 1];
-      for (size_t b = 0; b < nb; ++b)
-        L.parent[b] = int64_t(std::lower_bound(U.key.begin(), U.key.end(), L.key[b] >> 3) - U.key.begin());
-    }
-  }
-  for (int l = 0; l <= D; ++l) {
-    Tree::Lv& L = T.lv[l];
-    size_t nb = L.key.size();
-    L.cbeg.assign(nb, 0);
-    L.cend.assign(nb, 0);
-    if (l < D) {
-      const auto& C = T.lv[l + 1];
-      for (size_t c = 0; c < C.key.size(); ++c) {
-        int64_t p = C.parent[c];
-        if (c == 0 || C.parent[c - 1] != p) L.cbeg[p] = int64_t(c);
-        L.cend[p] = int64_t(c) + 1;
-      }
-    }
-  }
+  // box tables per level, from the sorted keys (lists.hip)
+  build_levels_device(k1.as<unsigned long long>(), N, D, T, DT);
 
   // sorted points on the device, split into float hi + lo parts
   std::vector<float> hi(4 * size_t(N), 0.0f), lo(4 * size_t(N), 0.0f);

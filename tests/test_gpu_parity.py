@@ -115,15 +115,20 @@ def test_repeat_is_bitwise_deterministic(cuda):
     assert np.array_equal(a, b)
 
 
-def test_sphere16_full_size_sampled_targets(cuda):
-    """The benchmark workload (K = 16 sphere, N = 65,536, eps = 1e-4) on 2,048 sampled targets."""
+@pytest.mark.parametrize("eps", [1e-4, pytest.param(1e-6, marks=pytest.mark.xfail(
+    reason="measured 1.43e-6: the eps = 1e-6 skeletons alone give 9.8e-7 (float64 pass with the "
+           "library's skeletons) and the float32 pass adds about 1e-6", strict=False))])
+def test_sphere16_full_size_sampled_targets(cuda, eps):
+    """The benchmark workload (K = 16 sphere, N = 65,536) with the eps = 1e-4 and the
+    eps = 1e-6 plan, on 2,048 sampled targets against the direct sum."""
     pts, f, cfg = workloads.make_config("sphere16")
-    plan = _dfmm().Plan(pts, cfg["K"], eps=cfg["eps"], cache_dir=CACHE, device=0)
+    plan = _dfmm().Plan(pts, cfg["K"], eps=eps, cache_dir=CACHE, device=0)
     u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
     tg = workloads.sample_targets(len(pts), cfg["n_check"], cfg["check_seed"])
     err = rel_l2(u[:, tg], direct_sum(pts, f, tg))
-    print(f"sphere16: rel L2 vs direct sum on {len(tg)} targets {err:.2e}")
-    assert err <= cfg["eps"]
+    print(f"sphere16 eps={eps:g}: rel L2 vs direct sum on {len(tg)} targets {err:.2e}, "
+          f"ranks {[plan.info().rank[l] for l in range(plan.info().depth + 1)]}")
+    assert err <= eps
 
 
 def test_ellipsoid32_nrhs32_sampled_targets(cuda):
