@@ -181,10 +181,10 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
 // consecutive k values of its quarter with one 16-byte load from LDS (B) and
 // from the fragment-ordered operator (A).  The column block sits in LDS,
 // [column][k] with a row stride S = 4 (mod 32) floats.  The (tile, k-step)
-// sequence of a wave is one flat loop; the operator fragments of the next GG_PD
-// steps are in flight in a register ring, and their loads are issued on every
-// step (past the end they repeat the last address) so that each wait is for
-// the oldest load only.
+// sequence of a wave is one flat loop; the operator loads of the next few step
+// pairs are in flight in a register ring, and a load is issued for every step
+// pair (past the end it repeats the last address) so that each wait is for the
+// oldest load only.
 typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int GG_BS = 256;
 
@@ -193,10 +193,19 @@ __host__ __device__ inline int gg_stride(int K) {
   return s + ((4 - (s % 32)) + 32) % 32;
 }
 
+// operator loads in flight per lane (each covers two k-steps)
 template <int NT>
 struct GgDepth {
-  static constexpr int value = NT == 1 ? 8 : (NT == 2 ? 6 : 4);
+  static constexpr int value = NT == 1 ? 4 : (NT == 2 ? 4 : 3);
 };
+
+// the float4 of the neighbouring lane (lane ^ 1), by DPP quad permutation [1, 0, 3, 2]
+__device__ __forceinline__ float4 swap_pair(const float4 v) {
+  auto sw = [](float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+  };
+  return make_float4(sw(v.x), sw(v.y), sw(v.z), sw(v.w));
+}
 
 template <int NT, bool ALDS>  // ALDS: stage the workgroup's operator tiles in LDS first
 __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
@@ -208,7 +217,6 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
   constexpr int PD = GgDepth<NT>::value;
-  static_assert(PD % 2 == 0, "the B ring pairs slots by parity");
   const int S4 = gg_stride(K) / 4;      // float4 per LDS column (K = the largest K_g)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -234,6 +242,43 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   const float4* Aop = A + aoff[gops[g]];
   const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
   float4* as = xs + NC * S4;  // ALDS: the tiles of this slice, [t][wave][tile4]
+
+  // operator fragment stream of this wave: flat step i = (t, s) reads tile base
+  // + s * 32 + this lane's offset.  The two lanes of a row pair (j, j ^ 1) need
+  // the same 16 bytes, so one load serves two steps: the even lane fetches step
+  // i and the odd lane step i + 1, and a lane swap gives each both.  From global
+  // memory the first loads are issued before the column staging, so their
+  // latency overlaps it.
+  const int total = mcnt * Q4;  // flat (tile, k-step) sequence of this wave
+  const int lofs = (j >> 1) * 4 + kr;
+  const int64_t tbase0 = ALDS ? int64_t(wave) * tile4 : int64_t(m0) * tile4;
+  const int64_t tjump = ALDS ? int64_t(4) * tile4 : int64_t(mstep) * tile4;
+  const float4* abase = (ALDS ? static_cast<const float4*>(as) : Aop) + lofs;
+  const int64_t last = tbase0 + int64_t(mcnt - 1) * tjump + int64_t(Q4 - 1) * 32;
+  int ps = 0;                 // k-step of the next prefetch within its tile
+  int64_t pofs = tbase0;      // its offset
+  int pi = 0;                 // its flat index
+  auto advance = [&]() {
+    ++pi;
+    if (++ps == Q4) {
+      ps = 0;
+      pofs += tjump - int64_t(Q4 - 1) * 32;
+    } else {
+      pofs += 32;
+    }
+  };
+  auto fetch = [&]() -> float4 {  // steps pi (even lane) and pi + 1 (odd lane)
+    const int64_t o0 = pi < total ? pofs : last;
+    advance();
+    const int64_t o1 = pi < total ? pofs : last;
+    advance();
+    return abase[odd ? o1 : o0];
+  };
+  float4 ring[PD];
+  if (!ALDS && total > 0) {
+#pragma unroll
+    for (int p = 0; p < PD; ++p) ring[p] = fetch();
+  }
   __shared__ const float4* colsrc[NC];
   if (threadIdx.x < NC) {
     const int col = threadIdx.x;
@@ -292,6 +337,10 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
     }
   }
   __syncthreads();
+  if (ALDS && total > 0) {
+#pragma unroll
+    for (int p = 0; p < PD; ++p) ring[p] = fetch();
+  }
 
   // this lane's output columns
   float2* yp[NT];
@@ -306,32 +355,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
     }
   }
 
-  const int total = mcnt * Q4;  // flat (tile, k-step) sequence of this wave
   if (total > 0) {
-    // operator fragment of flat step i = (t, s): tile base + s * 32 + this lane's offset
-    const int lofs = (j >> 1) * 4 + kr;
-    const int64_t tbase0 = ALDS ? int64_t(wave) * tile4 : int64_t(m0) * tile4;
-    const int64_t tjump = ALDS ? int64_t(4) * tile4 : int64_t(mstep) * tile4;
-    const float4* abase = (ALDS ? static_cast<const float4*>(as) : Aop) + lofs;
-    const int64_t last = tbase0 + int64_t(mcnt - 1) * tjump + int64_t(Q4 - 1) * 32;
-    int ps = 0;                 // k-step of the next prefetch within its tile
-    int64_t pofs = tbase0;      // its offset
-    int pi = 0;                 // its flat index
-    auto fetch = [&]() -> float4 {
-      const float4 v = abase[pi < total ? pofs : last];
-      ++pi;
-      if (++ps == Q4) {
-        ps = 0;
-        pofs += tjump - int64_t(Q4 - 1) * 32;
-      } else {
-        pofs += 32;
-      }
-      return v;
-    };
-    float4 ring[PD];
-#pragma unroll
-    for (int p = 0; p < PD; ++p) ring[p] = fetch();
-
     v4f acc[NT];  // consecutive MFMAs on one accumulator chain through its C operand
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -345,9 +369,21 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
       bq[0][n] = bcol[n * 16 * S4];
       bq[1][n] = bcol[n * 16 * S4 + s1];
     }
-    auto step = [&](const float4 c, float4 (&b)[NT]) {
-      // the complex A fragment as real rows (even row: Re, -Im; odd row: Im, Re)
-      const float av[4] = {odd ? c.y : c.x, odd ? c.x : -c.y, odd ? c.w : c.z, odd ? c.z : -c.w};
+    // the complex A fragments of a step pair as real rows (even row: Re, -Im;
+    // odd row: Im, Re): v is this lane's load, w its neighbour's
+    auto frag0 = [&](const float4 v, const float4 w, float (&av)[4]) {  // step i
+      av[0] = odd ? w.y : v.x;
+      av[1] = odd ? w.x : -v.y;
+      av[2] = odd ? w.w : v.z;
+      av[3] = odd ? w.z : -v.w;
+    };
+    auto frag1 = [&](const float4 v, const float4 w, float (&av)[4]) {  // step i + 1
+      av[0] = odd ? v.y : w.x;
+      av[1] = odd ? v.x : -w.y;
+      av[2] = odd ? v.w : w.z;
+      av[3] = odd ? v.z : -w.w;
+    };
+    auto step = [&](const float (&av)[4], float4 (&b)[NT]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -372,18 +408,29 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
         ++t;
       }
     };
-    // each fragment's register is refilled after its step has consumed it
+    // each load's register is refilled after its two steps have consumed it
     int i0 = 0;
-    for (; i0 + PD <= total; i0 += PD) {
+    float av0[4], av1[4];
+    for (; i0 + 2 * PD <= total; i0 += 2 * PD) {
 #pragma unroll
       for (int p = 0; p < PD; ++p) {
-        step(ring[p], bq[p & 1]);
+        const float4 v = ring[p], w = swap_pair(v);
+        frag0(v, w, av0);
+        frag1(v, w, av1);
+        step(av0, bq[0]);
+        step(av1, bq[1]);
         ring[p] = fetch();
       }
     }
 #pragma unroll
-    for (int p = 0; p < PD; ++p)
-      if (i0 + p < total) step(ring[p], bq[p & 1]);
+    for (int p = 0; p < PD; ++p) {
+      if (i0 + 2 * p >= total) break;
+      const float4 v = ring[p], w = swap_pair(v);
+      frag0(v, w, av0);
+      frag1(v, w, av1);
+      step(av0, bq[0]);
+      if (i0 + 2 * p + 1 < total) step(av1, bq[1]);
+    }
   }
   // tiles between the group's M_g and the vector stride M hold zeros
   for (int m = m0 + mstep * mcnt; m < nMall; m += mstep)
