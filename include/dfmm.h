@@ -106,7 +106,12 @@ void dfmm_options_default(dfmm_options* opt);
  * in a domain of width K with end-to-end target eps (1e-7 <= eps <= 1e-2).
  * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
  * every level (Section 2.2), the wedge labels, the needed directions and the
- * translation tables, all resident on the device.  Synchronous. */
+ * translation tables, all resident on the device.  Synchronous.
+ * The skeletons use tau = 0.15 eps (eps >= 1e-5) or 0.05 eps.  Plans with
+ * eps < 1e-5 (or an operator set with tau < 3e-6) are "precise": the
+ * near-field distances, 1/r and products are float64, the directional
+ * operators are stored as float32 hi + lo parts, and every translation GEMM adds
+ * its float32 sums into float64 partial sums every 32 products. */
 int dfmm_plan(const double* points, int64_t N, double K, double eps, dfmm_plan_t* out);
 int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* opt,
                  dfmm_plan_t* out);

@@ -34,15 +34,14 @@ __device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
 // G for a separation given in float64: the distance and the phase reduction
 // r - rint(r) are done in float64 (the phase error stays ~2e-7 rad however far
 // apart the points are), sin/cos of the reduced phase and 1/r in float32.
-__device__ __forceinline__ float2 green_d(double dx, double dy, double dz) {
-  double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  if (r2 == 0.0) return make_float2(0.0f, 0.0f);
-  double r = sqrt(r2);
-  float t = float(r - rint(r));
+__device__ __forceinline__ double2 green_d(double dx, double dy, double dz) {
+  const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  if (r2 == 0.0) return make_double2(0.0, 0.0);
+  const double r = sqrt(r2);
   float s, c;
-  sincospif(2.0f * t, &s, &c);
-  float ri = rsqrtf(float(r2));
-  return make_float2(c * ri, s * ri);
+  sincospif(2.0f * float(r - rint(r)), &s, &c);  // the phase reduced in float64 first
+  const double ri = 1.0 / r;
+  return make_double2(double(c) * ri, double(s) * ri);
 }
 
 // sin and cos of 2 pi t for |t| <= 1/2 (t in turns): quadrant q = rint(4 t),
@@ -63,17 +62,22 @@ __device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
   pc = fmaf(x2, pc, 4.1666668e-02f);                        // 1/4!
   pc = fmaf(x2, pc, -0.5f);                                 // -1/2!
   pc = fmaf(x2, pc, 1.0f);
+  // rotate by qi quarter turns without branches: odd qi swaps the pair, the
+  // sine is negative for qi = 2, 3 and the cosine for qi = 1, 2
   const int qi = int(q) & 3;
-  s = qi == 0 ? ps : (qi == 1 ? pc : (qi == 2 ? -ps : -pc));
-  c = qi == 0 ? pc : (qi == 1 ? -ps : (qi == 2 ? -pc : ps));
+  const bool sw = (qi & 1) != 0;
+  const float s0 = sw ? pc : ps, c0 = sw ? ps : pc;
+  s = __int_as_float(__float_as_int(s0) ^ ((qi & 2) << 30));
+  c = __int_as_float(__float_as_int(c0) ^ (((qi + 1) & 2) << 30));
 }
 
-// G for a float32 separation: r from float32 squares, phase r - rint(r),
-// sin/cos by sincos_turns.  Phase error ~2e-7 r rad: for the eps >= 1e-5 plans.
+// G for a float32 separation: r from float32 squares and the hardware
+// reciprocal square root, phase r - rint(r), sin/cos by sincos_turns.  Phase
+// error ~2e-7 r rad: for the eps >= 1e-5 plans.  A coincident pair (r = 0)
+// gives 0 without a branch (1/r taken as 0, so r and the phase are 0 too).
 __device__ __forceinline__ float2 green_f(float dx, float dy, float dz) {
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-  if (r2 == 0.0f) return make_float2(0.0f, 0.0f);
-  const float ri = rsqrtf(r2);
+  const float ri = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
   const float r = r2 * ri;
   float s, c;
   sincos_turns(r - rintf(r), s, c);
@@ -207,9 +211,13 @@ __device__ __forceinline__ float4 swap_pair(const float4 v) {
   return make_float4(sw(v.x), sw(v.y), sw(v.z), sw(v.w));
 }
 
-template <int NT, bool ALDS>  // ALDS: stage the workgroup's operator tiles in LDS first
+// ALDS: stage the workgroup's operator tiles in LDS first.  ACC64: every two
+// k-steps (32 real products per output) the float32 MFMA sums are added into
+// float64 partial sums, so the rounding of long float32 dot products (which
+// grows with their length) stays at that of 32 terms.
+template <int NT, bool ALDS, bool ACC64>
 __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
-                                           const int* __restrict__ gmk, int M, int K,
+                                           const int* __restrict__ gmk, int M, int K, int split,
                                            const int* __restrict__ gops, const int* __restrict__ gv0,
                                            const int* __restrict__ vsrc, const int* __restrict__ vdst,
                                            const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
@@ -217,7 +225,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
   constexpr int PD = GgDepth<NT>::value;
-  const int S4 = gg_stride(K) / 4;      // float4 per LDS column (K = the largest K_g)
+  const int S4 = gg_stride(split * K) / 4;  // float4 per LDS column (split K >= every K_g)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, kr = lane >> 4;
@@ -239,6 +247,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   // a wave reads long contiguous runs) with incremental indices, issuing a
   // batch of loads before storing them.
   const int per_col = Kg / 2;  // float4 per column
+  const int pcs = per_col / split;  // float4 per source vector (split = 2: each read twice)
   const float4* Aop = A + aoff[gops[g]];
   const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
   float4* as = xs + NC * S4;  // ALDS: the tiles of this slice, [t][wave][tile4]
@@ -305,7 +314,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
         dst[u] = -1;
         if (base + u * GG_BS < nel) {
           const float4* p = colsrc[col];
-          if (p) v[u] = p[q4];
+          if (p) v[u] = p[q4 < pcs ? q4 : q4 - pcs];
           dst[u] = col * S4 + q4;
         }
         col += dcol;
@@ -357,8 +366,13 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 
   if (total > 0) {
     v4f acc[NT];  // consecutive MFMAs on one accumulator chain through its C operand
+    double a64[ACC64 ? NT : 1][4];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int n = 0; n < (ACC64 ? NT : 1); ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a64[n][r] = 0.0;
     int s = 0, t = 0;
     // B fragments: a ring of two steps (slot p & 1 of the unrolled loop)
     const float4* bcol = xs + j * S4 + kr * Q4;
@@ -396,12 +410,30 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
       if (s2 >= Q4) s2 -= Q4;
 #pragma unroll
       for (int n = 0; n < NT; ++n) b[n] = bcol[n * 16 * S4 + s2];
+      if constexpr (ACC64) {
+        if ((s & 1) || s + 1 == Q4) {
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a64[n][r] += double(acc[n][r]);
+            acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
       if (++s == Q4) {  // tile done: lane holds real rows 4kr .. 4kr+3 = complex rows 2kr, 2kr+1
         const int m = m0 + mstep * t;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const v4f a = acc[n];
-          if (yp[n]) reinterpret_cast<float4*>(yp[n] + 8 * m + 2 * kr)[0] = make_float4(a[0], a[1], a[2], a[3]);
+          float4 o;
+          if constexpr (ACC64) {
+            o = make_float4(float(a64[n][0]), float(a64[n][1]), float(a64[n][2]), float(a64[n][3]));
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a64[n][r] = 0.0;
+          } else {
+            const v4f a = acc[n];
+            o = make_float4(a[0], a[1], a[2], a[3]);
+          }
+          if (yp[n]) reinterpret_cast<float4*>(yp[n] + 8 * m + 2 * kr)[0] = o;
           acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
         }
         s = 0;
@@ -441,20 +473,20 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 
 #define DFMM_GG_PARAMS                                                                                       \
   const float4 *__restrict__ A, const int64_t *__restrict__ aoff, const int *__restrict__ gmk, int M, int K,  \
-      const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,                 \
+      int split, const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,      \
       const int *__restrict__ vdst, const int *__restrict__ chunk_grp, const int *__restrict__ chunk_c0,       \
       int nrhs, const float2 *__restrict__ X, float2 *__restrict__ Y
-#define DFMM_GG_ARGS A, aoff, gmk, M, K, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
+#define DFMM_GG_ARGS A, aoff, gmk, M, K, split, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
 
 // The same tile engine under two names, so that kernel traces separate the
 // translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
-template <int NT, bool ALDS>
+template <int NT, bool ALDS, bool ACC64>
 __global__ void __launch_bounds__(GG_BS) k_m2l(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64>(DFMM_GG_ARGS);
 }
-template <int NT, bool ALDS>
+template <int NT, bool ALDS, bool ACC64>
 __global__ void __launch_bounds__(GG_BS) k_transfer(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64>(DFMM_GG_ARGS);
 }
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
@@ -466,23 +498,29 @@ __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri,
   if (t >= nslot * RN) return;
   int64_t s = t / RN;
   int e = int(t % RN);
-  float2 acc = accumulate ? U[t] : make_float2(0.f, 0.f);
+  // the pair contributions of one slot cancel to a large extent: sum in float64
+  double ax = 0.0, ay = 0.0;
+  if (accumulate) {
+    const float2 u0 = U[t];
+    ax = u0.x;
+    ay = u0.y;
+  }
   int j = rs[s];
   const int j1 = rs[s + 1];
   for (; j + 4 <= j1; j += 4) {  // four loads in flight, added in order
     const float2 y0 = Y[int64_t(ri[j]) * RN + e], y1 = Y[int64_t(ri[j + 1]) * RN + e];
     const float2 y2 = Y[int64_t(ri[j + 2]) * RN + e], y3 = Y[int64_t(ri[j + 3]) * RN + e];
-    acc.x += y0.x; acc.y += y0.y;
-    acc.x += y1.x; acc.y += y1.y;
-    acc.x += y2.x; acc.y += y2.y;
-    acc.x += y3.x; acc.y += y3.y;
+    ax += y0.x; ay += y0.y;
+    ax += y1.x; ay += y1.y;
+    ax += y2.x; ay += y2.y;
+    ax += y3.x; ay += y3.y;
   }
   for (; j < j1; ++j) {
     const float2 y = Y[int64_t(ri[j]) * RN + e];
-    acc.x += y.x;
-    acc.y += y.y;
+    ax += y.x;
+    ay += y.y;
   }
-  U[t] = acc;
+  U[t] = make_float2(float(ax), float(ay));
 }
 
 // ---- leaf evaluation: L2T plus the near-field sum, written in user order ----------
@@ -501,16 +539,26 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 }
 
 constexpr int EV_CHUNK = 256;  // source points staged in LDS at a time
+// Fast plans (eps >= 1e-5) use leaf-local float32 coordinates: every point is
+// stored relative to its leaf centre (the float64 difference rounded once), and
+// a source is moved into the target leaf's frame by the exact difference of
+// the two centres (multiples of 1/2), so a separation carries ~1e-7 absolute
+// error; the products are summed in float32 over a staged chunk and the chunk
+// sums in float64.  Precise plans form the separations in float64 from the
+// hi/lo parts of the points and sum every product in float64.
 template <bool PRECISE, int RC>  // RC: right-hand sides per pass
 __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ phi, const float4* __restrict__ plo,
+                                                      const float4* __restrict__ ploc,
+                                                      const float4* __restrict__ lcen,
                                                       const int* __restrict__ lstart,
                                                       const int* __restrict__ nstart, const int* __restrict__ nsrc,
                                                       const float2* __restrict__ fs, const float2* __restrict__ W,
                                                       const float2* __restrict__ ulf, int R, int nrhs, int64_t N,
                                                       const int* __restrict__ perm, float2* __restrict__ u) {
-  __shared__ float4 sh[EV_CHUNK], sq[EV_CHUNK];
+  __shared__ float4 sh[EV_CHUNK], sq[PRECISE ? EV_CHUNK : 1];
   __shared__ float2 sf[EV_CHUNK * RC];
   __shared__ int nb_beg[EV_BS], nb_off[EV_BS + 1];
+  __shared__ float4 nb_dc[EV_BS];
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   const int tl = lane & 15, sl = lane >> 4;
@@ -520,10 +568,15 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
   // all neighbour ranges at once; offsets by a wave prefix sum
   {
     int beg = 0, cnt = 0;
+    float4 dc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < nn) {
       const int A = nsrc[n0 + lane];
       beg = lstart[A];
       cnt = lstart[A + 1] - beg;
+      if (!PRECISE) {
+        const float4 ca = lcen[A], cb = lcen[b];
+        dc = make_float4(ca.x - cb.x, ca.y - cb.y, ca.z - cb.z, 0.f);  // exact
+      }
     }
     int incl = cnt;
     for (int d = 1; d < EV_BS; d <<= 1) {
@@ -532,6 +585,7 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
     }
     nb_beg[lane] = beg;
     nb_off[lane] = incl - cnt;
+    nb_dc[lane] = dc;
     if (lane == EV_BS - 1) nb_off[EV_BS] = incl;
   }
   __syncthreads();
@@ -542,7 +596,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
       const int t = t0 + tl;
       const bool act = t < s1;
       const int tt = act ? t : s0;
-      const float4 th = phi[tt], tq = plo[tt];
+      const float4 th = PRECISE ? phi[tt] : ploc[tt];
+      const float4 tq = PRECISE ? plo[tt] : make_float4(0.f, 0.f, 0.f, 0.f);
       double ar[RC], ai[RC];
       // L2T: sum_q W[t][q] U_LF[leaf][k][q] over this lane's quarter of q
       {
@@ -568,32 +623,57 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
         __syncthreads();
         for (int i = lane; i < fill; i += EV_BS) {
           const int gidx = base + i;
-          int kk = 0;
-          while (kk + 1 < nn && nb_off[kk + 1] <= gidx) ++kk;
+          int kk = 0;  // the neighbour holding element gidx: largest kk with nb_off[kk] <= gidx
+#pragma unroll
+          for (int step = 16; step > 0; step >>= 1)
+            if (kk + step < nn && nb_off[kk + step] <= gidx) kk += step;
           const int j = nb_beg[kk] + (gidx - nb_off[kk]);
-          sh[i] = phi[j];
-          sq[i] = plo[j];
+          if (PRECISE) {
+            sh[i] = phi[j];
+            sq[i] = plo[j];
+          } else {
+            const float4 pl = ploc[j], d = nb_dc[kk];
+            sh[i] = make_float4(pl.x + d.x, pl.y + d.y, pl.z + d.z, 0.f);
+          }
           for (int k = 0; k < nk; ++k) sf[i * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
         }
         __syncthreads();
-        for (int i = sl; i < fill; i += 4) {
-          const float4 h = sh[i], l = sq[i];
-          float2 gg;
-          if (PRECISE) {
+        if constexpr (PRECISE) {  // 1/r and the products in float64
+          for (int i = sl; i < fill; i += 4) {
+            const float4 h = sh[i], l = sq[i];
             const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
             const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
             const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
-            gg = green_d(dx, dy, dz);
-          } else {
-            gg = green_f((th.x - h.x) + (tq.x - l.x), (th.y - h.y) + (tq.y - l.y), (th.z - h.z) + (tq.z - l.z));
+            const double2 gg = green_d(dx, dy, dz);
+#pragma unroll
+            for (int k = 0; k < RC; ++k) {
+              if (k < nk) {
+                const float2 fk = sf[i * RC + k];
+                ar[k] += gg.x * double(fk.x) - gg.y * double(fk.y);
+                ai[k] += gg.x * double(fk.y) + gg.y * double(fk.x);
+              }
+            }
+          }
+        } else {
+          float cr[RC], ci[RC];
+#pragma unroll
+          for (int k = 0; k < RC; ++k) cr[k] = ci[k] = 0.f;
+          for (int i = sl; i < fill; i += 4) {
+            const float4 h = sh[i];
+            const float2 gg = green_f(th.x - h.x, th.y - h.y, th.z - h.z);
+#pragma unroll
+            for (int k = 0; k < RC; ++k) {
+              if (k < nk) {
+                const float2 fk = sf[i * RC + k];
+                cr[k] = fmaf(gg.x, fk.x, fmaf(-gg.y, fk.y, cr[k]));
+                ci[k] = fmaf(gg.x, fk.y, fmaf(gg.y, fk.x, ci[k]));
+              }
+            }
           }
 #pragma unroll
           for (int k = 0; k < RC; ++k) {
-            if (k < nk) {
-              const float2 fk = sf[i * RC + k];
-              ar[k] += double(gg.x * fk.x - gg.y * fk.y);
-              ai[k] += double(gg.x * fk.y + gg.y * fk.x);
-            }
+            ar[k] += cr[k];
+            ai[k] += ci[k];
           }
         }
       }
@@ -715,32 +795,34 @@ constexpr int kGgDynLds = 159 * 1024;
 // M-tiles per wave of the largest group for a given number of M-slices
 static int gg_mt(const GGemm& G, int slices) { return (G.M / 8 + 4 * slices - 1) / (4 * slices); }
 
-template <int NT, bool ALDS>
+template <int NT, bool ALDS, bool ACC64>
 static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
-  const size_t lds = gg_lds_total(G.K, NT, gg_mt(G, L.slices), ALDS);
-  auto kern = L.m2l ? &k_m2l<NT, ALDS> : &k_transfer<NT, ALDS>;
+  const size_t lds = gg_lds_total(G.K * G.split, NT, gg_mt(G, L.slices), ALDS);
+  auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64> : &k_transfer<NT, ALDS, ACC64>;
   static bool attr = false;
   if (!attr) {
-    for (auto k : {&k_m2l<NT, ALDS>, &k_transfer<NT, ALDS>})
+    for (auto k : {&k_m2l<NT, ALDS, ACC64>, &k_transfer<NT, ALDS, ACC64>})
       DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    kGgDynLds));
     attr = true;
   }
   hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
-                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.ops.as<int>(),
+                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.split, G.ops.as<int>(),
                      G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs,
                      X, Y);
 }
 
 template <int NT>
 static void launch_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
-  if (L.alds) launch_nt_a<NT, true>(L, nrhs, X, Y, st);
-  else launch_nt_a<NT, false>(L, nrhs, X, Y, st);
+  if (L.G->acc64) launch_nt_a<NT, false, true>(L, nrhs, X, Y, st);  // precise plans
+  else if (L.alds) launch_nt_a<NT, true, false>(L, nrhs, X, Y, st);
+  else launch_nt_a<NT, false, false>(L, nrhs, X, Y, st);
 }
 
 static bool gg_fits(const GGemm& G, int nt, int slices, bool alds) {
-  return gg_lds_total(G.K, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
+  if (alds && G.acc64) return false;
+  return gg_lds_total(G.K * G.split, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
 }
 
 static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
@@ -844,7 +926,7 @@ static std::string tune_path(const dfmm_plan_s& P, const std::vector<const GGemm
   fnv(h, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
   fnv(h, &nrhs, sizeof(nrhs));
   for (const GGemm* g : gs) {
-    const int64_t dims[5] = {g->M, g->K, g->T, g->ngroups, g->nvec};
+    const int64_t dims[7] = {g->M, g->K, g->T, g->ngroups, g->nvec, g->split, int64_t(g->acc64)};
     fnv(h, dims, sizeof(dims));
     fnv(h, g->v0_h.data(), g->v0_h.size() * sizeof(int32_t));
   }
@@ -991,7 +1073,8 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   }
 #define DFMM_LEAF(PREC, RCV)                                                                                \
   hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(),   \
-                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), \
+                     P.ptlo.as<float4>(), P.ploc.as<float4>(), P.leaf_center.as<float4>(),                     \
+                     P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),                     \
                      S.fs.as<float2>(), P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u)
   if (P.precise) {
     if (nrhs == 1) DFMM_LEAF(true, 1); else DFMM_LEAF(true, 8);

@@ -102,6 +102,9 @@ struct DevBuf {
 // pack_operator().
 struct GGemm {
   int M = 0, K = 0, T = 1;   // vector strides (rows of Y and of X vectors); per-group sizes <= these
+  int split = 1;             // 2: each operator is [T_hi | T_lo] (K doubled) and every source
+                             // vector is read twice, so the float32 rounding of T cancels
+  bool acc64 = false;        // float64 partial sums every two k-steps (precise plans)
   int64_t ngroups = 0, nvec = 0, nops = 0;
   DevBuf A;                  // operators in fragment order, op i at float4 offset aoff[i]
   DevBuf aoff;               // int64[nops]
@@ -116,6 +119,9 @@ struct GGemm {
 // Pack an M x K complex matrix (row-major, interleaved float64) into the
 // fragment order read by the GEMM kernel.
 void pack_operator(const double* Tc, int M, int K, float* out);
+// pack_operator of T (split = 1) or of [T_hi | T_lo] (split = 2), T_hi the float32
+// rounding of T and T_lo that of the remainder; out holds 2 M K split floats
+void pack_operator_split(const double* Tc, int M, int K, int split, float* out);
 
 // ---- one HF level of the plan -------------------------------------------------
 struct HFLevel {
@@ -231,7 +237,7 @@ struct dfmm_plan_s {
   double K = 0.0;
   int D = 0;       // leaf level
   int w_top = 0;
-  bool precise = false;  // eps < 1e-5: float64 distances in the near field
+  bool precise = false;  // eps < 1e-5: float64 near-field distances, split HF operators
   double plan_seconds = 0.0;
   std::string tune_dir;  // where GEMM launch choices are kept (empty: not kept)
   dfmm_info info{};
@@ -243,6 +249,7 @@ struct dfmm_plan_s {
   std::vector<std::vector<int64_t>> out_slots, in_slots;  // per level: ns x 2
   // device
   dfmm::DevBuf pthi, ptlo;       // float4[N] sorted points (hi, lo split)
+  dfmm::DevBuf ploc;             // float4[N] sorted points relative to their leaf centre
   dfmm::DevBuf perm_d;           // int32[N]
   dfmm::DevBuf leaf_start;       // int32[nleaf + 1]
   dfmm::DevBuf leaf_center;      // float4[nleaf]

@@ -71,6 +71,23 @@ void pack_operator(const double* Tc, int M, int K, float* out) {
         }
 }
 
+void pack_operator_split(const double* Tc, int M, int K, int split, float* out) {
+  if (split == 1) {
+    pack_operator(Tc, M, K, out);
+    return;
+  }
+  std::vector<double> T2(size_t(2) * M * 2 * K);
+  for (int q = 0; q < M; ++q)
+    for (int p = 0; p < K; ++p)
+      for (int c = 0; c < 2; ++c) {
+        const double v = Tc[2 * (size_t(q) * K + p) + c];
+        const double hi = double(float(v));
+        T2[2 * (size_t(q) * 2 * K + p) + c] = hi;
+        T2[2 * (size_t(q) * 2 * K + K + p) + c] = v - hi;
+      }
+  pack_operator(T2.data(), M, 2 * K, out);
+}
+
 namespace {
 
 }  // namespace
@@ -189,7 +206,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   // incoming check potentials of B); the pair outputs are summed per in-slot.
   auto build_m2l = [&](const std::vector<PairRec>& pr, double w, int R,
                        const std::vector<const Skel*>& skin, const SlotIndex* osl, const SlotIndex* isl,
-                       int64_t nin, GGemm& G, DevBuf& rs, DevBuf& ri, int64_t& ngroups, double& flops) {
+                       int64_t nin, GGemm& G, DevBuf& rs, DevBuf& ri, int64_t& ngroups, double& flops,
+                       int split) {
     // algorithmic bytes of the launch: each group's operator once (complex64,
     // unpadded), each pair's source vector read and its output written once
     double& bytes_op = info.bytes_m2l_op;
@@ -231,7 +249,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     }
     std::vector<int32_t> vdst(vsrc.size());
     for (size_t i = 0; i < vdst.size(); ++i) vdst[i] = int32_t(i);
-    std::vector<float> At(size_t(2) * R * R * ngroups, 0.0f);
+    std::vector<float> At(size_t(2) * R * R * split * ngroups, 0.0f);
     std::vector<int32_t> gmk(size_t(2) * ngroups);
     std::vector<int64_t> aoff(ngroups);
     parallel_for(ngroups, [&](int64_t gi) {
@@ -242,8 +260,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
              sz = double(std::get<2>(keys[gi])) * w;
       const int Mg = pad8(si->r), Kg = pad8(so->r);
       gmk[2 * gi] = Mg;
-      gmk[2 * gi + 1] = Kg;
-      aoff[gi] = int64_t(gi) * R * R / 2;
+      gmk[2 * gi + 1] = Kg * split;
+      aoff[gi] = int64_t(gi) * R * R * split / 2;
       std::vector<double> G(size_t(2) * so->r), T(size_t(2) * Mg * Kg, 0.0);
       for (int q = 0; q < si->r; ++q) {
         for (int p = 0; p < so->r; ++p)
@@ -261,11 +279,13 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           T[2 * (size_t(q) * Kg + j) + 1] = im;
         }
       }
-      pack_operator(T.data(), Mg, Kg, &At[size_t(2) * R * R * gi]);
+      pack_operator_split(T.data(), Mg, Kg, split, &At[size_t(2) * R * R * split * gi]);
     });
     G.M = R;
     G.K = R;
     G.T = 1;
+    G.split = split;
+    G.acc64 = P.precise;
     G.ngroups = ngroups;
     G.nvec = int64_t(vsrc.size());
     G.nops = ngroups;
@@ -285,12 +305,14 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<const Skel*> s1{&sl};
     P.lf.npairs = int64_t(pairs[D].size());
     build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nleaf, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
-              P.lf.ngroups, P.lf.flops);
+              P.lf.ngroups, P.lf.flops, 1);
     info.flops_m2l_lf = P.lf.flops;
     info.flops_m2l_level[D] = P.lf.flops;
   }
 
   // ---- HF levels ----------------------------------------------------------------
+  // precise plans split the directional operators into float32 hi + lo parts
+  const int hf_split = P.precise ? 2 : 1;
   P.hf.clear();
   P.hf.resize(e_top + 1);
   for (int e = e_top; e >= 0; --e) {
@@ -324,7 +346,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     // G(b^c + delta_o, a^{w,l}) (D^{w,l})^T (Rc x R) maps the parent's incoming
     // check potentials to the child's (c = the child skeleton of wedge l).
     int ndir = int(6 * w * w);
-    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * H.Rc, 0.0f), Md(Mu.size(), 0.0f);
+    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * H.Rc * hf_split, 0.0f), Md(Mu.size(), 0.0f);
     std::vector<char> dir_used(ndir, 0);
     for (auto& s : OS[l].list) dir_used[s.second] = 1;
     for (auto& s : IS[l].list) dir_used[s.second] = 1;
@@ -370,8 +392,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           dn[2 * (size_t(j) * Ms + q)] = re;
           dn[2 * (size_t(j) * Ms + q) + 1] = im;
         }
-      pack_operator(up.data(), Ms, Mc, &Mu[size_t(2) * id * H.R * H.Rc]);
-      pack_operator(dn.data(), Mc, Ms, &Md[size_t(2) * id * H.R * H.Rc]);
+      pack_operator_split(up.data(), Ms, Mc, hf_split, &Mu[size_t(2) * id * H.R * H.Rc * hf_split]);
+      pack_operator_split(dn.data(), Mc, Ms, hf_split, &Md[size_t(2) * id * H.R * H.Rc * hf_split]);
     });
 
     // HF-M2M and HF-L2L as pair lists: one pair per (parent slot, child), grouped
@@ -383,13 +405,13 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       // by_op[op] = list of (source vector, destination slot)
       std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv, gmk;
       std::vector<int64_t> aoff(nops);
-      for (int64_t op = 0; op < nops; ++op) aoff[op] = op * int64_t(M) * K / 2;
+      for (int64_t op = 0; op < nops; ++op) aoff[op] = op * int64_t(M) * K * hf_split / 2;
       std::vector<std::vector<int32_t>> per(ndst);
       for (int64_t op = 0; op < int64_t(by_op.size()); ++op) {
         if (by_op[op].empty()) continue;
         opsv.push_back(int32_t(op));
         gmk.push_back(opM[op]);
-        gmk.push_back(opK[op]);
+        gmk.push_back(opK[op] * hf_split);
         for (auto& sd : by_op[op]) {
           per[sd.second].push_back(int32_t(vsrc.size()));
           vsrc.push_back(sd.first);
@@ -405,6 +427,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       G.M = M;
       G.K = K;
       G.T = 1;
+      G.split = hf_split;
+      G.acc64 = P.precise;
       G.ngroups = int64_t(v0.size()) - 1;
       G.nvec = int64_t(vsrc.size());
       G.nops = nops;
@@ -467,7 +491,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<const Skel*> sp;
     for (auto& s : sk) sp.push_back(&s);
     build_m2l(pairs[l], double(w), H.R, sp, &OS[l], &IS[l], H.nin, H.m2l, H.red_start, H.red_idx, H.ngroups,
-              H.flops);
+              H.flops, hf_split);
     info.flops_m2l_hf += H.flops;
     info.flops_m2l_level[l] = H.flops;
   }
