@@ -176,9 +176,9 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
 // The complex product y = A x is done as a real product on interleaved data:
 // real row 2q (re) of A is (Re A[q][p], -Im A[q][p]) per column pair (2p, 2p+1)
 // and row 2q+1 (im) is (Im, Re); x and y stay in their natural interleaved
-// layout.  One workgroup (4 waves) handles NT*16 vector columns of one group
-// (one operator).  The 16-row M-tiles m of the group go to the waves as
-// m = wave + 4 (slice + slices t), t = 0, 1, ... (slice = blockIdx.y), and each
+// layout.  One workgroup (NW = 2 or 4 waves) handles NT*16 vector columns of
+// one group (one operator).  The 16-row M-tiles m of the group go to the waves
+// as m = wave + NW (slice + slices t), t = 0, 1, ... (slice = blockIdx.y), and each
 // wave walks its tiles one after the other, so a group's own M_g sets the work
 // and no MFMA runs on an empty tile.  The K dimension of a tile is split into
 // four quarters, one per group of 16 lanes (MFMA k index): a lane reads four
@@ -190,7 +190,6 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
 // pair (past the end it repeats the last address) so that each wait is for the
 // oldest load only.
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int GG_BS = 256;
 
 __host__ __device__ inline int gg_stride(int K) {
   int s = 2 * K;
@@ -215,7 +214,7 @@ __device__ __forceinline__ float4 swap_pair(const float4 v) {
 // k-steps (32 real products per output) the float32 MFMA sums are added into
 // float64 partial sums, so the rounding of long float32 dot products (which
 // grows with their length) stays at that of 32 terms.
-template <int NT, bool ALDS, bool ACC64>
+template <int NT, bool ALDS, bool ACC64, int NW>
 __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
                                            const int* __restrict__ gmk, int M, int K, int split,
                                            const int* __restrict__ gops, const int* __restrict__ gv0,
@@ -225,6 +224,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
   constexpr int PD = GgDepth<NT>::value;
+  constexpr int BS = 64 * NW;
   const int S4 = gg_stride(split * K) / 4;  // float4 per LDS column (split K >= every K_g)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -234,7 +234,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   const int Mg = gmk[2 * g], Kg = gmk[2 * g + 1];  // this group's operator size
   const int Q4 = Kg / 8;                 // k-steps per tile (K_g / 2 real k per quarter, 4 per step)
   const int nM = Mg / 8, nMall = M / 8;  // 16-row real M-tiles with data / in the vector stride
-  const int m0 = wave + 4 * int(blockIdx.y), mstep = 4 * int(gridDim.y);
+  const int m0 = wave + NW * int(blockIdx.y), mstep = NW * int(gridDim.y);
   const int mcnt = m0 < nM ? (nM - m0 + mstep - 1) / mstep : 0;
   const int64_t c0 = chunk_c0[blockIdx.x];
   const int vbeg = gv0[g];
@@ -261,7 +261,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   const int total = mcnt * Q4;  // flat (tile, k-step) sequence of this wave
   const int lofs = (j >> 1) * 4 + kr;
   const int64_t tbase0 = ALDS ? int64_t(wave) * tile4 : int64_t(m0) * tile4;
-  const int64_t tjump = ALDS ? int64_t(4) * tile4 : int64_t(mstep) * tile4;
+  const int64_t tjump = ALDS ? int64_t(NW) * tile4 : int64_t(mstep) * tile4;
   const float4* abase = (ALDS ? static_cast<const float4*>(as) : Aop) + lofs;
   const int64_t last = tbase0 + int64_t(mcnt - 1) * tjump + int64_t(Q4 - 1) * 32;
   int ps = 0;                 // k-step of the next prefetch within its tile
@@ -303,16 +303,16 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   {
     constexpr int UB = 4;  // loads in flight per thread
     const int nel = NC * per_col;
-    const int dcol = GG_BS / per_col, dq = GG_BS % per_col;
+    const int dcol = BS / per_col, dq = BS % per_col;
     int col = int(threadIdx.x) / per_col, q4 = int(threadIdx.x) % per_col;
-    for (int base = int(threadIdx.x); base < nel; base += UB * GG_BS) {
+    for (int base = int(threadIdx.x); base < nel; base += UB * BS) {
       float4 v[UB];
       int dst[UB];
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         dst[u] = -1;
-        if (base + u * GG_BS < nel) {
+        if (base + u * BS < nel) {
           const float4* p = colsrc[col];
           if (p) v[u] = p[q4 < pcs ? q4 : q4 - pcs];
           dst[u] = col * S4 + q4;
@@ -330,12 +330,12 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
     }
   }
   if (ALDS) {
-    const int tmax = nM > 4 * int(blockIdx.y) ? (nM - 4 * int(blockIdx.y) + mstep - 1) / mstep : 0;
+    const int tmax = nM > NW * int(blockIdx.y) ? (nM - NW * int(blockIdx.y) + mstep - 1) / mstep : 0;
     const int nel = 4 * tmax * tile4;
-    const int dblk = GG_BS / tile4, doff = GG_BS % tile4;
+    const int dblk = BS / tile4, doff = BS % tile4;
     int blk = int(threadIdx.x) / tile4, off = int(threadIdx.x) % tile4;
-    for (int idx = int(threadIdx.x); idx < nel; idx += GG_BS) {
-      const int m = (blk & 3) + 4 * int(blockIdx.y) + mstep * (blk >> 2);
+    for (int idx = int(threadIdx.x); idx < nel; idx += BS) {
+      const int m = (blk % NW) + NW * int(blockIdx.y) + mstep * (blk / NW);
       as[idx] = m < nM ? Aop[int64_t(m) * tile4 + off] : make_float4(0.f, 0.f, 0.f, 0.f);
       blk += dblk;
       off += doff;
@@ -480,13 +480,13 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 
 // The same tile engine under two names, so that kernel traces separate the
 // translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
-template <int NT, bool ALDS, bool ACC64>
-__global__ void __launch_bounds__(GG_BS) k_m2l(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64>(DFMM_GG_ARGS);
+template <int NT, bool ALDS, bool ACC64, int NW>
+__global__ void __launch_bounds__(64 * NW) k_m2l(DFMM_GG_PARAMS) {
+  ggemm_tile<NT, ALDS, ACC64, NW>(DFMM_GG_ARGS);
 }
-template <int NT, bool ALDS, bool ACC64>
-__global__ void __launch_bounds__(GG_BS) k_transfer(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64>(DFMM_GG_ARGS);
+template <int NT, bool ALDS, bool ACC64, int NW>
+__global__ void __launch_bounds__(64 * NW) k_transfer(DFMM_GG_PARAMS) {
+  ggemm_tile<NT, ALDS, ACC64, NW>(DFMM_GG_ARGS);
 }
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
@@ -717,7 +717,8 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
   const GGemm* G = nullptr;
   int nt = 4;          // 16-column tiles per workgroup
   int slices = 1;      // M-slices (grid y)
-  bool alds = false;   // operator slice staged in LDS
+  int nw = 4;          // waves per workgroup (2 or 4)
+  bool alds = false;   // operator slice staged in LDS (4-wave workgroups)
   bool m2l = false;    // translation launch (kernel name k_m2l) or tree transfer (k_transfer)
   int64_t nchunks = 0;
   DevBuf grp, col0;
@@ -754,11 +755,12 @@ static void xcd_order(std::vector<int32_t>& grp, std::vector<int32_t>& col0) {
   col0.swap(c2);
 }
 
-// Chunks and grid for one (tile width, M-slices) choice.
-static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices) {
+// Chunks and grid for one (tile width, M-slices, waves, operator-in-LDS) choice.
+static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices, int nw = 4, bool alds = false) {
   L.G = &G;
   L.nt = nt;
-  L.alds = false;
+  L.nw = nw;
+  L.alds = alds;
   std::vector<int32_t> grp, col0;
   make_chunks(G, nrhs, L.nt * 16, grp, col0);
   xcd_order(grp, col0);
@@ -785,7 +787,7 @@ static void prepare(Launch& L, const GGemm& G, int nrhs) {
 
 static size_t gg_lds_bytes(int K, int nt) { return sizeof(float) * size_t(gg_stride(K)) * size_t(nt * 16); }
 static size_t gg_lds_total(int K, int nt, int mt, bool alds) {
-  return gg_lds_bytes(K, nt) + (alds ? size_t(2048) * mt * (K / 8) : 0);
+  return gg_lds_bytes(K, nt) + (alds ? size_t(2048) * mt * (K / 8) : 0);  // 4 waves x mt tiles
 }
 
 // dynamic LDS limit of the GEMM kernels: 160 KB less 1 KB for their static LDS
@@ -795,19 +797,19 @@ constexpr int kGgDynLds = 159 * 1024;
 // M-tiles per wave of the largest group for a given number of M-slices
 static int gg_mt(const GGemm& G, int slices) { return (G.M / 8 + 4 * slices - 1) / (4 * slices); }
 
-template <int NT, bool ALDS, bool ACC64>
+template <int NT, bool ALDS, bool ACC64, int NW>
 static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
   const size_t lds = gg_lds_total(G.K * G.split, NT, gg_mt(G, L.slices), ALDS);
-  auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64> : &k_transfer<NT, ALDS, ACC64>;
+  auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64, NW> : &k_transfer<NT, ALDS, ACC64, NW>;
   static bool attr = false;
   if (!attr) {
-    for (auto k : {&k_m2l<NT, ALDS, ACC64>, &k_transfer<NT, ALDS, ACC64>})
+    for (auto k : {&k_m2l<NT, ALDS, ACC64, NW>, &k_transfer<NT, ALDS, ACC64, NW>})
       DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    kGgDynLds));
     attr = true;
   }
-  hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(GG_BS), lds, st,
+  hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(64 * NW), lds, st,
                      G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.split, G.ops.as<int>(),
                      G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs,
                      X, Y);
@@ -815,13 +817,18 @@ static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, h
 
 template <int NT>
 static void launch_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
-  if (L.G->acc64) launch_nt_a<NT, false, true>(L, nrhs, X, Y, st);  // precise plans
-  else if (L.alds) launch_nt_a<NT, true, false>(L, nrhs, X, Y, st);
-  else launch_nt_a<NT, false, false>(L, nrhs, X, Y, st);
+  if (L.nw == 2) {
+    if (L.G->acc64) launch_nt_a<NT, false, true, 2>(L, nrhs, X, Y, st);  // precise plans
+    else launch_nt_a<NT, false, false, 2>(L, nrhs, X, Y, st);
+  } else {
+    if (L.G->acc64) launch_nt_a<NT, false, true, 4>(L, nrhs, X, Y, st);
+    else if (L.alds) launch_nt_a<NT, true, false, 4>(L, nrhs, X, Y, st);
+    else launch_nt_a<NT, false, false, 4>(L, nrhs, X, Y, st);
+  }
 }
 
-static bool gg_fits(const GGemm& G, int nt, int slices, bool alds) {
-  if (alds && G.acc64) return false;
+static bool gg_fits(const GGemm& G, int nt, int slices, bool alds, int nw) {
+  if (alds && (G.acc64 || nw != 4)) return false;
   return gg_lds_total(G.K * G.split, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
 }
 
@@ -829,35 +836,34 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
   if (L.nchunks == 0) return;
   const GGemm& G = *L.G;
   if (G.T != 1) throw Error{DFMM_EUNSUPPORTED, "grouped GEMM with more than one term per group"};
-  if (!gg_fits(G, L.nt, L.slices, L.alds))
+  if (!gg_fits(G, L.nt, L.slices, L.alds, L.nw))
     throw Error{DFMM_EUNSUPPORTED, "skeleton rank too large for the GEMM kernel"};
   if (L.nt == 4) launch_nt<4>(L, nrhs, X, Y, st);
   else if (L.nt == 2) launch_nt<2>(L, nrhs, X, Y, st);
   else launch_nt<1>(L, nrhs, X, Y, st);
 }
 
-// Tile autotuner: time every (tile width, M-slices) candidate of one launch on
-// the apply stream (its output goes to the pair scratch Y only) and keep the
-// fastest.  Runs once per plan and nrhs.
+// Tile autotuner: time every (tile width, M-slices, waves per workgroup,
+// operator-in-LDS) candidate of one launch on the apply stream (its output goes
+// to the pair scratch Y only) and keep the fastest.  Runs once per plan and nrhs.
 static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   prepare(L, G, nrhs);
   if (G.ngroups == 0) return;
   const char* env = std::getenv("DFMM_AUTOTUNE");
   if (env && env[0] == '0') return;
-  int nM = G.M / 8;
-  int max_slices = std::max(1, (nM + 3) / 4);
+  const int nM = G.M / 8;
   hipEvent_t e0, e1;
   DFMM_HIP(hipEventCreate(&e0));
   DFMM_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_nt = L.nt, best_sl = L.slices;
+  int best_nt = L.nt, best_sl = L.slices, best_nw = L.nw;
   bool best_alds = false;
+  for (int nw : {4, 2})
   for (int alds = 0; alds < 2; ++alds)
   for (int nt : {1, 2, 4})
-    for (int sl = 1; sl <= std::min(max_slices, 4); ++sl) {
-      if (!gg_fits(G, nt, sl, alds != 0)) continue;
-      prepare_cfg(L, G, nrhs, nt, sl);
-      L.alds = alds != 0;
+    for (int sl = 1; sl <= std::min(std::max(1, (nM + nw - 1) / nw), 4); ++sl) {
+      if (!gg_fits(G, nt, sl, alds != 0, nw)) continue;
+      prepare_cfg(L, G, nrhs, nt, sl, nw, alds != 0);
       launch_gemm(L, nrhs, X, Y, st);  // warm-up
       DFMM_HIP(hipEventRecord(e0, st));
       for (int i = 0; i < 3; ++i) launch_gemm(L, nrhs, X, Y, st);
@@ -869,13 +875,13 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
         best = ms;
         best_nt = nt;
         best_sl = sl;
+        best_nw = nw;
         best_alds = alds != 0;
       }
     }
   DFMM_HIP(hipEventDestroy(e0));
   DFMM_HIP(hipEventDestroy(e1));
-  prepare_cfg(L, G, nrhs, best_nt, best_sl);
-  L.alds = best_alds;
+  prepare_cfg(L, G, nrhs, best_nt, best_sl, best_nw, best_alds);
 }
 
 static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
@@ -941,19 +947,19 @@ static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const
   FILE* fp = std::fopen(path.c_str(), "r");
   if (!fp) return false;
   int n = 0;
-  bool ok = std::fscanf(fp, "dfmm-tune 1 %d", &n) == 1 && n == int(ls.size());
-  std::vector<int> v(3 * size_t(n));
+  bool ok = std::fscanf(fp, "dfmm-tune 2 %d", &n) == 1 && n == int(ls.size());
+  std::vector<int> v(4 * size_t(std::max(n, 0)));
   for (int i = 0; ok && i < n; ++i) {
-    ok = std::fscanf(fp, "%d %d %d", &v[3 * i], &v[3 * i + 1], &v[3 * i + 2]) == 3;
-    const int nt = v[3 * i], sl = v[3 * i + 1];
-    ok = ok && (nt == 1 || nt == 2 || nt == 4) && sl >= 1 && sl <= 64;
+    int* c = &v[4 * size_t(i)];  // tile width, M-slices, operator in LDS, waves
+    ok = std::fscanf(fp, "%d %d %d %d", &c[0], &c[1], &c[2], &c[3]) == 4;
+    ok = ok && (c[0] == 1 || c[0] == 2 || c[0] == 4) && c[1] >= 1 && c[1] <= 64 && (c[3] == 2 || c[3] == 4);
   }
   std::fclose(fp);
   if (!ok) return false;
   for (int i = 0; i < n; ++i) {
-    prepare_cfg(*ls[i], *gs[i], nrhs, v[3 * i], v[3 * i + 1]);
-    ls[i]->alds = v[3 * i + 2] != 0;
-    if (!gg_fits(*gs[i], ls[i]->nt, ls[i]->slices, ls[i]->alds)) return false;
+    const int* c = &v[4 * size_t(i)];
+    if (!gg_fits(*gs[i], c[0], c[1], c[2] != 0, c[3])) return false;
+    prepare_cfg(*ls[i], *gs[i], nrhs, c[0], c[1], c[3], c[2] != 0);
   }
   return true;
 }
@@ -963,8 +969,8 @@ static void save_tuning(const std::string& path, const std::vector<Launch*>& ls)
   const std::string tmp = path + ".tmp";
   FILE* fp = std::fopen(tmp.c_str(), "w");
   if (!fp) return;  // the record is an optimisation only
-  std::fprintf(fp, "dfmm-tune 1 %d\n", int(ls.size()));
-  for (const Launch* L : ls) std::fprintf(fp, "%d %d %d\n", L->nt, L->slices, L->alds ? 1 : 0);
+  std::fprintf(fp, "dfmm-tune 2 %d\n", int(ls.size()));
+  for (const Launch* L : ls) std::fprintf(fp, "%d %d %d %d\n", L->nt, L->slices, L->alds ? 1 : 0, L->nw);
   const bool ok = std::fclose(fp) == 0;
   if (ok) std::rename(tmp.c_str(), path.c_str());
 }

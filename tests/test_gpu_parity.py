@@ -115,9 +115,7 @@ def test_repeat_is_bitwise_deterministic(cuda):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("eps", [1e-4, pytest.param(1e-6, marks=pytest.mark.xfail(
-    reason="measured 1.43e-6: the eps = 1e-6 skeletons alone give 9.8e-7 (float64 pass with the "
-           "library's skeletons) and the float32 pass adds about 1e-6", strict=False))])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_sphere16_full_size_sampled_targets(cuda, eps):
     """The benchmark workload (K = 16 sphere, N = 65,536) with the eps = 1e-4 and the
     eps = 1e-6 plan, on 2,048 sampled targets against the direct sum."""
