@@ -539,26 +539,23 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 }
 
 constexpr int EV_CHUNK = 256;  // source points staged in LDS at a time
-// Fast plans (eps >= 1e-5) use leaf-local float32 coordinates: every point is
-// stored relative to its leaf centre (the float64 difference rounded once), and
-// a source is moved into the target leaf's frame by the exact difference of
-// the two centres (multiples of 1/2), so a separation carries ~1e-7 absolute
-// error; the products are summed in float32 over a staged chunk and the chunk
-// sums in float64.  Precise plans form the separations in float64 from the
-// hi/lo parts of the points and sum every product in float64.
+constexpr int EV_SUM = 16;     // fast plans: products summed in float32 this many at a time
+// Separations come from the hi/lo float parts of the points: the hi parts of a
+// close pair subtract exactly, so even a pair at distance 0.01 keeps its
+// separation to ~1e-14 (leaf-local float32 coordinates would leave ~1e-8
+// absolute, i.e. 1e-6 relative in 1/r for such pairs).  Fast plans (eps >= 1e-5)
+// then work in float32 and sum EV_SUM products at a time before adding them in
+// float64; precise plans form the separations, 1/r and the products in float64.
 template <bool PRECISE, int RC>  // RC: right-hand sides per pass
 __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ phi, const float4* __restrict__ plo,
-                                                      const float4* __restrict__ ploc,
-                                                      const float4* __restrict__ lcen,
                                                       const int* __restrict__ lstart,
                                                       const int* __restrict__ nstart, const int* __restrict__ nsrc,
                                                       const float2* __restrict__ fs, const float2* __restrict__ W,
                                                       const float2* __restrict__ ulf, int R, int nrhs, int64_t N,
                                                       const int* __restrict__ perm, float2* __restrict__ u) {
-  __shared__ float4 sh[EV_CHUNK], sq[PRECISE ? EV_CHUNK : 1];
+  __shared__ float4 sh[EV_CHUNK], sq[EV_CHUNK];
   __shared__ float2 sf[EV_CHUNK * RC];
   __shared__ int nb_beg[EV_BS], nb_off[EV_BS + 1];
-  __shared__ float4 nb_dc[EV_BS];
   const int b = blockIdx.x;
   const int lane = threadIdx.x;
   const int tl = lane & 15, sl = lane >> 4;
@@ -568,15 +565,10 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
   // all neighbour ranges at once; offsets by a wave prefix sum
   {
     int beg = 0, cnt = 0;
-    float4 dc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < nn) {
       const int A = nsrc[n0 + lane];
       beg = lstart[A];
       cnt = lstart[A + 1] - beg;
-      if (!PRECISE) {
-        const float4 ca = lcen[A], cb = lcen[b];
-        dc = make_float4(ca.x - cb.x, ca.y - cb.y, ca.z - cb.z, 0.f);  // exact
-      }
     }
     int incl = cnt;
     for (int d = 1; d < EV_BS; d <<= 1) {
@@ -585,7 +577,6 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
     }
     nb_beg[lane] = beg;
     nb_off[lane] = incl - cnt;
-    nb_dc[lane] = dc;
     if (lane == EV_BS - 1) nb_off[EV_BS] = incl;
   }
   __syncthreads();
@@ -596,8 +587,7 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
       const int t = t0 + tl;
       const bool act = t < s1;
       const int tt = act ? t : s0;
-      const float4 th = PRECISE ? phi[tt] : ploc[tt];
-      const float4 tq = PRECISE ? plo[tt] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 th = phi[tt], tq = plo[tt];
       double ar[RC], ai[RC];
       // L2T: sum_q W[t][q] U_LF[leaf][k][q] over this lane's quarter of q
       {
@@ -628,13 +618,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
           for (int step = 16; step > 0; step >>= 1)
             if (kk + step < nn && nb_off[kk + step] <= gidx) kk += step;
           const int j = nb_beg[kk] + (gidx - nb_off[kk]);
-          if (PRECISE) {
-            sh[i] = phi[j];
-            sq[i] = plo[j];
-          } else {
-            const float4 pl = ploc[j], d = nb_dc[kk];
-            sh[i] = make_float4(pl.x + d.x, pl.y + d.y, pl.z + d.z, 0.f);
-          }
+          sh[i] = phi[j];
+          sq[i] = plo[j];
           for (int k = 0; k < nk; ++k) sf[i * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
         }
         __syncthreads();
@@ -655,25 +640,29 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
             }
           }
         } else {
-          float cr[RC], ci[RC];
+          for (int i0 = sl; i0 < fill; i0 += 4 * EV_SUM) {
+            const int i1 = min(fill, i0 + 4 * EV_SUM);
+            float cr[RC], ci[RC];
 #pragma unroll
-          for (int k = 0; k < RC; ++k) cr[k] = ci[k] = 0.f;
-          for (int i = sl; i < fill; i += 4) {
-            const float4 h = sh[i];
-            const float2 gg = green_f(th.x - h.x, th.y - h.y, th.z - h.z);
+            for (int k = 0; k < RC; ++k) cr[k] = ci[k] = 0.f;
+            for (int i = i0; i < i1; i += 4) {
+              const float4 h = sh[i], l = sq[i];
+              const float2 gg = green_f((th.x - h.x) + (tq.x - l.x), (th.y - h.y) + (tq.y - l.y),
+                                        (th.z - h.z) + (tq.z - l.z));
 #pragma unroll
-            for (int k = 0; k < RC; ++k) {
-              if (k < nk) {
-                const float2 fk = sf[i * RC + k];
-                cr[k] = fmaf(gg.x, fk.x, fmaf(-gg.y, fk.y, cr[k]));
-                ci[k] = fmaf(gg.x, fk.y, fmaf(gg.y, fk.x, ci[k]));
+              for (int k = 0; k < RC; ++k) {
+                if (k < nk) {
+                  const float2 fk = sf[i * RC + k];
+                  cr[k] = fmaf(gg.x, fk.x, fmaf(-gg.y, fk.y, cr[k]));
+                  ci[k] = fmaf(gg.x, fk.y, fmaf(gg.y, fk.x, ci[k]));
+                }
               }
             }
-          }
 #pragma unroll
-          for (int k = 0; k < RC; ++k) {
-            ar[k] += cr[k];
-            ai[k] += ci[k];
+            for (int k = 0; k < RC; ++k) {
+              ar[k] += cr[k];
+              ai[k] += ci[k];
+            }
           }
         }
       }
@@ -1079,8 +1068,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   }
 #define DFMM_LEAF(PREC, RCV)                                                                                \
   hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(),   \
-                     P.ptlo.as<float4>(), P.ploc.as<float4>(), P.leaf_center.as<float4>(),                     \
-                     P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),                     \
+                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), \
                      S.fs.as<float2>(), P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u)
   if (P.precise) {
     if (nrhs == 1) DFMM_LEAF(true, 1); else DFMM_LEAF(true, 8);

@@ -249,7 +249,6 @@ struct dfmm_plan_s {
   std::vector<std::vector<int64_t>> out_slots, in_slots;  // per level: ns x 2
   // device
   dfmm::DevBuf pthi, ptlo;       // float4[N] sorted points (hi, lo split)
-  dfmm::DevBuf ploc;             // float4[N] sorted points relative to their leaf centre
   dfmm::DevBuf perm_d;           // int32[N]
   dfmm::DevBuf leaf_start;       // int32[nleaf + 1]
   dfmm::DevBuf leaf_center;      // float4[nleaf]

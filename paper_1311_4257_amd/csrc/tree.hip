@@ -101,15 +101,7 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   }
   P.max_leaf_pts = mx;
   P.leaf_center.upload(lc);
-  // every point relative to its leaf centre (float64 difference, rounded once)
-  std::vector<float> loc(4 * size_t(N), 0.0f);
-  for (size_t b = 0; b < LL.key.size(); ++b) {
-    const double c[3] = {(double(LL.cx[b]) + 0.5) * 0.5 - K / 2.0, (double(LL.cy[b]) + 0.5) * 0.5 - K / 2.0,
-                         (double(LL.cz[b]) + 0.5) * 0.5 - K / 2.0};
-    for (int64_t s = LL.start[b]; s < LL.end[b]; ++s)
-      for (int a = 0; a < 3; ++a) loc[4 * s + a] = float(T.pts[3 * s + a] - c[a]);
-  }
-  P.ploc.upload(loc);
+
 }
 
 }  // namespace dfmm

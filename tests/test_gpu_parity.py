@@ -106,6 +106,24 @@ def test_nrhs_batch_equals_single(cuda):
         assert np.array_equal(u1[0], ub[j]), j
 
 
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_near_field_only_close_pairs(cuda, eps):
+    """Points in two adjacent leaves only (so every pair is near field), with
+    pairs 1e-3 .. 1e-2 apart: the pass is the direct sum up to float32 rounding."""
+    rng = np.random.default_rng(11)
+    a = rng.uniform(0.02, 0.48, (120, 3)) + np.array([0.0, 0.0, 0.0])
+    b = rng.uniform(0.02, 0.48, (120, 3)) + np.array([0.5, 0.0, 0.0])
+    close = a[:40] + rng.normal(0, 1, (40, 3)) * 3e-3       # close partners of the first 40 of a
+    pts = np.concatenate([a, b, np.clip(close, 0.001, 0.499)])
+    f = (rng.standard_normal((1, len(pts))) + 1j * rng.standard_normal((1, len(pts)))).astype(np.complex128)
+    plan = _dfmm().Plan(pts, 4.0, eps=eps, cache_dir=CACHE, device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    ref = direct_sum(pts, f, np.arange(len(pts)))
+    err = rel_l2(u, ref)
+    print(f"near field only, eps={eps:g}: rel L2 {err:.2e}")
+    assert err < 1e-6
+
+
 def test_repeat_is_bitwise_deterministic(cuda):
     pts, f, cfg = workloads.make_config("sphere4", N=2048)
     plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oracle_opset(1e-3, 1)), device=0)
