@@ -125,7 +125,10 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * tuning record in the cache directory if one matches, else by timing the
  * candidate shapes on `stream` (waits for them; DFMM_AUTOTUNE=0 takes the
  * default shapes instead).  Later applies with the same nrhs allocate nothing
- * and do not wait.  Applies on one plan must not run concurrently. */
+ * and do not wait.  The near-field sum runs on a second stream owned by the
+ * plan (default priority), forked from and joined back into `stream` with
+ * events, so the apply is complete when `stream` reaches its end.  Applies on
+ * one plan must not run concurrently. */
 int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
 
 void dfmm_destroy(dfmm_plan_t plan);
@@ -186,9 +189,12 @@ int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes)
  * applies, and restarts the recording.  Stages, in order:
  *   0 permute-in, 1 S2M, 2 HF-M2M, 3 HF-M2L (grouped GEMM), 4 HF-M2L reduction,
  *   5 HF-L2L, 6 LF-M2L (grouped GEMM), 7 LF-M2L reduction,
- *   8 leaf evaluation (L2T + near field + permute-out), 9 zero fill.
+ *   8 leaf evaluation (L2T, adds the near field, permute-out), 9 zero fill,
+ *   10 near field (on the plan's second stream, concurrent with stages 1-7).
+ * Stages 0-9 are intervals between launches on the apply stream (they add up
+ * to the apply time); stage 10 overlaps them.
  * *n receives the number of stages written (<= cap). */
-enum { DFMM_NUM_STAGES = 10 };
+enum { DFMM_NUM_STAGES = 11 };
 int dfmm_set_timing(dfmm_plan_t plan, int applies);
 int dfmm_stage_times(dfmm_plan_t plan, double* ms, int64_t* launches, int cap, int* n);
 

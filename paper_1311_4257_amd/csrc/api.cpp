@@ -311,8 +311,9 @@ void dfmm_destroy(dfmm_plan_t plan) {
   plan->ws = nullptr;
   delete plan->timer;
   plan->timer = nullptr;
+  const int dev = plan->device;
   delete plan;
-  if (cur != 0) (void)hipSetDevice(cur);
+  if (cur != dev) (void)hipSetDevice(cur);
 }
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info) {

@@ -546,13 +546,15 @@ constexpr int EV_SUM = 16;     // fast plans: products summed in float32 this ma
 // absolute, i.e. 1e-6 relative in 1/r for such pairs).  Fast plans (eps >= 1e-5)
 // then work in float32 and sum EV_SUM products at a time before adding them in
 // float64; precise plans form the separations, 1/r and the products in float64.
+// The near field of every target goes to unear (float64, sorted order); it
+// needs only the permuted densities, so it runs on a second stream beside the
+// far-field passes, and k_l2t adds it to the far field.
 template <bool PRECISE, int RC>  // RC: right-hand sides per pass
 __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ phi, const float4* __restrict__ plo,
                                                       const int* __restrict__ lstart,
                                                       const int* __restrict__ nstart, const int* __restrict__ nsrc,
-                                                      const float2* __restrict__ fs, const float2* __restrict__ W,
-                                                      const float2* __restrict__ ulf, int R, int nrhs, int64_t N,
-                                                      const int* __restrict__ perm, float2* __restrict__ u) {
+                                                      const float2* __restrict__ fs, int nrhs, int64_t N,
+                                                      double2* __restrict__ unear) {
   __shared__ float4 sh[EV_CHUNK], sq[EV_CHUNK];
   __shared__ float2 sf[EV_CHUNK * RC];
   __shared__ int nb_beg[EV_BS], nb_off[EV_BS + 1];
@@ -589,24 +591,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
       const int tt = act ? t : s0;
       const float4 th = phi[tt], tq = plo[tt];
       double ar[RC], ai[RC];
-      // L2T: sum_q W[t][q] U_LF[leaf][k][q] over this lane's quarter of q
-      {
-        float2 acc[RC];
 #pragma unroll
-        for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
-#pragma unroll 4
-        for (int q = sl; q < R; q += 4) {
-          const float2 w = W[int64_t(tt) * R + q];
-#pragma unroll
-          for (int k = 0; k < RC; ++k)
-            if (k < nk) cfma(acc[k], w, ulf[(int64_t(b) * nrhs + k0 + k) * R + q]);
-        }
-#pragma unroll
-        for (int k = 0; k < RC; ++k) {
-          ar[k] = acc[k].x;
-          ai[k] = acc[k].y;
-        }
-      }
+      for (int k = 0; k < RC; ++k) ar[k] = ai[k] = 0.0;
       // near field: the adjacent leaves' points are staged in LDS chunk by chunk
       for (int base = 0; base < total; base += EV_CHUNK) {
         const int fill = min(EV_CHUNK, total - base);
@@ -673,10 +659,46 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
         ar[k] += shfl_xor_d(ar[k], 32);
         ai[k] += shfl_xor_d(ai[k], 32);
       }
-      if (act && sl == 0) {
-        const int64_t o = perm[t];
-        for (int k = 0; k < nk; ++k) u[int64_t(k0 + k) * N + o] = make_float2(float(ar[k]), float(ai[k]));
-      }
+      if (act && sl == 0)
+        for (int k = 0; k < nk; ++k) unear[int64_t(k0 + k) * N + t] = make_double2(ar[k], ai[k]);
+    }
+  }
+}
+
+// L2T and the output: u[k][perm[t]] = sum_q W[t][q] U_LF[leaf(t)][k][q] + unear[k][t].
+// 16 lanes per target read 16 consecutive q at a time (128-byte runs); a
+// lane keeps its W values over the right-hand sides.
+constexpr int L2T_BS = 256;
+constexpr int L2T_QMAX = 16;  // W values per lane: R <= 16 * L2T_QMAX
+__global__ void __launch_bounds__(L2T_BS) k_l2t(const float2* __restrict__ W, const float2* __restrict__ ulf,
+                                                 const int* __restrict__ leaf_of, const double2* __restrict__ unear,
+                                                 const int* __restrict__ perm, int R, int nrhs, int64_t N,
+                                                 float2* __restrict__ u) {
+  const int64_t t = (int64_t(blockIdx.x) * L2T_BS + threadIdx.x) >> 4;
+  const int l = threadIdx.x & 15;
+  const bool act = t < N;
+  const int64_t tt = act ? t : 0;
+  const int leaf = leaf_of[tt];
+  float2 w[L2T_QMAX];
+  const int nq = (R - l + 15) / 16;  // this lane's q = l, l + 16, ...
+#pragma unroll
+  for (int i = 0; i < L2T_QMAX; ++i)
+    if (i < nq) w[i] = W[tt * R + l + 16 * i];
+  const int64_t o = act ? perm[tt] : 0;
+  for (int k = 0; k < nrhs; ++k) {
+    const float2* ur = ulf + (int64_t(leaf) * nrhs + k) * R;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < L2T_QMAX; ++i)
+      if (i < nq) cfma(acc, w[i], ur[l + 16 * i]);
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) {
+      acc.x += __shfl_xor(acc.x, m, 16);
+      acc.y += __shfl_xor(acc.y, m, 16);
+    }
+    if (act && l == 0) {
+      const double2 nf = unear[int64_t(k) * N + tt];
+      u[int64_t(k) * N + o] = make_float2(float(double(acc.x) + nf.x), float(double(acc.y) + nf.y));
     }
   }
 }
@@ -716,9 +738,23 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
 struct ApplyState {
   int nrhs = 0;
   std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
-  DevBuf fs, flf, ulf, Y;
+  DevBuf fs, flf, ulf, Y, unear;
   std::vector<Launch> m2m, l2l, m2l;          // per HF level
   Launch lf_m2l;
+  // second stream for the near field (default priority) and its fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  void ensure_side() {
+    if (side) return;
+    DFMM_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    DFMM_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    DFMM_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
+  ~ApplyState() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 void destroy_apply_state(ApplyState* s) { delete s; }
@@ -878,6 +914,7 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   S.nrhs = nrhs;
   int64_t N = P.N;
   S.fs.alloc(sizeof(float2) * N * nrhs);
+  S.unear.alloc(sizeof(double2) * N * nrhs);
   S.flf.alloc(sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs);
   S.ulf.alloc(sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs);
   int64_t ymax = P.lf.npairs * P.lf.R;
@@ -1009,6 +1046,24 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, f, S.fs.as<float2>(),
                      P.perm_d.as<int>(), N, nrhs);
   mark(ST_PERMUTE);
+  // the near field needs only the permuted densities: it runs on the side
+  // stream while the far-field passes run on st
+  S.ensure_side();
+  DFMM_HIP(hipEventRecord(S.fork, st));
+  DFMM_HIP(hipStreamWaitEvent(S.side, S.fork, 0));
+  if (tm) tm->side_begin(S.side);
+#define DFMM_NEAR(PREC, RCV)                                                                                   \
+  hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, S.side, P.pthi.as<float4>(), \
+                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),    \
+                     S.fs.as<float2>(), nrhs, N, S.unear.as<double2>())
+  if (P.precise) {
+    if (nrhs == 1) DFMM_NEAR(true, 1); else DFMM_NEAR(true, 8);
+  } else {
+    if (nrhs == 1) DFMM_NEAR(false, 1); else DFMM_NEAR(false, 8);
+  }
+#undef DFMM_NEAR
+  if (tm) tm->side_mark(ST_NEAR, S.side);
+  DFMM_HIP(hipEventRecord(S.join, S.side));
   if (nrhs == 1)
     hipLaunchKernelGGL(k_s2m<1>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
@@ -1066,16 +1121,11 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
                        P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, 1, S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
-#define DFMM_LEAF(PREC, RCV)                                                                                \
-  hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, st, P.pthi.as<float4>(),   \
-                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), \
-                     S.fs.as<float2>(), P.lf.W.as<float2>(), S.ulf.as<float2>(), Rl, nrhs, N, P.perm_d.as<int>(), u)
-  if (P.precise) {
-    if (nrhs == 1) DFMM_LEAF(true, 1); else DFMM_LEAF(true, 8);
-  } else {
-    if (nrhs == 1) DFMM_LEAF(false, 1); else DFMM_LEAF(false, 8);
-  }
-#undef DFMM_LEAF
+  DFMM_HIP(hipStreamWaitEvent(st, S.join, 0));
+  if (Rl > 16 * L2T_QMAX) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank too large for L2T"};
+  hipLaunchKernelGGL(k_l2t, dim3(nblocks(N * 16, L2T_BS)), dim3(L2T_BS), 0, st, P.lf.W.as<float2>(),
+                     S.ulf.as<float2>(), P.leaf_of.as<int>(), S.unear.as<double2>(), P.perm_d.as<int>(), Rl, nrhs, N,
+                     u);
   mark(ST_LEAF);
   DFMM_HIP(hipGetLastError());
 }
@@ -1098,17 +1148,34 @@ void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, c
 // ---- stage timer -------------------------------------------------------------------
 bool StageTimer::begin_apply(hipStream_t st) {
   if (used + kPerApply > pool.size()) return false;
-  apply_begin.push_back(used);
   DFMM_HIP(hipEventRecord(pool[used], st));
-  tags.push_back(-1);
-  ++used;
+  stage.push_back(-1);
+  from.push_back(used);
+  last_main = used++;
   return true;
 }
 
-void StageTimer::mark(int stage, hipStream_t st) {
+void StageTimer::mark(int st_id, hipStream_t st) {
   if (used >= pool.size()) return;
   DFMM_HIP(hipEventRecord(pool[used], st));
-  tags.push_back(stage);
+  stage.push_back(st_id);
+  from.push_back(last_main);
+  last_main = used++;
+}
+
+void StageTimer::side_begin(hipStream_t side) {
+  if (used >= pool.size()) return;
+  DFMM_HIP(hipEventRecord(pool[used], side));
+  stage.push_back(-1);
+  from.push_back(used);
+  side_from = used++;
+}
+
+void StageTimer::side_mark(int st_id, hipStream_t side) {
+  if (used >= pool.size()) return;
+  DFMM_HIP(hipEventRecord(pool[used], side));
+  stage.push_back(st_id);
+  from.push_back(side_from);
   ++used;
 }
 
@@ -1120,17 +1187,16 @@ void StageTimer::collect(double* ms, int64_t* launches) {
   if (used == 0) return;
   // the events carry no system-scope fence: wait for the device, then read them
   DFMM_HIP(hipDeviceSynchronize());
-  DFMM_HIP(hipEventSynchronize(pool[used - 1]));
-  for (size_t i = 1; i < used; ++i) {
-    if (tags[i] < 0) continue;  // first event of an apply
+  for (size_t i = 0; i < used; ++i) {
+    if (stage[i] < 0) continue;
     float t = 0.f;
-    DFMM_HIP(hipEventElapsedTime(&t, pool[i - 1], pool[i]));
-    ms[tags[i]] += t;
-    launches[tags[i]] += 1;
+    DFMM_HIP(hipEventElapsedTime(&t, pool[from[i]], pool[i]));
+    ms[stage[i]] += t;
+    launches[stage[i]] += 1;
   }
   used = 0;
-  tags.clear();
-  apply_begin.clear();
+  stage.clear();
+  from.clear();
 }
 
 StageTimer::StageTimer(int applies) {

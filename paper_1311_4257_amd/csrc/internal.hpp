@@ -208,20 +208,24 @@ void destroy_apply_state(ApplyState* s);
 
 // Stages reported by dfmm_stage_times (same order as in include/dfmm.h).
 enum { ST_PERMUTE = 0, ST_S2M, ST_M2M, ST_M2L, ST_REDUCE, ST_L2L, ST_LF_M2L, ST_LF_REDUCE, ST_LEAF,
-       ST_ZERO, ST_COUNT };
+       ST_ZERO, ST_NEAR, ST_COUNT };
 
 // HIP events recorded on the apply stream after every launch, for a bounded
 // number of applies; no host synchronisation until collect().
 struct StageTimer {
   static constexpr size_t kPerApply = 64;
   std::vector<hipEvent_t> pool;
-  std::vector<int> tags;            // stage of the interval that ends at each event (-1: apply start)
-  std::vector<size_t> apply_begin;
+  std::vector<int> stage;           // stage of the interval that ends at each event (-1: none)
+  std::vector<size_t> from;         // the event where that interval starts
   size_t used = 0;
+  size_t last_main = 0;             // latest event on the apply stream
+  size_t side_from = 0;             // start event of the open side-stream interval
   explicit StageTimer(int applies);
   ~StageTimer();
   bool begin_apply(hipStream_t st);
-  void mark(int stage, hipStream_t st);
+  void mark(int stage, hipStream_t st);            // interval since the previous apply-stream event
+  void side_begin(hipStream_t side);               // opens an interval on the side stream
+  void side_mark(int stage, hipStream_t side);     // closes it
   void collect(double* ms, int64_t* launches);  // sums per stage, then resets
 };
 void run_apply(dfmm_plan_s& P, const void* f, void* u, int nrhs, hipStream_t st);
@@ -251,6 +255,7 @@ struct dfmm_plan_s {
   dfmm::DevBuf pthi, ptlo;       // float4[N] sorted points (hi, lo split)
   dfmm::DevBuf perm_d;           // int32[N]
   dfmm::DevBuf leaf_start;       // int32[nleaf + 1]
+  dfmm::DevBuf leaf_of;          // int32[N]: leaf of each sorted point
   dfmm::DevBuf leaf_center;      // float4[nleaf]
   dfmm::DevBuf near_start, near_src;  // CSR over leaves
   int max_leaf_pts = 0;

@@ -101,6 +101,10 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   }
   P.max_leaf_pts = mx;
   P.leaf_center.upload(lc);
+  std::vector<int32_t> lof(static_cast<size_t>(N));
+  for (size_t b = 0; b < LL.key.size(); ++b)
+    for (int64_t s = LL.start[b]; s < LL.end[b]; ++s) lof[size_t(s)] = int32_t(b);
+  P.leaf_of.upload(lof);
 
 }
 

@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2l", "lf_reduce",
-          "leaf_eval", "zero"]
+          "leaf_eval", "zero", "near_field"]
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
 

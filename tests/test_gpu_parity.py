@@ -124,6 +124,31 @@ def test_near_field_only_close_pairs(cuda, eps):
     assert err < 1e-6
 
 
+def test_back_to_back_applies_on_a_stream(cuda):
+    """Applies enqueued back to back (no host wait) on a non-default stream give
+    bitwise the results of separately synchronized applies: the near-field
+    stream forks from and joins into the caller's stream."""
+    import torch
+
+    pts, f, cfg = workloads.make_config("sphere4")
+    plan = _dfmm().Plan(pts, cfg["K"], eps=1e-4, cache_dir=CACHE, device=0)
+    rng = np.random.default_rng(5)
+    fs = [_to_dev((rng.standard_normal(f.shape) + 1j * rng.standard_normal(f.shape)), cuda) for _ in range(4)]
+    ref = []
+    for x in fs:
+        ref.append(plan.apply(x).cpu().numpy())
+        torch.cuda.synchronize()
+    stream = torch.cuda.Stream(device=cuda)
+    us = [torch.empty_like(x) for x in fs]
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            for x, u in zip(fs, us):
+                plan.apply(x, u, stream)
+    stream.synchronize()
+    for u, r in zip(us, ref):
+        assert np.array_equal(u.cpu().numpy(), r)
+
+
 def test_repeat_is_bitwise_deterministic(cuda):
     pts, f, cfg = workloads.make_config("sphere4", N=2048)
     plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oracle_opset(1e-3, 1)), device=0)
