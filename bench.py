@@ -182,6 +182,18 @@ def main() -> int:
         plan.apply(fd, u, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same applies replayed from a HIP graph (one capture, K replays)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.apply(fd, u)
+    graph.replay()
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - tg0) * 1e3 / args.steps
+    del graph
     # the same number of steps again with the stage events (timing-only HIP
     # events recorded on the apply stream between launches): per-kernel durations
     plan.set_timing(args.steps)
@@ -226,6 +238,15 @@ def main() -> int:
         if rec.get("source_sha1") == gemm_source_hash() and nrhs == 1:
             traffic = rec["bytes_per_launch"]
     per_stage = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]}
+    # near-field sum: point pairs (self pairs included, they contribute 0), flops
+    # counted as 14 + 3 transcendentals per pair plus a complex MAC (8) per rhs
+    nf_sec = stages["near_field"][0] * 1e-3 / args.steps
+    nf_pairs = info.near_point_pairs
+    nf_flops = nf_pairs * (17 + 8 * nrhs)
+    near = {"kernel": "k_leaf_eval (near field, second stream, overlapping the far-field passes)",
+            "point_pairs": nf_pairs, "ms": nf_sec * 1e3, "pairs_per_s": nf_pairs / nf_sec,
+            "tflops": nf_flops / nf_sec / 1e12, "frac_fp32_vector_unpacked": nf_flops / nf_sec / 1e12 / 78.6,
+            "frac_fp32_vector_packed": nf_flops / nf_sec / 1e12 / 157.3}
 
     eps_s = f"{eps:.0e}".replace("e-0", "e-")
     out = {
@@ -248,6 +269,7 @@ def main() -> int:
         "accuracy_ok": bool(err <= eps),
         "stage_ms": per_stage,
         "ms_per_step_with_stage_events": ms_events,
+        "ms_per_step_graph_replay": ms_graph,
         "roofline": {
             "bound": "mfma" if mfma_bound else "hbm",
             "kernel": "k_m2l (grouped M2L GEMM, HF + LF launches)",
@@ -263,6 +285,7 @@ def main() -> int:
             "flops_per_level": {f"w={info.K / 2 ** l:g}": info.flops_m2l_level[l] * nrhs
                                 for l in range(info.depth + 1) if info.flops_m2l_level[l] > 0},
         },
+        "near_field": near,
         "plan_seconds": info.plan_seconds,
     }
     if not args.no_cpu_baseline and args.workload == "sphere16":

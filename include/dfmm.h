@@ -128,7 +128,11 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * and do not wait.  The near-field sum runs on a second stream owned by the
  * plan (default priority), forked from and joined back into `stream` with
  * events, so the apply is complete when `stream` reaches its end.  Applies on
- * one plan must not run concurrently. */
+ * one plan must not run concurrently.  An apply may be captured into a HIP
+ * graph (stream capture on `stream`) once an uncaptured apply with the same
+ * nrhs has run on the plan; the captured apply reads f and writes u at the
+ * addresses given at capture.  Capturing before that returns DFMM_EINVAL;
+ * stage timing is off inside a capture. */
 int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
 
 void dfmm_destroy(dfmm_plan_t plan);

@@ -1026,6 +1026,13 @@ static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, hipStream_t s
 }
 
 void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t st) {
+  // under stream capture only launches, event records and event waits may be
+  // issued: the workspace, the tuning and the side stream must already exist
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  DFMM_HIP(hipStreamIsCapturing(st, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (capturing && (!P.ws || P.ws->nrhs != nrhs || !P.ws->side))
+    throw Error{DFMM_EINVAL, "dfmm_apply under stream capture needs an earlier uncaptured apply with the same nrhs"};
   if (!P.ws) P.ws = new ApplyState();
   ApplyState& S = *P.ws;
   if (S.nrhs != nrhs) {
@@ -1039,7 +1046,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   const int Rl = P.lf.R;
   const int e_top = int(P.hf.size()) - 1;
   StageTimer* tm = P.timer;
-  if (tm && !tm->begin_apply(st)) tm = nullptr;
+  if (tm && (capturing || !tm->begin_apply(st))) tm = nullptr;  // no stage events inside a graph
   auto mark = [&](int stage) {
     if (tm) tm->mark(stage, st);
   };

@@ -149,6 +149,46 @@ def test_back_to_back_applies_on_a_stream(cuda):
         assert np.array_equal(u.cpu().numpy(), r)
 
 
+def test_graph_captured_apply_replays_match_eager(cuda):
+    """An apply captured into a HIP graph (after one uncaptured apply with the same
+    nrhs) replays bitwise equal to eager applies, with eager work and host
+    synchronisation between the replays; capturing first is refused."""
+    import torch
+
+    pts, _, cfg = workloads.make_config("sphere4")
+    N = pts.shape[0]
+    plan = _dfmm().Plan(pts, cfg["K"], eps=1e-4, cache_dir=CACHE, device=0)
+    rng = np.random.default_rng(7)
+
+    def dens():
+        return _to_dev(rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N)), cuda)
+
+    x = dens()
+    u = torch.empty_like(x)
+    g0 = torch.cuda.CUDAGraph()
+    with pytest.raises(_dfmm().DfmmError):
+        with torch.cuda.graph(g0):
+            u.zero_()
+            plan.apply(x, u)
+    xs = [dens() for _ in range(3)]
+    eager = []
+    for xx in xs:
+        eager.append(plan.apply(xx).cpu().numpy())
+        torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.apply(x, u)
+    for _ in range(2):
+        for xx, ref in zip(xs, eager):
+            x.copy_(xx)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(u.cpu().numpy(), ref)
+    # the eager path still works after the capture
+    assert np.array_equal(plan.apply(xs[0]).cpu().numpy(), eager[0])
+
+
 def test_repeat_is_bitwise_deterministic(cuda):
     pts, f, cfg = workloads.make_config("sphere4", N=2048)
     plan = _dfmm().Plan(pts, cfg["K"], opset=inject(oracle_opset(1e-3, 1)), device=0)
