@@ -133,6 +133,126 @@ def cpu_baseline(pts, f, K, eps_tau, n_sample=16384):
     }
 
 
+def _log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def serving_bench(args) -> int:
+    """Continuous batching over 6 resident plans against the single-request form.
+
+    Requests: plan uniform over the 6, nrhs uniform over {1, 4, 16}, complex64
+    N(0, 1) densities (seed 505).  Both forms run the same plans (eps = 1e-4,
+    float32 apply) on the same requests: first with every request queued at
+    t = 0 (saturation throughput), then with Poisson arrivals at 0.5, 0.8 and
+    0.95 of the single-request form's measured capacity (p50/p99 latency).
+    """
+    import numpy as np
+    import torch
+
+    from oracle.kernel import direct_sum, rel_l2
+    from paper_1311_4257_amd import dfmm, workloads
+    from paper_1311_4257_amd.serve import Request, Server, latency_stats
+
+    dev = torch.device("cuda:0")
+    eps = 1e-4 if args.eps is None else args.eps
+    plans, names, pts_all, plan_s = [], [], [], []
+    for name, kind, K, N, seed in workloads.SERVING_PLANS:
+        pts = workloads.serving_points(kind, K, N, seed)
+        t = time.perf_counter()
+        plans.append(dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0))
+        plan_s.append(time.perf_counter() - t)
+        names.append(name)
+        pts_all.append(pts)
+        _log(f"plan {name}: N={N} K={K:g} {plan_s[-1]:.2f} s")
+    # accuracy of each plan alone against the direct sum (256 sampled targets)
+    acc = {}
+    for p, plan in enumerate(plans):
+        f = workloads.densities(plan.N, 1, 600 + p)
+        u = plan.apply(torch.from_numpy(f.astype(np.complex64)).to(dev)).cpu().numpy()
+        tg = workloads.sample_targets(plan.N, 256, 700 + p)
+        acc[names[p]] = rel_l2(u.astype(np.complex128)[:, tg], direct_sum(pts_all[p], f, tg))
+        _log(f"accuracy {names[p]}: {acc[names[p]]:.2e}")
+
+    n = args.requests
+    pidx, nrhs, gaps = workloads.serving_mix(n, len(plans), 505)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(505)
+    reqs = []
+    for i in range(n):
+        p, k = int(pidx[i]), int(nrhs[i])
+        f = torch.complex(torch.randn((k, plans[p].N), generator=gen, device=dev),
+                          torch.randn((k, plans[p].N), generator=gen, device=dev))
+        reqs.append(Request(i, p, f, torch.empty_like(f), 0.0))
+    work = sum(plans[r.plan].N * r.nrhs for r in reqs)
+    budget = 200 << 30
+    single = Server(plans, budget, mode="single")
+    batched = Server(plans, budget, max_batch_rhs=32, mode="batched")
+    single.warm([1, 4, 16])
+    batched.warm([1, 2, 4, 8, 16, 32])
+    _log(f"warm: footprint {batched.footprint() / 2**30:.1f} GiB of {budget / 2**30:.0f} GiB")
+
+    def run(srv, arrivals):
+        for r, t in zip(reqs, arrivals):
+            r.arrival, r.done = float(t), float("nan")
+        span = srv.run(reqs)
+        st = latency_stats(reqs)
+        st["matvecs_per_s"] = work / span
+        st["span_s"] = span
+        st["passes"] = len(srv.batches)
+        return st
+
+    out_runs = {}
+    zero = np.zeros(n)
+    out_runs["saturation"] = {"single": run(single, zero), "batched": run(batched, zero)}
+    _log(f"saturation: {json.dumps(out_runs['saturation'])}")
+    # the same requests alone and in the mix: compare a sample of batched results
+    diffs = []
+    for r in reqs[:: max(1, n // 60)]:
+        a = plans[r.plan].apply(r.f)
+        diffs.append(float(torch.linalg.norm(r.u - a) / torch.linalg.norm(a)))
+    cap_req = n / out_runs["saturation"]["single"]["span_s"]
+    loads = []
+    for frac in (0.5, 0.8, 0.95):
+        rate = frac * cap_req
+        arr = np.cumsum(gaps) / rate
+        arr -= arr[0]
+        row = {"load": frac, "rate_req_per_s": rate, "single": run(single, arr), "batched": run(batched, arr)}
+        loads.append(row)
+        _log(f"load {frac}: {json.dumps(row)}")
+    sat = out_runs["saturation"]
+    line = {
+        "metric": "FMM matvecs/s (N*nrhs/s) at 1e-4 rel err vs direct sum; p50/p99 serve latency",
+        "value": sat["batched"]["matvecs_per_s"],
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": sat["batched"]["span_s"] * 1e3 / n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving mix: {n} requests over 6 resident plans "
+                               f"({', '.join(names)}), nrhs uniform over {{1, 4, 16}}, complex64 N(0,1) "
+                               f"densities (seed 505), eps={eps:g}; value = continuous-batching throughput "
+                               f"with every request queued at t=0",
+                   "plans": [{"name": nm, "N": pl.N, "plan_s": round(ps, 3), "rel_l2_err": acc[nm]}
+                             for nm, pl, ps in zip(names, plans, plan_s)],
+                   "max_batch_rhs": 32, "hbm_budget_gib": budget / 2 ** 30},
+        "serving": {
+            "saturation": sat,
+            "batched_over_single": sat["batched"]["matvecs_per_s"] / sat["single"]["matvecs_per_s"],
+            "single_capacity_req_per_s": cap_req,
+            "poisson_loads": loads,
+            "mix_vs_alone_max_rel_diff": max(diffs),
+            "footprint_gib": batched.footprint() / 2 ** 30,
+        },
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +264,8 @@ def main() -> int:
                     help="the K=16 sphere (default, the headline line) or the K=32 ellipsoid with 32 rhs")
     ap.add_argument("--eps", type=float, default=None, help="plan eps (default: the workload's)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--serve", action="store_true", help="the serving mix instead of one workload")
+    ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
     args = ap.parse_args()
     if args.traffic_summary:
         rec = traffic_summary(*args.traffic_summary)
@@ -156,6 +278,9 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
+
+    if args.serve:
+        return serving_bench(args)
 
     import numpy as np
     import torch

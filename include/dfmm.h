@@ -120,12 +120,13 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * data (interleaved float re, im), layout [nrhs][N], in the caller's original
  * point order; u is overwritten; f and u must not overlap.  Work is enqueued
  * on `stream` (a hipStream_t; null = the null stream) and the call returns
- * without waiting.  The first apply with a new nrhs sizes the plan's workspace
- * for it (synchronous allocation) and fixes the GEMM launch shapes: from the
- * tuning record in the cache directory if one matches, else by timing the
- * candidate shapes on `stream` (waits for them; DFMM_AUTOTUNE=0 takes the
- * default shapes instead).  Later applies with the same nrhs allocate nothing
- * and do not wait.  The near-field sum runs on a second stream owned by the
+ * without waiting.  The first apply with a new nrhs grows the plan's workspace
+ * if nrhs is the largest so far (synchronous allocation) and fixes the GEMM
+ * launch shapes for it: for a power of two from the tuning record in the cache
+ * directory if one matches, else by timing the candidate shapes on `stream`
+ * (waits for them; DFMM_AUTOTUNE=0 takes the default shapes instead); for
+ * other nrhs from the power of two below (see dfmm_apply_batch).  Later
+ * applies with the same nrhs allocate nothing and do not wait.  The near-field sum runs on a second stream owned by the
  * plan (default priority), forked from and joined back into `stream` with
  * events, so the apply is complete when `stream` reaches its end.  Applies on
  * one plan must not run concurrently.  An apply may be captured into a HIP
@@ -134,6 +135,33 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * addresses given at capture.  Capturing before that returns DFMM_EINVAL;
  * stage timing is off inside a capture. */
 int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
+
+/* Batched form of dfmm_apply for a request loop: nreq (1 .. DFMM_MAX_BATCH)
+ * requests on one plan in one pass.  Request r has nrhs[r] >= 1 right-hand
+ * sides at DEVICE pointer f[r] and its result goes to u[r] (both complex64,
+ * [nrhs[r]][N], caller's point order; total nrhs <= 4096).  The pass sees one
+ * apply with sum(nrhs) right-hand sides: the densities are gathered from the
+ * requests' buffers by the first kernel and the potentials scattered to
+ * theirs by the last, without staging copies; every result equals what
+ * dfmm_apply gives for that request alone up to the float32 rounding of the
+ * translations (the column order of a batch does not change a column's
+ * arithmetic).  The host arrays are read before the call returns.  No output
+ * may overlap an input or another output (DFMM_EINVAL).  The workspace grows to
+ * the largest total nrhs seen and keeps the GEMM launch shapes of every total
+ * nrhs seen.  Only powers of two are tuned; any other total takes the shapes
+ * of the largest power of two below it (tuned first if needed) and builds
+ * only its chunk tables, so a loop with many batch sizes allocates and tunes
+ * a few times at its start.  Stream, capture and concurrency rules as for
+ * dfmm_apply. */
+#define DFMM_MAX_BATCH 32
+int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* const* u, const int* nrhs,
+                     void* stream);
+
+/* Device bytes of the apply workspace for nrhs right-hand sides (vectors, pair
+ * scratch, sorted densities and near-field sums), for admission against an HBM
+ * budget; the plan's own memory is dfmm_info.device_bytes.  The workspace is
+ * grow-only: it holds the size of the largest nrhs applied so far. */
+int dfmm_workspace_bytes(dfmm_plan_t plan, int nrhs, size_t* bytes);
 
 void dfmm_destroy(dfmm_plan_t plan);
 

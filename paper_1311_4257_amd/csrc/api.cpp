@@ -294,11 +294,64 @@ int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream)
     const char* ub = static_cast<const char*>(u);
     size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
     if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
+    ReqTable R{};
+    R.f[0] = static_cast<const float2*>(f);
+    R.u[0] = static_cast<float2*>(u);
+    R.k0[0] = 0;
+    R.n = 1;
     int cur = 0;
     DFMM_HIP(hipGetDevice(&cur));
     if (cur != plan->device) DFMM_HIP(hipSetDevice(plan->device));
-    run_apply(*plan, f, u, nrhs, static_cast<hipStream_t>(stream));
+    run_apply(*plan, R, nrhs, static_cast<hipStream_t>(stream));
     if (cur != plan->device) DFMM_HIP(hipSetDevice(cur));
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* const* u, const int* nrhs,
+                     void* stream) {
+  return guarded([&]() {
+    if (!plan || !f || !u || !nrhs) return fail(DFMM_EINVAL, "null plan or array");
+    if (nreq < 1 || nreq > DFMM_MAX_BATCH) return fail(DFMM_EINVAL, "nreq must be in [1, DFMM_MAX_BATCH]");
+    ReqTable R{};
+    int total = 0;
+    const size_t col = size_t(8) * size_t(plan->N);
+    for (int r = 0; r < nreq; ++r) {
+      if (!f[r] || !u[r]) return fail(DFMM_EINVAL, "null request vector");
+      if (nrhs[r] < 1) return fail(DFMM_EINVAL, "request nrhs must be >= 1");
+      R.f[r] = static_cast<const float2*>(f[r]);
+      R.u[r] = static_cast<float2*>(u[r]);
+      R.k0[r] = total;
+      total += nrhs[r];
+      if (total > 4096) return fail(DFMM_EINVAL, "total nrhs must be <= 4096");
+    }
+    // no output may overlap an input or another output
+    for (int r = 0; r < nreq; ++r) {
+      const char* ur = static_cast<const char*>(u[r]);
+      const size_t ub = col * size_t(nrhs[r]);
+      for (int q = 0; q < nreq; ++q) {
+        const char* fq = static_cast<const char*>(f[q]);
+        const char* uq = static_cast<const char*>(u[q]);
+        const size_t qb = col * size_t(nrhs[q]);
+        if (fq < ur + ub && ur < fq + qb) return fail(DFMM_EINVAL, "an output overlaps an input");
+        if (q != r && uq < ur + ub && ur < uq + qb) return fail(DFMM_EINVAL, "two outputs overlap");
+      }
+    }
+    R.n = nreq;
+    int cur = 0;
+    DFMM_HIP(hipGetDevice(&cur));
+    if (cur != plan->device) DFMM_HIP(hipSetDevice(plan->device));
+    run_apply(*plan, R, total, static_cast<hipStream_t>(stream));
+    if (cur != plan->device) DFMM_HIP(hipSetDevice(cur));
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_workspace_bytes(dfmm_plan_t plan, int nrhs, size_t* bytes) {
+  return guarded([&]() {
+    if (!plan || !bytes) return fail(DFMM_EINVAL, "null plan or output");
+    if (nrhs < 1 || nrhs > 4096) return fail(DFMM_EINVAL, "nrhs must be in [1, 4096]");
+    *bytes = workspace_bytes(*plan, nrhs);
     return int(DFMM_OK);
   });
 }

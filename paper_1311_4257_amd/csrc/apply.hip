@@ -14,6 +14,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <string>
 
 #include "internal.hpp"
@@ -87,13 +89,22 @@ __device__ __forceinline__ float2 green_f(float dx, float dy, float dz) {
 inline unsigned nblocks(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
 
 // ---- permutation into Morton order ------------------------------------------
-__global__ void k_permute_in(const float2* __restrict__ f, float2* __restrict__ fs,
-                             const int* __restrict__ perm, int64_t N, int nrhs) {
+// The densities of a batch of requests: batch column k belongs to the last
+// request r with k0[r] <= k (a select chain over uniform kernel arguments).
+__device__ __forceinline__ int req_of(const ReqTable& R, int k) {
+  int r = 0;
+  for (int q = 1; q < R.n; ++q) r = k >= R.k0[q] ? q : r;
+  return r;
+}
+
+__global__ void k_permute_in(const ReqTable R, float2* __restrict__ fs, const int* __restrict__ perm, int64_t N,
+                             int nrhs) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= N * nrhs) return;
   int64_t s = i / nrhs;
   int k = int(i % nrhs);
-  fs[i] = f[int64_t(k) * N + perm[s]];
+  const int r = req_of(R, k);
+  fs[i] = R.f[r][int64_t(k - R.k0[r]) * N + perm[s]];
 }
 
 // ---- per-point leaf weights (plan time, float64) -----------------------------------
@@ -665,7 +676,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
   }
 }
 
-// L2T and the output: u[k][perm[t]] = sum_q W[t][q] U_LF[leaf(t)][k][q] + unear[k][t].
+// L2T and the output: u[k][perm[t]] = sum_q W[t][q] U_LF[leaf(t)][k][q] + unear[k][t],
+// u of batch column k being the output of its request.
 // 16 lanes per target read 16 consecutive q at a time (128-byte runs); a
 // lane keeps its W values over the right-hand sides.
 constexpr int L2T_BS = 256;
@@ -673,7 +685,7 @@ constexpr int L2T_QMAX = 16;  // W values per lane: R <= 16 * L2T_QMAX
 __global__ void __launch_bounds__(L2T_BS) k_l2t(const float2* __restrict__ W, const float2* __restrict__ ulf,
                                                  const int* __restrict__ leaf_of, const double2* __restrict__ unear,
                                                  const int* __restrict__ perm, int R, int nrhs, int64_t N,
-                                                 float2* __restrict__ u) {
+                                                 const ReqTable Q) {
   const int64_t t = (int64_t(blockIdx.x) * L2T_BS + threadIdx.x) >> 4;
   const int l = threadIdx.x & 15;
   const bool act = t < N;
@@ -698,7 +710,8 @@ __global__ void __launch_bounds__(L2T_BS) k_l2t(const float2* __restrict__ W, co
     }
     if (act && l == 0) {
       const double2 nf = unear[int64_t(k) * N + tt];
-      u[int64_t(k) * N + o] = make_float2(float(double(acc.x) + nf.x), float(double(acc.y) + nf.y));
+      const int r = req_of(Q, k);
+      Q.u[r][int64_t(k - Q.k0[r]) * N + o] = make_float2(float(double(acc.x) + nf.x), float(double(acc.y) + nf.y));
     }
   }
 }
@@ -735,12 +748,19 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
   DevBuf grp, col0;
 };
 
+// The GEMM launches of one nrhs (chunk tables and tuned shapes).
+struct LaunchSet {
+  std::vector<Launch> m2m, l2l, m2l;  // per HF level
+  Launch lf_m2l;
+};
+
+// Workspace of a plan: buffers sized for the largest nrhs applied so far
+// (grow-only), launch sets per nrhs.
 struct ApplyState {
-  int nrhs = 0;
+  int cap = 0;
   std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
   DevBuf fs, flf, ulf, Y, unear;
-  std::vector<Launch> m2m, l2l, m2l;          // per HF level
-  Launch lf_m2l;
+  std::map<int, std::unique_ptr<LaunchSet>> sets;
   // second stream for the near field (default priority) and its fork/join events
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -909,33 +929,59 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
   prepare_cfg(L, G, nrhs, best_nt, best_sl, best_nw, best_alds);
 }
 
-static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
-  if (S.nrhs == nrhs) return;
-  S.nrhs = nrhs;
-  int64_t N = P.N;
-  S.fs.alloc(sizeof(float2) * N * nrhs);
-  S.unear.alloc(sizeof(double2) * N * nrhs);
-  S.flf.alloc(sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs);
-  S.ulf.alloc(sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs);
+// Device bytes of each workspace buffer for nrhs right-hand sides.
+struct WsSizes {
+  size_t fs, unear, flf, ulf, Y;
+  std::vector<size_t> F, U;
+  size_t total() const {
+    size_t t = fs + unear + flf + ulf + Y;
+    for (size_t b : F) t += b;
+    for (size_t b : U) t += b;
+    return t;
+  }
+};
+
+static WsSizes ws_sizes(const dfmm_plan_s& P, int nrhs) {
+  WsSizes z;
+  const int64_t N = P.N;
+  z.fs = sizeof(float2) * N * nrhs;
+  z.unear = sizeof(double2) * N * nrhs;
+  z.flf = sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs;
+  z.ulf = z.flf;
   int64_t ymax = P.lf.npairs * P.lf.R;
-  S.F.clear();
-  S.U.clear();
-  for (auto& H : P.hf) {
-    S.F.emplace_back(new DevBuf());
-    S.U.emplace_back(new DevBuf());
-    S.F.back()->alloc(sizeof(float2) * std::max<int64_t>(1, H.nout) * H.R * nrhs);
-    S.U.back()->alloc(sizeof(float2) * std::max<int64_t>(1, H.nin) * H.R * nrhs);
+  for (const auto& H : P.hf) {
+    z.F.push_back(sizeof(float2) * std::max<int64_t>(1, H.nout) * H.R * nrhs);
+    z.U.push_back(sizeof(float2) * std::max<int64_t>(1, H.nin) * H.R * nrhs);
     ymax = std::max<int64_t>(ymax, H.npairs * H.R);
     ymax = std::max<int64_t>(ymax, H.m2m_npairs * H.R);
     ymax = std::max<int64_t>(ymax, H.l2l_npairs * H.Rc);
   }
-  S.Y.alloc(sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs);
-  S.m2m.clear();
-  S.l2l.clear();
-  S.m2l.clear();
-  S.m2m.resize(P.hf.size());
-  S.l2l.resize(P.hf.size());
-  S.m2l.resize(P.hf.size());
+  z.Y = sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs;
+  return z;
+}
+
+size_t workspace_bytes(const dfmm_plan_s& P, int nrhs) { return ws_sizes(P, nrhs).total(); }
+
+// Grow the buffers to nrhs right-hand sides (the launch sets do not hold
+// buffer addresses, so they stay valid).
+static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
+  if (nrhs <= S.cap) return;
+  DFMM_HIP(hipDeviceSynchronize());  // earlier applies may still read the old buffers
+  const WsSizes z = ws_sizes(P, nrhs);
+  S.cap = nrhs;
+  S.fs.alloc(z.fs);
+  S.unear.alloc(z.unear);
+  S.flf.alloc(z.flf);
+  S.ulf.alloc(z.ulf);
+  S.F.clear();
+  S.U.clear();
+  for (size_t e = 0; e < P.hf.size(); ++e) {
+    S.F.emplace_back(new DevBuf());
+    S.U.emplace_back(new DevBuf());
+    S.F.back()->alloc(z.F[e]);
+    S.U.back()->alloc(z.U[e]);
+  }
+  S.Y.alloc(z.Y);
 }
 
 // ---- tuning record: the chosen (tile width, M-slices, LDS operator) per launch,
@@ -1001,23 +1047,26 @@ static void save_tuning(const std::string& path, const std::vector<Launch*>& ls)
   if (ok) std::rename(tmp.c_str(), path.c_str());
 }
 
-// Tune the GEMM launches of the current nrhs on the apply stream.
-static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, hipStream_t st) {
+// Tune the GEMM launches of nrhs right-hand sides on the apply stream.
+static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS, hipStream_t st) {
   float2* Y = S.Y.as<float2>();
   std::vector<Launch*> ls;
   std::vector<const GGemm*> gs;
   std::vector<const float2*> xs;
+  LS.m2m.resize(P.hf.size());
+  LS.l2l.resize(P.hf.size());
+  LS.m2l.resize(P.hf.size());
   for (size_t e = 0; e < P.hf.size(); ++e) {
     const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
-    ls.insert(ls.end(), {&S.m2m[e], &S.l2l[e], &S.m2l[e]});
+    ls.insert(ls.end(), {&LS.m2m[e], &LS.l2l[e], &LS.m2l[e]});
     gs.insert(gs.end(), {&P.hf[e].m2m, &P.hf[e].l2l, &P.hf[e].m2l});
     xs.insert(xs.end(), {Fc, S.U[e]->as<float2>(), S.F[e]->as<float2>()});
-    S.m2l[e].m2l = true;
+    LS.m2l[e].m2l = true;
   }
-  ls.push_back(&S.lf_m2l);
+  ls.push_back(&LS.lf_m2l);
   gs.push_back(&P.lf.m2l);
   xs.push_back(S.flf.as<float2>());
-  S.lf_m2l.m2l = true;
+  LS.lf_m2l.m2l = true;
   const std::string path = tune_path(P, gs, nrhs);
   if (load_tuning(path, ls, gs, nrhs)) return;
   for (size_t i = 0; i < ls.size(); ++i) autotune(*ls[i], *gs[i], nrhs, xs[i], Y, st);
@@ -1025,22 +1074,51 @@ static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, hipStream_t s
   if (!(env && env[0] == '0')) save_tuning(path, ls);
 }
 
-void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t st) {
+// A launch set for nrhs that is not a power of two takes the tuned shapes of
+// the largest power of two below it (only its chunk tables are built), so a
+// request loop with many batch sizes tunes at most log2(max nrhs) + 1 of them.
+static void inherit_launches(dfmm_plan_s& P, int nrhs, const LaunchSet& from, LaunchSet& LS) {
+  LS.m2m.resize(P.hf.size());
+  LS.l2l.resize(P.hf.size());
+  LS.m2l.resize(P.hf.size());
+  auto take = [&](Launch& L, const Launch& F, const GGemm& G) {
+    prepare_cfg(L, G, nrhs, F.nt, F.slices, F.nw, F.alds);
+    L.m2l = F.m2l;
+  };
+  for (size_t e = 0; e < P.hf.size(); ++e) {
+    take(LS.m2m[e], from.m2m[e], P.hf[e].m2m);
+    take(LS.l2l[e], from.l2l[e], P.hf[e].l2l);
+    take(LS.m2l[e], from.m2l[e], P.hf[e].m2l);
+  }
+  take(LS.lf_m2l, from.lf_m2l, P.lf.m2l);
+}
+
+static LaunchSet& launch_set(dfmm_plan_s& P, ApplyState& S, int nrhs, hipStream_t st) {
+  auto it = S.sets.find(nrhs);
+  if (it != S.sets.end()) return *it->second;
+  std::unique_ptr<LaunchSet> ls(new LaunchSet());
+  if ((nrhs & (nrhs - 1)) == 0) {
+    tune_launches(P, nrhs, S, *ls, st);
+  } else {
+    int p2 = 1;
+    while (2 * p2 < nrhs) p2 *= 2;
+    inherit_launches(P, nrhs, launch_set(P, S, p2, st), *ls);
+  }
+  return *S.sets.emplace(nrhs, std::move(ls)).first->second;
+}
+
+void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   // under stream capture only launches, event records and event waits may be
   // issued: the workspace, the tuning and the side stream must already exist
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   DFMM_HIP(hipStreamIsCapturing(st, &cap));
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  if (capturing && (!P.ws || P.ws->nrhs != nrhs || !P.ws->side))
+  if (capturing && (!P.ws || P.ws->cap < nrhs || !P.ws->sets.count(nrhs) || !P.ws->side))
     throw Error{DFMM_EINVAL, "dfmm_apply under stream capture needs an earlier uncaptured apply with the same nrhs"};
   if (!P.ws) P.ws = new ApplyState();
   ApplyState& S = *P.ws;
-  if (S.nrhs != nrhs) {
-    ensure_workspace(P, nrhs, S);
-    tune_launches(P, nrhs, S, st);
-  }
-  const float2* f = static_cast<const float2*>(fv);
-  float2* u = static_cast<float2*>(uv);
+  ensure_workspace(P, nrhs, S);
+  LaunchSet& LS = launch_set(P, S, nrhs, st);
   const int64_t N = P.N;
   const int64_t nleaf = P.lf.nleaf;
   const int Rl = P.lf.R;
@@ -1050,7 +1128,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   auto mark = [&](int stage) {
     if (tm) tm->mark(stage, st);
   };
-  hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, f, S.fs.as<float2>(),
+  hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, R, S.fs.as<float2>(),
                      P.perm_d.as<int>(), N, nrhs);
   mark(ST_PERMUTE);
   // the near field needs only the permuted densities: it runs on the side
@@ -1082,7 +1160,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   for (int e = 0; e <= e_top; ++e) {
     HFLevel& H = P.hf[e];
     const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
-    launch_gemm(S.m2m[e], nrhs, Fc, S.Y.as<float2>(), st);
+    launch_gemm(LS.m2m[e], nrhs, Fc, S.Y.as<float2>(), st);
     int RN = H.R * nrhs;
     if (H.nout > 0)
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nout * RN, 256)), dim3(256), 0, st, H.m2m_rs.as<int>(),
@@ -1098,8 +1176,8 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   }
   for (int e = e_top; e >= 0; --e) {
     HFLevel& H = P.hf[e];
-    if (S.m2l[e].nchunks > 0) {
-      launch_gemm(S.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
+    if (LS.m2l[e].nchunks > 0) {
+      launch_gemm(LS.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
       mark(ST_M2L);
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
@@ -1107,7 +1185,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
       mark(ST_REDUCE);
     }
     float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
-    launch_gemm(S.l2l[e], nrhs, S.U[e]->as<float2>(), S.Y.as<float2>(), st);
+    launch_gemm(LS.l2l[e], nrhs, S.U[e]->as<float2>(), S.Y.as<float2>(), st);
     int RNc = H.Rc * nrhs;
     if (H.nchild_in > 0)
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nchild_in * RNc, 256)), dim3(256), 0, st, H.l2l_rs.as<int>(),
@@ -1120,8 +1198,8 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
     mark(ST_ZERO);
   }
   // LF-M2L
-  if (S.lf_m2l.nchunks > 0) {
-    launch_gemm(S.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
+  if (LS.lf_m2l.nchunks > 0) {
+    launch_gemm(LS.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
     mark(ST_LF_M2L);
     int RN = Rl * nrhs;
     hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
@@ -1132,7 +1210,7 @@ void run_apply(dfmm_plan_s& P, const void* fv, void* uv, int nrhs, hipStream_t s
   if (Rl > 16 * L2T_QMAX) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank too large for L2T"};
   hipLaunchKernelGGL(k_l2t, dim3(nblocks(N * 16, L2T_BS)), dim3(L2T_BS), 0, st, P.lf.W.as<float2>(),
                      S.ulf.as<float2>(), P.leaf_of.as<int>(), S.unear.as<double2>(), P.perm_d.as<int>(), Rl, nrhs, N,
-                     u);
+                     R);
   mark(ST_LEAF);
   DFMM_HIP(hipGetLastError());
 }

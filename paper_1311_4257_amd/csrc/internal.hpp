@@ -228,7 +228,19 @@ struct StageTimer {
   void side_mark(int stage, hipStream_t side);     // closes it
   void collect(double* ms, int64_t* launches);  // sums per stage, then resets
 };
-void run_apply(dfmm_plan_s& P, const void* f, void* u, int nrhs, hipStream_t st);
+// The requests of one apply: batch columns k0[r] .. k0[r + 1] - 1 (the last
+// request up to nrhs) are request r's right-hand sides, read from f[r] and
+// written to u[r] (each [nrhs_r][N], caller's point order).  Passed by value
+// as a kernel argument.
+constexpr int kMaxBatch = DFMM_MAX_BATCH;
+struct ReqTable {
+  const float2* f[kMaxBatch];
+  float2* u[kMaxBatch];
+  int k0[kMaxBatch];
+  int n;
+};
+void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st);
+size_t workspace_bytes(const dfmm_plan_s& P, int nrhs);
 void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT);
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                 const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);

@@ -18,10 +18,17 @@ LIB_PATH = os.path.join(_HERE, "libdfmm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libdfmm.so not built ({LIB_PATH}); run __graft_entry__.build()")
 
+# torch first: the library's HIP runtime dependency must resolve to the runtime
+# torch has loaded.  Loaded the other way round, the process holds two HIP
+# runtimes and whichever initializes second finds no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2l", "lf_reduce",
           "leaf_eval", "zero", "near_field"]
+
+MAX_BATCH = 32  # DFMM_MAX_BATCH
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
 
@@ -29,7 +36,7 @@ ABI_FUNCTIONS = [
     "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
     "dfmm_opset_set", "dfmm_opset_get", "dfmm_opset_info", "dfmm_opset_save", "dfmm_opset_load",
     "dfmm_opset_destroy", "dfmm_options_default", "dfmm_plan", "dfmm_plan_ex", "dfmm_apply",
-    "dfmm_destroy", "dfmm_plan_info", "dfmm_export", "dfmm_set_timing", "dfmm_stage_times",
+    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_destroy", "dfmm_plan_info", "dfmm_export", "dfmm_set_timing", "dfmm_stage_times",
 ]
 
 
@@ -66,6 +73,9 @@ _sig = {
     "dfmm_plan": (C.c_int, [_D, C.c_int64, C.c_double, C.c_double, C.POINTER(_P)]),
     "dfmm_plan_ex": (C.c_int, [_D, C.c_int64, C.c_double, C.POINTER(Options), C.POINTER(_P)]),
     "dfmm_apply": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "dfmm_apply_batch": (C.c_int, [_P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_int), C.c_void_p]),
+    "dfmm_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     "dfmm_destroy": (None, [_P]),
     "dfmm_plan_info": (C.c_int, [_P, C.POINTER(Info)]),
     "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -196,6 +206,32 @@ class Plan:
         _check(_lib.dfmm_apply(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u.data_ptr()),
                                f2.shape[0], C.c_void_p(stream.cuda_stream)))
         return u.reshape(-1) if one else u
+
+    def apply_batch(self, fs, us, stream=None):
+        """One pass over several requests: us[r] = A fs[r] for (nrhs_r, N) complex64
+        CUDA tensors (at most MAX_BATCH requests)."""
+        import torch
+
+        if len(fs) != len(us) or not 1 <= len(fs) <= MAX_BATCH:
+            raise ValueError(f"need 1 .. {MAX_BATCH} (f, u) pairs")
+        for f, u in zip(fs, us):
+            if f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous() or f.dim() != 2:
+                raise ValueError("each f must be a contiguous (nrhs, N) complex64 CUDA tensor")
+            if f.shape[1] != self.N or u.shape != f.shape or u.dtype != f.dtype or not u.is_contiguous():
+                raise ValueError("request shapes do not match the plan")
+        n = len(fs)
+        fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+        up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+        nr = (C.c_int * n)(*[f.shape[0] for f in fs])
+        if stream is None:
+            stream = torch.cuda.current_stream(fs[0].device)
+        _check(_lib.dfmm_apply_batch(self._h, n, fp, up, nr, C.c_void_p(stream.cuda_stream)))
+        return us
+
+    def workspace_bytes(self, nrhs: int) -> int:
+        b = C.c_size_t()
+        _check(_lib.dfmm_workspace_bytes(self._h, nrhs, C.byref(b)))
+        return b.value
 
     def info(self) -> Info:
         inf = Info()

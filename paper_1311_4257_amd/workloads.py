@@ -24,6 +24,9 @@ __all__ = [
     "sample_targets",
     "CONFIGS",
     "make_config",
+    "SERVING_PLANS",
+    "serving_points",
+    "serving_mix",
 ]
 
 
@@ -130,3 +133,37 @@ def make_config(name: str, **over):
         raise ValueError(cfg["kind"])
     f = densities(N, cfg["nrhs"], cfg["fseed"])
     return pts, f, cfg
+
+
+# The resident plans of the serving mix: (name, kind, K, N, seed).  Spheres of
+# diameter K, 4:2:1 ellipsoids with semi-axes (K/2, K/4, K/8), and the union of
+# 8 spheres of diameter K/4; N from 16,384 to 524,288.
+SERVING_PLANS = [
+    ("sphere8", "sphere", 8.0, 16384, 51),
+    ("sphere16", "sphere", 16.0, 65536, 52),
+    ("sphere32", "sphere", 32.0, 524288, 53),
+    ("ellipsoid16", "ellipsoid", 16.0, 16384, 54),
+    ("ellipsoid32", "ellipsoid", 32.0, 131072, 55),
+    ("union32", "union", 32.0, 131072, 56),
+]
+
+
+def serving_points(kind: str, K: float, N: int, seed: int) -> np.ndarray:
+    if kind == "sphere":
+        return sphere_points(N, K, seed)
+    if kind == "ellipsoid":
+        return ellipsoid_points(N, (K / 2, K / 4, K / 8), seed)
+    if kind == "union":
+        return sphere_union_points(N, K, 8, seed)
+    raise ValueError(kind)
+
+
+def serving_mix(n: int, n_plans: int, seed: int, nrhs_choices=(1, 4, 16)):
+    """A request stream: plan index uniform over n_plans, nrhs uniform over
+    nrhs_choices, and unit-rate Poisson inter-arrival gaps (divide by the
+    rate in requests per second for arrival times in seconds)."""
+    rng = np.random.default_rng(seed)
+    plan = rng.integers(0, n_plans, size=n)
+    nrhs = rng.choice(np.asarray(nrhs_choices), size=n)
+    gaps = rng.exponential(1.0, size=n)
+    return plan, nrhs, gaps

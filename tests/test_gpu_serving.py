@@ -1,0 +1,105 @@
+"""GPU: batched applies and the continuous-batching request loop.
+
+Every request's result must be the same alone and in a batch or a mix of
+plans: the columns of a pass do not share arithmetic, so the comparison is
+against the same plan's dfmm_apply of that request alone, to float32 rounding
+(relative L2 difference <= 1e-6; in practice bitwise).
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+from paper_1311_4257_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".dfmm_cache")
+TOL = 1e-6
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _plans():
+    from paper_1311_4257_amd import dfmm
+
+    p0 = dfmm.Plan(workloads.sphere_points(4096, 4.0, 1), 4.0, eps=1e-4, cache_dir=CACHE, device=0)
+    p1 = dfmm.Plan(workloads.ellipsoid_points(6000, (4.0, 2.0, 1.0), 3), 8.0, eps=1e-4, cache_dir=CACHE, device=0)
+    return [p0, p1]
+
+
+def _dens(torch, n, nrhs, gen, cuda):
+    return torch.complex(torch.randn((nrhs, n), generator=gen, device=cuda),
+                         torch.randn((nrhs, n), generator=gen, device=cuda))
+
+
+def test_apply_batch_matches_separate_applies(cuda):
+    import torch
+
+    from paper_1311_4257_amd import dfmm
+
+    plan = _plans()[0]
+    gen = torch.Generator(device=cuda)
+    gen.manual_seed(11)
+    fs = [_dens(torch, plan.N, k, gen, cuda) for k in (1, 2, 4, 1)]  # total 8; then 3 and 5 below
+    alone = [plan.apply(f).cpu().numpy() for f in fs]
+    us = [torch.empty_like(f) for f in fs]
+    plan.apply_batch(fs, us)
+    for u, a in zip(us, alone):
+        assert _rel(u.cpu().numpy(), a) <= TOL
+    # totals that are not powers of two take the launch shapes of the one below
+    for sel in ([0, 1], [2, 3]):  # totals 3 and 5
+        sub_f = [fs[i] for i in sel]
+        sub_u = [torch.empty_like(f) for f in sub_f]
+        plan.apply_batch(sub_f, sub_u)
+        for i, u in zip(sel, sub_u):
+            assert _rel(u.cpu().numpy(), alone[i]) <= TOL
+    # argument errors: overlapping outputs, too many requests
+    with pytest.raises(dfmm.DfmmError):
+        plan.apply_batch([fs[0], fs[3]], [us[0], us[0]])
+    with pytest.raises(ValueError):
+        plan.apply_batch([fs[0]] * (dfmm.MAX_BATCH + 1), [us[0]] * (dfmm.MAX_BATCH + 1))
+
+
+def test_request_loop_results_equal_alone_results(cuda):
+    """A mix of two plans, requests arriving together and staggered, nrhs 1-5:
+    the loop must batch (some pass holds several requests), overlap plans, and
+    return for every request what its plan gives it alone; the single-request
+    form returns the same."""
+    import torch
+
+    from paper_1311_4257_amd.serve import Request, Server, latency_stats
+
+    plans = _plans()
+    gen = torch.Generator(device=cuda)
+    gen.manual_seed(12)
+    rng = np.random.default_rng(13)
+    reqs = []
+    for i in range(40):
+        p = int(rng.integers(0, 2))
+        k = int(rng.choice([1, 2, 3, 5]))
+        f = _dens(torch, plans[p].N, k, gen, cuda)
+        t = 0.0 if i < 20 else 0.002 * (i - 20)  # half at once, half while the first are running
+        reqs.append(Request(i, p, f, torch.empty_like(f), t))
+    alone = [plans[r.plan].apply(r.f).cpu().numpy() for r in reqs]
+    torch.cuda.synchronize()
+    for mode in ("batched", "single"):
+        srv = Server(plans, budget_bytes=32 << 30, max_batch_rhs=16, mode=mode)
+        srv.warm([1, 2, 4, 8, 16])
+        for r in reqs:
+            r.u.zero_()
+        span = srv.run(reqs)
+        print(mode, f"{len(srv.batches)} passes, span {span * 1e3:.1f} ms", latency_stats(reqs))
+        assert np.isfinite(span) and span > 0
+        for r, a in zip(reqs, alone):
+            assert r.done >= r.arrival
+            assert _rel(r.u.cpu().numpy(), a) <= TOL, (mode, r.rid)
+        if mode == "batched":
+            assert max(len(b[1]) for b in srv.batches) > 1
+            assert all(b[2] <= 16 or len(b[1]) == 1 for b in srv.batches)
+        else:
+            assert len(srv.batches) == len(reqs)
