@@ -414,7 +414,7 @@ def main() -> int:
         "plan_seconds": info.plan_seconds,
     }
     if not args.no_cpu_baseline and args.workload == "sphere16":
-        out["cpu_baseline"] = cpu_baseline(pts, f, K, 0.15 * eps)  # the library's tau for eps
+        out["cpu_baseline"] = cpu_baseline(pts, f, K, info.tau)  # the plan's skeleton tolerance
     print(json.dumps(out))
     return 0
 

@@ -107,7 +107,7 @@ void dfmm_options_default(dfmm_options* opt);
  * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
  * every level (Section 2.2), the wedge labels, the needed directions and the
  * translation tables, all resident on the device.  Synchronous.
- * The skeletons use tau = 0.15 eps (eps >= 1e-5) or 0.05 eps.  Plans with
+ * The skeletons use tau = 0.1 eps (eps >= 1e-5) or 0.05 eps.  Plans with
  * eps < 1e-5 (or an operator set with tau < 3e-6) are "precise": the
  * near-field distances, 1/r and products are float64, the directional
  * operators are stored as float32 hi + lo parts, and every translation GEMM adds
@@ -190,6 +190,7 @@ typedef struct {
   double bytes_m2l_op;    /* M2L operators (complex64, unpadded r_in x r_out), once per offset group */
   double bytes_m2l_vec;   /* M2L source reads + output writes, 8 (r_in + r_out) per pair, per right-hand side */
   double flops_m2l_level[32]; /* flops_m2l_hf / flops_m2l_lf split by level 0..D */
+  double tau;             /* skeleton tolerance of the plan's operator set */
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);

@@ -676,6 +676,167 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
   }
 }
 
+// Near field for many right-hand sides (fast plans): per leaf, U[t][k] +=
+// sum_s G(x_t, x_s) F[s][k] as a complex GEMM on MFMA.  A workgroup takes a
+// leaf, a block of up to NM_TB of its targets and 16 NCT right-hand sides;
+// the adjacent leaves' points and densities are staged in LDS NM_SC at a time.
+// Each wave owns 8-target row tiles (w, w + 4, ...): it evaluates G for its 8
+// targets x NM_SC sources once (one source per lane, the hi/lo separations of
+// the VALU path) into LDS, then runs the products on v_mfma_f32_16x16x4f32 with
+// complex as interleaved real (A row 2t = (Re G, -Im G), row 2t + 1 =
+// (Im G, Re G) over k = (Re F, Im F) of a source).  Partial sums go to
+// float64 every 16 sources, as in the VALU path.
+constexpr int NM_SC = 64;   // sources per staged chunk
+constexpr int kNearMfmaMinRhs = 4;  // fast plans with at least this many rhs take the MFMA path
+constexpr int NM_NW = 4;    // waves per workgroup
+constexpr int NM_MAXT = 4;  // row tiles per wave
+constexpr int NM_TB = 8 * NM_NW * NM_MAXT;  // targets per workgroup (128)
+template <int NCT>
+__global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restrict__ phi, const float4* __restrict__ plo,
+                                                          const int* __restrict__ lstart,
+                                                          const int* __restrict__ nstart, const int* __restrict__ nsrc,
+                                                          const float2* __restrict__ fs, int nrhs, int64_t N,
+                                                          double2* __restrict__ unear) {
+  constexpr int NCOL = 16 * NCT;
+  constexpr int GS = NM_SC + 1;  // G row stride (float2): rows of different targets on different banks
+  __shared__ float4 sh[NM_SC], sq[NM_SC];
+  __shared__ float4 th[NM_TB], tq[NM_TB];
+  __shared__ float2 sf[NM_SC * NCOL];
+  __shared__ float2 sg[NM_NW * 8 * GS];
+  __shared__ int sj[NM_SC];
+  __shared__ int nb_beg[64], nb_off[65];
+  const int b = blockIdx.x;
+  const int c0 = int(blockIdx.y) * NCOL;
+  const int s0 = lstart[b] + int(blockIdx.z) * NM_TB;
+  const int s1 = min(lstart[b + 1], s0 + NM_TB);
+  if (s0 >= s1) return;  // uniform: this target block is past the leaf's end
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int n0 = nstart[b];
+  const int nn = min(nstart[b + 1] - n0, 64);  // adjacent leaves (at most 27)
+  if (w == 0) {  // neighbour ranges and their offsets (wave prefix sum)
+    int beg = 0, cnt = 0;
+    if (lane < nn) {
+      const int A = nsrc[n0 + lane];
+      beg = lstart[A];
+      cnt = lstart[A + 1] - beg;
+    }
+    int incl = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += v;
+    }
+    nb_beg[lane] = beg;
+    nb_off[lane] = incl - cnt;
+    if (lane == 63) nb_off[64] = incl;
+  }
+  for (int i = threadIdx.x; i < NM_TB; i += 64 * NM_NW) {
+    const int t = min(s0 + i, s1 - 1);
+    th[i] = phi[t];
+    tq[i] = plo[t];
+  }
+  __syncthreads();
+  const int total = nb_off[nn];
+  const int ntiles = (s1 - s0 + 7) / 8;
+  const int rr = lane & 15, kk = lane >> 4;  // A row / B column, k index of this lane
+  const int tr = rr >> 1, kp = kk & 1;       // target of the row, Re/Im part of k
+  const bool rodd = (rr & 1) != 0;
+  v4f acc[NM_MAXT][NCT];
+  double a64[NM_MAXT][NCT][4];
+#pragma unroll
+  for (int i = 0; i < NM_MAXT; ++i)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      acc[i][c] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a64[i][c][r] = 0.0;
+    }
+  float2* gw = sg + w * 8 * GS;
+  for (int base = 0; base < total; base += NM_SC) {
+    const int fill = min(NM_SC, total - base);
+    __syncthreads();  // the previous chunk is consumed
+    if (threadIdx.x < NM_SC) {
+      const int i = threadIdx.x;
+      int j = -1;
+      if (i < fill) {
+        const int g = base + i;
+        int q = 0;  // the neighbour holding element g: largest q with nb_off[q] <= g
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1)
+          if (q + step < nn && nb_off[q + step] <= g) q += step;
+        j = nb_beg[q] + (g - nb_off[q]);
+        sh[i] = phi[j];
+        sq[i] = plo[j];
+      }
+      sj[i] = j;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
+      const int i = e / NCOL, c = e % NCOL;
+      const int j = sj[i];
+      sf[e] = (j >= 0 && c0 + c < nrhs) ? fs[int64_t(j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const bool sval = lane < fill;
+    const float4 h = sh[lane], l = sq[lane];
+#pragma unroll
+    for (int i = 0; i < NM_MAXT; ++i) {
+      const int rt = w + NM_NW * i;
+      if (rt >= ntiles) break;
+      // G for this tile's 8 targets and this lane's source
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float4 a = th[rt * 8 + t], c = tq[rt * 8 + t];
+        float2 g = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
+        if (!sval || s0 + rt * 8 + t >= s1) g = make_float2(0.f, 0.f);
+        gw[t * GS + lane] = g;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // products: MFMA step q covers sources 2q, 2q + 1
+#pragma unroll 4
+      for (int q = 0; q < NM_SC / 2; ++q) {
+        const int src = 2 * q + (kk >> 1);
+        const float2 g = gw[tr * GS + src];
+        const float av = rodd ? (kp ? g.x : g.y) : (kp ? -g.y : g.x);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+          const float2 f = sf[src * NCOL + c * 16 + rr];
+          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, kp ? f.y : f.x, acc[i][c], 0, 0, 0);
+        }
+        if ((q & 7) == 7) {
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a64[i][c][r] += double(acc[i][c][r]);
+            acc[i][c] = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // lane holds rows 4 kk .. 4 kk + 3 = (Re, Im) of targets 2 kk, 2 kk + 1, column rr
+#pragma unroll
+  for (int i = 0; i < NM_MAXT; ++i) {
+    const int rt = w + NM_NW * i;
+    if (rt >= ntiles) break;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c0 + c * 16 + rr;
+      if (col >= nrhs) continue;
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int t = s0 + rt * 8 + 2 * kk + h2;
+        if (t < s1) unear[int64_t(col) * N + t] = make_double2(a64[i][c][2 * h2], a64[i][c][2 * h2 + 1]);
+      }
+    }
+  }
+}
+
 // L2T and the output: u[k][perm[t]] = sum_q W[t][q] U_LF[leaf(t)][k][q] + unear[k][t],
 // u of batch column k being the output of its request.
 // 16 lanes per target read 16 consecutive q at a time (128-byte runs); a
@@ -1143,6 +1304,17 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
                      S.fs.as<float2>(), nrhs, N, S.unear.as<double2>())
   if (P.precise) {
     if (nrhs == 1) DFMM_NEAR(true, 1); else DFMM_NEAR(true, 8);
+  } else if (nrhs >= kNearMfmaMinRhs) {
+    const dim3 grid(unsigned(nleaf), unsigned((nrhs + 31) / 32), unsigned((P.max_leaf_pts + NM_TB - 1) / NM_TB));
+    if (nrhs <= 16)
+      hipLaunchKernelGGL(k_near_mfma<1>, dim3(unsigned(nleaf), unsigned((nrhs + 15) / 16), grid.z), dim3(64 * NM_NW), 0,
+                         S.side, P.pthi.as<float4>(), P.ptlo.as<float4>(), P.leaf_start.as<int>(),
+                         P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(), nrhs, N,
+                         S.unear.as<double2>());
+    else
+      hipLaunchKernelGGL(k_near_mfma<2>, grid, dim3(64 * NM_NW), 0, S.side, P.pthi.as<float4>(), P.ptlo.as<float4>(),
+                         P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(),
+                         nrhs, N, S.unear.as<double2>());
   } else {
     if (nrhs == 1) DFMM_NEAR(false, 1); else DFMM_NEAR(false, 8);
   }

@@ -142,6 +142,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   info.w_top = P.w_top;
   info.nlevels_hf = e_top + 1;
   const OpSetImpl& ops = *get_ops(ctx, std::max(1, P.w_top));
+  info.tau = ops.tau;
   if (e_top >= 0 && (1 << e_top) > ops.w_hi)
     throw Error{DFMM_EUNSUPPORTED, "tree needs HF width " + std::to_string(1 << e_top) +
                                        " but the operator set stops at " + std::to_string(ops.w_hi)};
