@@ -39,12 +39,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3
+PEAK_F16_MATRIX_TFLOPS = 2500.0  # dense fp16 / bf16 MFMA
 PEAK_HBM_GBS = 8000.0
 CACHE_DIR = os.path.join(ROOT, ".dfmm_cache")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_traffic_sphere16.json")
 # the M2L launch is defined by the tile engine and the operator layout built at plan time
 GEMM_SOURCES = ["paper_1311_4257_amd/csrc/apply.hip", "paper_1311_4257_amd/csrc/plan.cpp"]
 CALIB_BYTES = 256 << 20
+# --precision -> (dfmm_options.precision, the dtype reported)
+PRECISIONS = {"fp32": (0, "f32"), "fp16x3": (1, "f16x3 (hi/lo f16 products, f32 sums)"),
+              "bf16x3": (2, "bf16x3 (hi/lo bf16 products, f32 sums)")}
 # workload name -> (description, targets checked against the direct sum)
 WORKLOADS = {
     "sphere16": ("sphere16: N=65536 uniform on a sphere of diameter K=16 (seed 2), complex64 N(0,1) "
@@ -265,6 +269,8 @@ def main() -> int:
     ap.add_argument("--eps", type=float, default=None, help="plan eps (default: the workload's)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of one workload")
+    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
+                    help="arithmetic of the translation GEMMs (fp32, or split 16-bit products)")
     ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
     args = ap.parse_args()
     if args.traffic_summary:
@@ -292,7 +298,8 @@ def main() -> int:
         cfg["eps"] = args.eps
     K, N, nrhs, eps = cfg["K"], cfg["N"], cfg["nrhs"], cfg["eps"]
     dev = torch.device("cuda:0")
-    plan = dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0)
+    prec, dtype = PRECISIONS[args.precision]
+    plan = dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0, precision=prec)
     info = plan.info()
     fd = torch.from_numpy(f.astype(np.complex64)).to(dev)
     u = torch.empty_like(fd)
@@ -351,9 +358,12 @@ def main() -> int:
     bytes_apply = info.bytes_m2l_op + info.bytes_m2l_vec * nrhs
     sec = m2l_ms * 1e-3 / args.steps  # M2L launch time per apply
     # the bound is whichever ceiling is lower for these flops and bytes
-    mfma_bound = flops_apply / (PEAK_FP32_MATRIX_TFLOPS * 1e12) >= bytes_apply / (PEAK_HBM_GBS * 1e9)
+    # a contraction is priced at the peak of its own MFMA dtype (16-bit plans: the
+    # algorithmic flops, not the three hardware products per term)
+    peak_mfma = PEAK_F16_MATRIX_TFLOPS if prec else PEAK_FP32_MATRIX_TFLOPS
+    mfma_bound = flops_apply / (peak_mfma * 1e12) >= bytes_apply / (PEAK_HBM_GBS * 1e9)
     if mfma_bound:
-        achieved, peak, unit = flops_apply / sec / 1e12, PEAK_FP32_MATRIX_TFLOPS, "TFLOP/s"
+        achieved, peak, unit = flops_apply / sec / 1e12, peak_mfma, "TFLOP/s"
     else:
         achieved, peak, unit = bytes_apply / sec / 1e9, PEAK_HBM_GBS, "GB/s"
     traffic = None
@@ -385,7 +395,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][0] + f", eps={eps_s}",
                    "K": K, "N": N, "nrhs": nrhs, "eps": eps, "w_top": info.w_top,

@@ -96,8 +96,23 @@ typedef struct {
                              sets, and the GEMM launch choices the first apply of each nrhs
                              measures (dfmm_tune_*.txt, keyed by launch shapes, nrhs, device) */
   int device;             /* HIP device ordinal; -1 = current device */
-  int reserved[7];
+  int precision;          /* DFMM_PREC_*: arithmetic of the translation GEMMs (default FP32) */
+  int reserved[6];
 } dfmm_options;
+
+/* Arithmetic of the translation GEMMs (M2M, M2L, L2L) of a plan.  FP32: float32
+ * MFMA.  FP16X3 / BF16X3: every operator entry a and vector entry x is split into
+ * a hi and a lo part of the 16-bit type (a = a_hi + a_lo to 22 resp. 16 bits)
+ * and a x is formed as a_hi x_hi + a_hi x_lo + a_lo x_hi on the 16-bit MFMA with
+ * float32 accumulation.  FP16X3 scales each operator (at plan time) and each
+ * source vector (per GEMM column, at staging) by a power of two into the fp16
+ * range and unscales the sums, and keeps float32-level accuracy; BF16X3 needs no
+ * scaling and keeps about 16 bits.  The near field and the leaf passes stay in
+ * float32 / float64.  Split precision is for fast plans only (eps >= 1e-5):
+ * DFMM_EINVAL otherwise. */
+#define DFMM_PREC_FP32 0
+#define DFMM_PREC_FP16X3 1
+#define DFMM_PREC_BF16X3 2
 
 /* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device. */
 void dfmm_options_default(dfmm_options* opt);

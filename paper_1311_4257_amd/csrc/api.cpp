@@ -281,6 +281,11 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
     std::unique_ptr<dfmm_plan_s> P(new dfmm_plan_s());
     P->device = dev;
     P->precise = opt->opset ? (opt->opset->tau < 3e-6) : (opt->eps < 1e-5);
+    if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_BF16X3)
+      return fail(DFMM_EINVAL, "unknown precision");
+    if (opt->precision != DFMM_PREC_FP32 && P->precise)
+      return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
+    P->prec = opt->precision;
     if (const char* dir = opt->cache_dir ? opt->cache_dir : std::getenv("DFMM_CACHE_DIR")) P->tune_dir = dir;
     PlanCtx ctx{opt, nullptr, nullptr};
     build_plan(*P, points, N, K, &plan_ops, &ctx);

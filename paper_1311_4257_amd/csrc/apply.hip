@@ -221,28 +221,71 @@ __device__ __forceinline__ float4 swap_pair(const float4 v) {
   return make_float4(sw(v.x), sw(v.y), sw(v.z), sw(v.w));
 }
 
+// ---- split 16-bit products (FP16X3 / BF16X3 plans) -----------------------------------
+// A 32-bit word holds two 16-bit values, the first in the low half.  x = hi + lo
+// with hi the 16-bit rounding of x and lo that of the (exact) remainder.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int PREC_F16 = 1, PREC_BF16 = 2;
+
+template <int PREC>
+__device__ __forceinline__ void split_pair(float a, float b, unsigned& hi, unsigned& lo) {
+  if constexpr (PREC == PREC_F16) {
+    const _Float16 ha = _Float16(a), hb = _Float16(b);
+    const _Float16 la = _Float16(a - float(ha)), lb = _Float16(b - float(hb));
+    hi = unsigned(__builtin_bit_cast(unsigned short, ha)) | (unsigned(__builtin_bit_cast(unsigned short, hb)) << 16);
+    lo = unsigned(__builtin_bit_cast(unsigned short, la)) | (unsigned(__builtin_bit_cast(unsigned short, lb)) << 16);
+  } else {
+    auto rne = [](float x) {  // bfloat16 bits, round to nearest even
+      const unsigned u = __float_as_uint(x);
+      return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    };
+    const unsigned ha = rne(a), hb = rne(b);
+    hi = ha | (hb << 16);
+    lo = rne(a - __uint_as_float(ha << 16)) | (rne(b - __uint_as_float(hb << 16)) << 16);
+  }
+}
+
+// (x, y) -> (y, x) of a word's two halves
+__device__ __forceinline__ unsigned rot16(unsigned x) { return __builtin_amdgcn_alignbit(x, x, 16); }
+
+template <int PREC>
+__device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
+  if constexpr (PREC == PREC_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                   0);
+}
+
 // ALDS: stage the workgroup's operator tiles in LDS first.  ACC64: every two
 // k-steps (32 real products per output) the float32 MFMA sums are added into
 // float64 partial sums, so the rounding of long float32 dot products (which
 // grows with their length) stays at that of 32 terms.
-template <int NT, bool ALDS, bool ACC64, int NW>
+template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const int64_t* __restrict__ aoff,
+                                           const int* __restrict__ aexp,
                                            const int* __restrict__ gmk, int M, int K, int split,
                                            const int* __restrict__ gops, const int* __restrict__ gv0,
                                            const int* __restrict__ vsrc, const int* __restrict__ vdst,
                                            const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
                                            int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
+  static_assert(!(ACC64 && PREC), "split 16-bit products are for fast plans");
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
   constexpr int PD = GgDepth<NT>::value;
   constexpr int BS = 64 * NW;
-  const int S4 = gg_stride(split * K) / 4;  // float4 per LDS column (split K >= every K_g)
+  // 16-bit plans: operators packed with K_g padded to 16 (two k-steps per MFMA)
+  auto kp = [](int k) { return PREC ? (k + 15) / 16 * 16 : k; };
+  const int S4 = gg_stride(split * kp(K)) / 4;  // float4 per LDS column (split K >= every K_g)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, kr = lane >> 4;
   const bool odd = (j & 1) != 0;
   const int g = chunk_grp[blockIdx.x];
-  const int Mg = gmk[2 * g], Kg = gmk[2 * g + 1];  // this group's operator size
+  const int Mg = gmk[2 * g], Kr = gmk[2 * g + 1];  // this group's operator size
+  const int Kg = kp(Kr);                 // packed K (Kr + zero columns in 16-bit plans)
   const int Q4 = Kg / 8;                 // k-steps per tile (K_g / 2 real k per quarter, 4 per step)
   const int nM = Mg / 8, nMall = M / 8;  // 16-row real M-tiles with data / in the vector stride
   const int m0 = wave + NW * int(blockIdx.y), mstep = NW * int(gridDim.y);
@@ -259,6 +302,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   // batch of loads before storing them.
   const int per_col = Kg / 2;  // float4 per column
   const int pcs = per_col / split;  // float4 per source vector (split = 2: each read twice)
+  const int preal = Kr / 2;         // float4 of the column that the vector holds (rest: zero padding)
   const float4* Aop = A + aoff[gops[g]];
   const int tile4 = Q4 * 32;  // float4 per M-tile in the fragment order
   float4* as = xs + NC * S4;  // ALDS: the tiles of this slice, [t][wave][tile4]
@@ -325,7 +369,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
         dst[u] = -1;
         if (base + u * BS < nel) {
           const float4* p = colsrc[col];
-          if (p) v[u] = p[q4 < pcs ? q4 : q4 - pcs];
+          if (p && (!PREC || q4 < preal)) v[u] = p[q4 < pcs ? q4 : q4 - pcs];
           dst[u] = col * S4 + q4;
         }
         col += dcol;
@@ -338,6 +382,40 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 #pragma unroll
       for (int u = 0; u < UB; ++u)
         if (dst[u] >= 0) xs[dst[u]] = v[u];
+    }
+  }
+  __shared__ int cexp[NC];  // 16-bit plans: power-of-two scale exponent of each column
+  if constexpr (PREC != 0) {
+    __syncthreads();  // the float32 columns are staged
+    if (threadIdx.x < NC) {
+      int e = 0;
+      if constexpr (PREC == PREC_F16) {  // largest column entry below 2^14 after scaling
+        float mx = 0.f;
+        const float4* c = xs + threadIdx.x * S4;
+        for (int q = 0; q < per_col; ++q) {
+          const float4 v = c[q];
+          mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+        if (mx > 0.f) {
+          int E;
+          (void)frexpf(mx, &E);
+          e = 14 - E;
+        }
+      }
+      cexp[threadIdx.x] = e;
+    }
+    __syncthreads();
+    for (int idx = int(threadIdx.x); idx < NC * per_col; idx += BS) {
+      const int col = idx / per_col, q = idx - col * per_col;
+      float4 v = xs[col * S4 + q];
+      if constexpr (PREC == PREC_F16) {
+        const int e = cexp[col];
+        v = make_float4(ldexpf(v.x, e), ldexpf(v.y, e), ldexpf(v.z, e), ldexpf(v.w, e));
+      }
+      unsigned h0, l0, h1, l1;
+      split_pair<PREC>(v.x, v.y, h0, l0);
+      split_pair<PREC>(v.z, v.w, h1, l1);
+      xs[col * S4 + q] = make_float4(__uint_as_float(h0), __uint_as_float(h1), __uint_as_float(l0), __uint_as_float(l1));
     }
   }
   if (ALDS) {
@@ -375,7 +453,80 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
     }
   }
 
-  if (total > 0) {
+  if constexpr (PREC != 0) {
+    if (total > 0) {
+      // operator scale of the group and column scales: the sums are unscaled at the write
+      const int ea = PREC == PREC_F16 ? aexp[gops[g]] : 0;
+      float osc[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) osc[n] = ldexpf(1.0f, -(ea + cexp[n * 16 + j]));
+      v4f acc[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+      const float4* bcol = xs + j * S4 + kr * Q4;
+      float4 b0[NT], b1[NT];  // steps s, s + 1 of every column tile (hi, hi, lo, lo words)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        b0[n] = bcol[n * 16 * S4];
+        b1[n] = bcol[n * 16 * S4 + 1];
+      }
+      int s = 0, t = 0;
+      constexpr unsigned SG = 0x80000000u;  // sign of a word's high half
+      // one ring slot = two k-steps = one 16x16x32 MFMA per product term; the
+      // even row of a complex row pair is (Re, -Im), the odd row (Im, Re)
+      auto dstep = [&](const float4 vf, const float4 wf) {
+        const unsigned vx = __float_as_uint(vf.x), vy = __float_as_uint(vf.y), vz = __float_as_uint(vf.z),
+                       vw = __float_as_uint(vf.w), wx = __float_as_uint(wf.x), wy = __float_as_uint(wf.y),
+                       wz = __float_as_uint(wf.z), ww = __float_as_uint(wf.w);
+        const v4u ah = odd ? v4u{rot16(wx), rot16(wy), rot16(vx), rot16(vy)} : v4u{vx ^ SG, vy ^ SG, wx ^ SG, wy ^ SG};
+        const v4u al = odd ? v4u{rot16(wz), rot16(ww), rot16(vz), rot16(vw)} : v4u{vz ^ SG, vw ^ SG, wz ^ SG, ww ^ SG};
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const v4u bh = {__float_as_uint(b0[n].x), __float_as_uint(b0[n].y), __float_as_uint(b1[n].x),
+                          __float_as_uint(b1[n].y)};
+          const v4u bl = {__float_as_uint(b0[n].z), __float_as_uint(b0[n].w), __float_as_uint(b1[n].z),
+                          __float_as_uint(b1[n].w)};
+          acc[n] = mfma16<PREC>(ah, bh, acc[n]);
+          acc[n] = mfma16<PREC>(ah, bl, acc[n]);
+          acc[n] = mfma16<PREC>(al, bh, acc[n]);
+        }
+        s += 2;
+        const int s2 = s == Q4 ? 0 : s;  // the next step pair (the column is the same for every M-tile)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          b0[n] = bcol[n * 16 * S4 + s2];
+          b1[n] = bcol[n * 16 * S4 + s2 + 1];
+        }
+        if (s == Q4) {  // tile done: lane holds real rows 4kr .. 4kr+3 = complex rows 2kr, 2kr+1
+          const int m = m0 + mstep * t;
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const v4f a = acc[n];
+            const float4 o = make_float4(a[0] * osc[n], a[1] * osc[n], a[2] * osc[n], a[3] * osc[n]);
+            if (yp[n]) reinterpret_cast<float4*>(yp[n] + 8 * m + 2 * kr)[0] = o;
+            acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+          s = 0;
+          ++t;
+        }
+      };
+      int i0 = 0;  // total is even: Q4 is even in 16-bit plans
+      for (; i0 + 2 * PD <= total; i0 += 2 * PD) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p) {
+          const float4 v = ring[p], w = swap_pair(v);
+          dstep(v, w);
+          ring[p] = fetch();
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < PD; ++p) {
+        if (i0 + 2 * p >= total) break;
+        const float4 v = ring[p], w = swap_pair(v);
+        dstep(v, w);
+      }
+    }
+  } else if (total > 0) {
     v4f acc[NT];  // consecutive MFMAs on one accumulator chain through its C operand
     double a64[ACC64 ? NT : 1][4];
 #pragma unroll
@@ -483,21 +634,22 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 }
 
 #define DFMM_GG_PARAMS                                                                                       \
-  const float4 *__restrict__ A, const int64_t *__restrict__ aoff, const int *__restrict__ gmk, int M, int K,  \
+  const float4 *__restrict__ A, const int64_t *__restrict__ aoff, const int *__restrict__ aexp,               \
+      const int *__restrict__ gmk, int M, int K,                                                               \
       int split, const int *__restrict__ gops, const int *__restrict__ gv0, const int *__restrict__ vsrc,      \
       const int *__restrict__ vdst, const int *__restrict__ chunk_grp, const int *__restrict__ chunk_c0,       \
       int nrhs, const float2 *__restrict__ X, float2 *__restrict__ Y
-#define DFMM_GG_ARGS A, aoff, gmk, M, K, split, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
+#define DFMM_GG_ARGS A, aoff, aexp, gmk, M, K, split, gops, gv0, vsrc, vdst, chunk_grp, chunk_c0, nrhs, X, Y
 
 // The same tile engine under two names, so that kernel traces separate the
 // translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
-template <int NT, bool ALDS, bool ACC64, int NW>
+template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 __global__ void __launch_bounds__(64 * NW) k_m2l(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64, NW>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS);
 }
-template <int NT, bool ALDS, bool ACC64, int NW>
+template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 __global__ void __launch_bounds__(64 * NW) k_transfer(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64, NW>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS);
 }
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
@@ -1003,39 +1155,49 @@ constexpr int kGgDynLds = 159 * 1024;
 // M-tiles per wave of the largest group for a given number of M-slices
 static int gg_mt(const GGemm& G, int slices) { return (G.M / 8 + 4 * slices - 1) / (4 * slices); }
 
-template <int NT, bool ALDS, bool ACC64, int NW>
+template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
-  const size_t lds = gg_lds_total(G.K * G.split, NT, gg_mt(G, L.slices), ALDS);
-  auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64, NW> : &k_transfer<NT, ALDS, ACC64, NW>;
+  const size_t lds = gg_lds_total(kpad(G.K, G.prec) * G.split, NT, gg_mt(G, L.slices), ALDS);
+  auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64, NW, PREC> : &k_transfer<NT, ALDS, ACC64, NW, PREC>;
   static bool attr = false;
   if (!attr) {
-    for (auto k : {&k_m2l<NT, ALDS, ACC64, NW>, &k_transfer<NT, ALDS, ACC64, NW>})
+    for (auto k : {&k_m2l<NT, ALDS, ACC64, NW, PREC>, &k_transfer<NT, ALDS, ACC64, NW, PREC>})
       DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    kGgDynLds));
     attr = true;
   }
   hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(64 * NW), lds, st,
-                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.gmk.as<int>(), G.M, G.K, G.split, G.ops.as<int>(),
+                     G.A.as<float4>(), G.aoff.as<int64_t>(), G.aexp.as<int>(), G.gmk.as<int>(), G.M, G.K, G.split,
+                     G.ops.as<int>(),
                      G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), L.grp.as<int>(), L.col0.as<int>(), nrhs,
                      X, Y);
 }
 
+template <int NT, int PREC>
+static void launch_nt_p(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  if (L.nw == 2) launch_nt_a<NT, false, false, 2, PREC>(L, nrhs, X, Y, st);
+  else if (L.alds) launch_nt_a<NT, true, false, 4, PREC>(L, nrhs, X, Y, st);
+  else launch_nt_a<NT, false, false, 4, PREC>(L, nrhs, X, Y, st);
+}
+
 template <int NT>
 static void launch_nt(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
+  if (L.G->prec == DFMM_PREC_FP16X3) return launch_nt_p<NT, PREC_F16>(L, nrhs, X, Y, st);
+  if (L.G->prec == DFMM_PREC_BF16X3) return launch_nt_p<NT, PREC_BF16>(L, nrhs, X, Y, st);
   if (L.nw == 2) {
-    if (L.G->acc64) launch_nt_a<NT, false, true, 2>(L, nrhs, X, Y, st);  // precise plans
-    else launch_nt_a<NT, false, false, 2>(L, nrhs, X, Y, st);
+    if (L.G->acc64) launch_nt_a<NT, false, true, 2, 0>(L, nrhs, X, Y, st);  // precise plans
+    else launch_nt_a<NT, false, false, 2, 0>(L, nrhs, X, Y, st);
   } else {
-    if (L.G->acc64) launch_nt_a<NT, false, true, 4>(L, nrhs, X, Y, st);
-    else if (L.alds) launch_nt_a<NT, true, false, 4>(L, nrhs, X, Y, st);
-    else launch_nt_a<NT, false, false, 4>(L, nrhs, X, Y, st);
+    if (L.G->acc64) launch_nt_a<NT, false, true, 4, 0>(L, nrhs, X, Y, st);
+    else if (L.alds) launch_nt_a<NT, true, false, 4, 0>(L, nrhs, X, Y, st);
+    else launch_nt_a<NT, false, false, 4, 0>(L, nrhs, X, Y, st);
   }
 }
 
 static bool gg_fits(const GGemm& G, int nt, int slices, bool alds, int nw) {
   if (alds && (G.acc64 || nw != 4)) return false;
-  return gg_lds_total(G.K * G.split, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
+  return gg_lds_total(kpad(G.K, G.prec) * G.split, nt, gg_mt(G, slices), alds) <= size_t(kGgDynLds);
 }
 
 static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
@@ -1165,7 +1327,7 @@ static std::string tune_path(const dfmm_plan_s& P, const std::vector<const GGemm
   fnv(h, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
   fnv(h, &nrhs, sizeof(nrhs));
   for (const GGemm* g : gs) {
-    const int64_t dims[7] = {g->M, g->K, g->T, g->ngroups, g->nvec, g->split, int64_t(g->acc64)};
+    const int64_t dims[8] = {g->M, g->K, g->T, g->ngroups, g->nvec, g->split, int64_t(g->acc64), g->prec};
     fnv(h, dims, sizeof(dims));
     fnv(h, g->v0_h.data(), g->v0_h.size() * sizeof(int32_t));
   }

@@ -105,6 +105,9 @@ struct GGemm {
   int split = 1;             // 2: each operator is [T_hi | T_lo] (K doubled) and every source
                              // vector is read twice, so the float32 rounding of T cancels
   bool acc64 = false;        // float64 partial sums every two k-steps (precise plans)
+  int prec = 0;              // DFMM_PREC_*: FP16X3 / BF16X3 hold A as 16-bit hi + lo pairs, K padded
+                             // to 16 (kpad), one power-of-two scale exponent per operator (aexp)
+  DevBuf aexp;               // int32[nops] (FP16X3)
   int64_t ngroups = 0, nvec = 0, nops = 0;
   DevBuf A;                  // operators in fragment order, op i at float4 offset aoff[i]
   DevBuf aoff;               // int64[nops]
@@ -122,6 +125,14 @@ void pack_operator(const double* Tc, int M, int K, float* out);
 // pack_operator of T (split = 1) or of [T_hi | T_lo] (split = 2), T_hi the float32
 // rounding of T and T_lo that of the remainder; out holds 2 M K split floats
 void pack_operator_split(const double* Tc, int M, int K, int split, float* out);
+// K of a packed operator: a multiple of 16 for the 16-bit MFMA (two k-steps per instruction)
+inline int kpad(int K, int prec) { return prec ? (K + 15) / 16 * 16 : K; }
+// Convert nops packed float32 operators (stride floats apart) in place to the
+// hi + lo 16-bit format of prec: each float4 slot (re0, im0, re1, im1) becomes
+// four 32-bit words (hi re0 | hi im0), (hi re1 | hi im1), (lo re0 | lo im0),
+// (lo re1 | lo im1), low half first.  FP16X3 first scales operator i by
+// 2^aexp[i] so that its largest entry is below 2^14.
+void to_half_ops(std::vector<float>& A, int64_t nops, int64_t stride, int prec, std::vector<int32_t>& aexp);
 
 // ---- one HF level of the plan -------------------------------------------------
 struct HFLevel {
@@ -254,6 +265,7 @@ struct dfmm_plan_s {
   int D = 0;       // leaf level
   int w_top = 0;
   bool precise = false;  // eps < 1e-5: float64 near-field distances, split HF operators
+  int prec = 0;          // DFMM_PREC_*: arithmetic of the translation GEMMs
   double plan_seconds = 0.0;
   std::string tune_dir;  // where GEMM launch choices are kept (empty: not kept)
   dfmm_info info{};

@@ -88,6 +88,89 @@ void pack_operator_split(const double* Tc, int M, int K, int split, float* out) 
   pack_operator(T2.data(), M, 2 * K, out);
 }
 
+// float32 -> IEEE binary16 bits, round to nearest even (subnormals kept; the
+// callers scale every value below 2^14, so there is no overflow)
+static uint16_t f32_to_f16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  x &= 0x7FFFFFFFu;
+  if (x >= 0x477FF000u) return uint16_t(sign | 0x7C00u);  // rounds past 65504: infinity
+  if (x < 0x38800000u) {                                   // below 2^-14: subnormal or zero
+    if (x <= 0x33000000u) return uint16_t(sign);           // <= 2^-25 rounds to zero
+    const uint32_t mant = (x & 0x7FFFFFu) | 0x800000u;
+    const int shift = 126 - int(x >> 23);                  // value = mant 2^(e - 150) = m 2^-24
+    uint32_t m = mant >> shift;
+    const uint32_t rem = mant & ((1u << shift) - 1u), half = 1u << (shift - 1);
+    if (rem > half || (rem == half && (m & 1u))) ++m;
+    return uint16_t(sign | m);
+  }
+  uint32_t r = x - 0x38000000u;  // rebias the exponent from 127 to 15
+  r += 0xFFFu + ((r >> 13) & 1u);
+  return uint16_t(sign | (r >> 13));
+}
+
+static float f16_to_f32(uint16_t h) {
+  const uint32_t sign = uint32_t(h & 0x8000u) << 16, e = (h >> 10) & 0x1Fu, m = h & 0x3FFu;
+  float v;
+  if (e == 0) v = std::ldexp(float(m), -24);
+  else v = std::ldexp(float(m | 0x400u), int(e) - 25);
+  uint32_t b;
+  std::memcpy(&b, &v, 4);
+  b |= sign;
+  std::memcpy(&v, &b, 4);
+  return v;
+}
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs)
+static uint16_t f32_to_bf16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  x += 0x7FFFu + ((x >> 16) & 1u);
+  return uint16_t(x >> 16);
+}
+
+static float bf16_to_f32(uint16_t h) {
+  const uint32_t b = uint32_t(h) << 16;
+  float v;
+  std::memcpy(&v, &b, 4);
+  return v;
+}
+
+void to_half_ops(std::vector<float>& A, int64_t nops, int64_t stride, int prec, std::vector<int32_t>& aexp) {
+  aexp.assign(size_t(nops), 0);
+  parallel_for(nops, [&](int64_t i) {
+    float* a = A.data() + size_t(i) * size_t(stride);
+    int e = 0;
+    if (prec == DFMM_PREC_FP16X3) {
+      float mx = 0.0f;
+      for (int64_t k = 0; k < stride; ++k) mx = std::max(mx, std::fabs(a[k]));
+      if (mx > 0.0f) {
+        int E = 0;
+        (void)std::frexp(mx, &E);  // mx < 2^E
+        e = 14 - E;
+      }
+    }
+    aexp[size_t(i)] = e;
+    for (int64_t k = 0; k < stride; k += 4) {
+      uint16_t hi[4], lo[4];
+      for (int c = 0; c < 4; ++c) {
+        const float v = std::ldexp(a[k + c], e);
+        if (prec == DFMM_PREC_FP16X3) {
+          hi[c] = f32_to_f16(v);
+          lo[c] = f32_to_f16(v - f16_to_f32(hi[c]));
+        } else {
+          hi[c] = f32_to_bf16(v);
+          lo[c] = f32_to_bf16(v - bf16_to_f32(hi[c]));
+        }
+      }
+      const uint32_t w[4] = {uint32_t(hi[0]) | uint32_t(hi[1]) << 16, uint32_t(hi[2]) | uint32_t(hi[3]) << 16,
+                             uint32_t(lo[0]) | uint32_t(lo[1]) << 16, uint32_t(lo[2]) | uint32_t(lo[3]) << 16};
+      std::memcpy(a + k, w, 16);
+    }
+  });
+}
+
 namespace {
 
 }  // namespace
@@ -250,7 +333,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     }
     std::vector<int32_t> vdst(vsrc.size());
     for (size_t i = 0; i < vdst.size(); ++i) vdst[i] = int32_t(i);
-    std::vector<float> At(size_t(2) * R * R * split * ngroups, 0.0f);
+    const int RK = kpad(R, P.prec);  // packed K of every operator of the launch
+    std::vector<float> At(size_t(2) * R * RK * split * ngroups, 0.0f);
     std::vector<int32_t> gmk(size_t(2) * ngroups);
     std::vector<int64_t> aoff(ngroups);
     parallel_for(ngroups, [&](int64_t gi) {
@@ -262,8 +346,9 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       const int Mg = pad8(si->r), Kg = pad8(so->r);
       gmk[2 * gi] = Mg;
       gmk[2 * gi + 1] = Kg * split;
-      aoff[gi] = int64_t(gi) * R * R * split / 2;
-      std::vector<double> G(size_t(2) * so->r), T(size_t(2) * Mg * Kg, 0.0);
+      aoff[gi] = int64_t(gi) * R * RK * split / 2;
+      const int Kp = kpad(Kg, P.prec);
+      std::vector<double> G(size_t(2) * so->r), T(size_t(2) * Mg * Kp, 0.0);
       for (int q = 0; q < si->r; ++q) {
         for (int p = 0; p < so->r; ++p)
           green64(si->b[3 * q] - (sx + so->b[3 * p]), si->b[3 * q + 1] - (sy + so->b[3 * p + 1]),
@@ -276,12 +361,18 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi2 * di;
             im += gr * di + gi2 * dr;
           }
-          T[2 * (size_t(q) * Kg + j)] = re;
-          T[2 * (size_t(q) * Kg + j) + 1] = im;
+          T[2 * (size_t(q) * Kp + j)] = re;
+          T[2 * (size_t(q) * Kp + j) + 1] = im;
         }
       }
-      pack_operator_split(T.data(), Mg, Kg, split, &At[size_t(2) * R * R * split * gi]);
+      pack_operator_split(T.data(), Mg, Kp, split, &At[size_t(2) * R * RK * split * gi]);
     });
+    if (P.prec) {
+      std::vector<int32_t> aexp;
+      to_half_ops(At, ngroups, int64_t(2) * R * RK * split, P.prec, aexp);
+      G.aexp.upload(aexp);
+    }
+    G.prec = P.prec;
     G.M = R;
     G.K = R;
     G.T = 1;
@@ -347,7 +438,9 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     // G(b^c + delta_o, a^{w,l}) (D^{w,l})^T (Rc x R) maps the parent's incoming
     // check potentials to the child's (c = the child skeleton of wedge l).
     int ndir = int(6 * w * w);
-    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * H.Rc * hf_split, 0.0f), Md(Mu.size(), 0.0f);
+    const int KU = kpad(H.Rc, P.prec), KD = kpad(H.R, P.prec);  // packed K of the up / down operators
+    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * KU * hf_split, 0.0f);
+    std::vector<float> Md(size_t(2) * ndir * 8 * H.Rc * KD * hf_split, 0.0f);
     std::vector<char> dir_used(ndir, 0);
     for (auto& s : OS[l].list) dir_used[s.second] = 1;
     for (auto& s : IS[l].list) dir_used[s.second] = 1;
@@ -368,7 +461,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       const int Ms = pad8(s.r), Mc = pad8(c.r);
       op_ms[id] = Ms;
       op_mc[id] = Mc;
-      std::vector<double> up(size_t(2) * Ms * Mc, 0.0), dn(size_t(2) * Mc * Ms, 0.0);
+      const int Kpu = kpad(Mc, P.prec), Kpd = kpad(Ms, P.prec);
+      std::vector<double> up(size_t(2) * Ms * Kpu, 0.0), dn(size_t(2) * Mc * Kpd, 0.0);
       for (int p = 0; p < s.r; ++p)
         for (int k = 0; k < c.r; ++k) {  // (G D^c)[p][k]
           double re = 0.0, im = 0.0;
@@ -378,8 +472,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          up[2 * (size_t(p) * Mc + k)] = re;
-          up[2 * (size_t(p) * Mc + k) + 1] = im;
+          up[2 * (size_t(p) * Kpu + k)] = re;
+          up[2 * (size_t(p) * Kpu + k) + 1] = im;
         }
       for (int j = 0; j < c.r; ++j)
         for (int q = 0; q < s.r; ++q) {  // (G^T D^T)[j][q] = sum_p G[p][j] D[q][p]
@@ -390,11 +484,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             re += gr * dr - gi * di;
             im += gr * di + gi * dr;
           }
-          dn[2 * (size_t(j) * Ms + q)] = re;
-          dn[2 * (size_t(j) * Ms + q) + 1] = im;
+          dn[2 * (size_t(j) * Kpd + q)] = re;
+          dn[2 * (size_t(j) * Kpd + q) + 1] = im;
         }
-      pack_operator_split(up.data(), Ms, Mc, hf_split, &Mu[size_t(2) * id * H.R * H.Rc * hf_split]);
-      pack_operator_split(dn.data(), Mc, Ms, hf_split, &Md[size_t(2) * id * H.R * H.Rc * hf_split]);
+      pack_operator_split(up.data(), Ms, Kpu, hf_split, &Mu[size_t(2) * id * H.R * KU * hf_split]);
+      pack_operator_split(dn.data(), Mc, Kpd, hf_split, &Md[size_t(2) * id * H.Rc * KD * hf_split]);
     });
 
     // HF-M2M and HF-L2L as pair lists: one pair per (parent slot, child), grouped
@@ -406,7 +500,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       // by_op[op] = list of (source vector, destination slot)
       std::vector<int32_t> v0(1, 0), vsrc, vdst, opsv, gmk;
       std::vector<int64_t> aoff(nops);
-      for (int64_t op = 0; op < nops; ++op) aoff[op] = op * int64_t(M) * K * hf_split / 2;
+      for (int64_t op = 0; op < nops; ++op) aoff[op] = op * int64_t(M) * kpad(K, P.prec) * hf_split / 2;
       std::vector<std::vector<int32_t>> per(ndst);
       for (int64_t op = 0; op < int64_t(by_op.size()); ++op) {
         if (by_op[op].empty()) continue;
@@ -430,6 +524,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       G.T = 1;
       G.split = hf_split;
       G.acc64 = P.precise;
+      G.prec = P.prec;
       G.ngroups = int64_t(v0.size()) - 1;
       G.nvec = int64_t(vsrc.size());
       G.nops = nops;
@@ -452,6 +547,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           int32_t src = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
           by_op[size_t(d) * 8 + C.octant[c]].push_back({src, int32_t(i)});
         }
+      }
+      if (P.prec) {
+        std::vector<int32_t> aexp;
+        to_half_ops(Mu, int64_t(ndir) * 8, int64_t(2) * H.R * KU * hf_split, P.prec, aexp);
+        H.m2m.aexp.upload(aexp);
       }
       H.m2m.A.upload(Mu);
       finish_pairs(H.m2m, by_op, H.R, H.Rc, int64_t(ndir) * 8, H.nout, H.m2m_rs, H.m2m_ri, H.m2m_npairs, op_ms,
@@ -483,6 +583,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
               if (sidx >= 0) by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(i)});
             }
         }
+      }
+      if (P.prec) {
+        std::vector<int32_t> aexp;
+        to_half_ops(Md, int64_t(ndir) * 8, int64_t(2) * H.Rc * KD * hf_split, P.prec, aexp);
+        H.l2l.aexp.upload(aexp);
       }
       H.l2l.A.upload(Md);
       finish_pairs(H.l2l, by_op, H.Rc, H.R, int64_t(ndir) * 8, H.nchild_in, H.l2l_rs, H.l2l_ri, H.l2l_npairs,

@@ -29,6 +29,7 @@ STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2
           "leaf_eval", "zero", "near_field"]
 
 MAX_BATCH = 32  # DFMM_MAX_BATCH
+PREC_FP32, PREC_FP16X3, PREC_BF16X3 = 0, 1, 2  # DFMM_PREC_*
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
 
@@ -42,7 +43,7 @@ ABI_FUNCTIONS = [
 
 class Options(C.Structure):
     _fields_ = [("eps", C.c_double), ("opset", C.c_void_p), ("cache_dir", C.c_char_p),
-                ("device", C.c_int), ("reserved", C.c_int * 7)]
+                ("device", C.c_int), ("precision", C.c_int), ("reserved", C.c_int * 6)]
 
 
 class Info(C.Structure):
@@ -172,7 +173,7 @@ class Plan:
     """A resident plan for one point set: dfmm_plan / dfmm_plan_ex."""
 
     def __init__(self, points, K: float, eps: float = 1e-4, opset: OpSet | None = None,
-                 cache_dir: str | None = None, device: int = -1):
+                 cache_dir: str | None = None, device: int = -1, precision: int = 0):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2 or pts.shape[1] != 3:
             raise ValueError("points must be (N, 3)")
@@ -183,6 +184,7 @@ class Plan:
         self._cache = cache_dir.encode() if cache_dir else None
         opt.cache_dir = self._cache
         opt.device = device
+        opt.precision = precision
         h = _P()
         _check(_lib.dfmm_plan_ex(_dptr(pts), pts.shape[0], float(K), C.byref(opt), C.byref(h)))
         self._h = h

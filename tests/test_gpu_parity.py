@@ -235,3 +235,30 @@ def test_ellipsoid32_nrhs32_sampled_targets(cuda):
     worst = max(rel_l2(u[k, tg], ref[k]) for k in range(f.shape[0]))
     print(f"ellipsoid32 nrhs=32: rel L2 {err:.2e} (worst rhs {worst:.2e}), w_top {plan.info().w_top}")
     assert err <= cfg["eps"]
+
+
+@pytest.mark.parametrize("nrhs", [1, 6])
+def test_split_precision_plans(cuda, nrhs):
+    """FP16X3 / BF16X3 translation GEMMs (hi/lo 16-bit products, float32 sums)
+    against the float32 plan on the same skeletons: FP16X3 (scaled, 22-bit
+    operands) to float32 level, BF16X3 (16-bit operands) to ~1e-5; both within
+    eps of the direct sum.  Split precision is refused for precise plans."""
+    dfmm = _dfmm()
+    pts = workloads.sphere_points(16384, 8.0, 31)
+    f = workloads.densities(len(pts), nrhs, 32)
+    fd = _to_dev(f, cuda)
+    tg = workloads.sample_targets(len(pts), 512, 33)
+    ref = direct_sum(pts, f, tg)
+    u = {}
+    for prec in (dfmm.PREC_FP32, dfmm.PREC_FP16X3, dfmm.PREC_BF16X3):
+        plan = dfmm.Plan(pts, 8.0, eps=1e-4, cache_dir=CACHE, device=0, precision=prec)
+        u[prec] = plan.apply(fd).cpu().numpy().astype(np.complex128)
+    d16 = rel_l2(u[dfmm.PREC_FP16X3], u[dfmm.PREC_FP32])
+    dbf = rel_l2(u[dfmm.PREC_BF16X3], u[dfmm.PREC_FP32])
+    errs = {p: rel_l2(v[:, tg], ref) for p, v in u.items()}
+    print(f"nrhs={nrhs}: fp16x3 vs fp32 {d16:.2e}, bf16x3 vs fp32 {dbf:.2e}, vs direct sum {errs}")
+    assert d16 < 2e-6
+    assert dbf < 1e-4
+    assert all(e <= 1e-4 for e in errs.values())
+    with pytest.raises(dfmm.DfmmError):
+        dfmm.Plan(pts[:512] / 2, 4.0, eps=1e-6, cache_dir=CACHE, device=0, precision=dfmm.PREC_FP16X3)
