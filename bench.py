@@ -159,23 +159,29 @@ def serving_bench(args) -> int:
 
     dev = torch.device("cuda:0")
     eps = 1e-4 if args.eps is None else args.eps
-    plans, names, pts_all, plan_s = [], [], [], []
+    prec_b, dtype_b = PRECISIONS[args.precision]
+    plans, bplans, names, pts_all, plan_s = [], [], [], [], []
     for name, kind, K, N, seed in workloads.SERVING_PLANS:
         pts = workloads.serving_points(kind, K, N, seed)
         t = time.perf_counter()
         plans.append(dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0))
         plan_s.append(time.perf_counter() - t)
+        # the batched form runs plans of its own precision (the same plans at fp32)
+        bplans.append(plans[-1] if prec_b == 0 else
+                      dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0, precision=prec_b))
         names.append(name)
         pts_all.append(pts)
         _log(f"plan {name}: N={N} K={K:g} {plan_s[-1]:.2f} s")
     # accuracy of each plan alone against the direct sum (256 sampled targets)
-    acc = {}
+    acc, acc_b = {}, {}
     for p, plan in enumerate(plans):
         f = workloads.densities(plan.N, 1, 600 + p)
-        u = plan.apply(torch.from_numpy(f.astype(np.complex64)).to(dev)).cpu().numpy()
+        fd = torch.from_numpy(f.astype(np.complex64)).to(dev)
         tg = workloads.sample_targets(plan.N, 256, 700 + p)
-        acc[names[p]] = rel_l2(u.astype(np.complex128)[:, tg], direct_sum(pts_all[p], f, tg))
-        _log(f"accuracy {names[p]}: {acc[names[p]]:.2e}")
+        ref = direct_sum(pts_all[p], f, tg)
+        acc[names[p]] = rel_l2(plan.apply(fd).cpu().numpy().astype(np.complex128)[:, tg], ref)
+        acc_b[names[p]] = rel_l2(bplans[p].apply(fd).cpu().numpy().astype(np.complex128)[:, tg], ref)
+        _log(f"accuracy {names[p]}: fp32 {acc[names[p]]:.2e}, batched form {acc_b[names[p]]:.2e}")
 
     n = args.requests
     pidx, nrhs, gaps = workloads.serving_mix(n, len(plans), 505)
@@ -190,7 +196,7 @@ def serving_bench(args) -> int:
     work = sum(plans[r.plan].N * r.nrhs for r in reqs)
     budget = 200 << 30
     single = Server(plans, budget, mode="single")
-    batched = Server(plans, budget, max_batch_rhs=32, mode="batched")
+    batched = Server(bplans, budget, max_batch_rhs=32, mode="batched")
     single.warm([1, 4, 16])
     batched.warm([1, 2, 4, 8, 16, 32])
     _log(f"warm: footprint {batched.footprint() / 2**30:.1f} GiB of {budget / 2**30:.0f} GiB")
@@ -212,7 +218,7 @@ def serving_bench(args) -> int:
     # the same requests alone and in the mix: compare a sample of batched results
     diffs = []
     for r in reqs[:: max(1, n // 60)]:
-        a = plans[r.plan].apply(r.f)
+        a = bplans[r.plan].apply(r.f)
         diffs.append(float(torch.linalg.norm(r.u - a) / torch.linalg.norm(a)))
     cap_req = n / out_runs["saturation"]["single"]["span_s"]
     loads = []
@@ -235,14 +241,17 @@ def serving_bench(args) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_b,
         "data": "synthetic",
         "config": {"workload": f"serving mix: {n} requests over 6 resident plans "
                                f"({', '.join(names)}), nrhs uniform over {{1, 4, 16}}, complex64 N(0,1) "
                                f"densities (seed 505), eps={eps:g}; value = continuous-batching throughput "
                                f"with every request queued at t=0",
-                   "plans": [{"name": nm, "N": pl.N, "plan_s": round(ps, 3), "rel_l2_err": acc[nm]}
+                   "plans": [{"name": nm, "N": pl.N, "plan_s": round(ps, 3), "rel_l2_err_fp32": acc[nm],
+                              "rel_l2_err_batched_form": acc_b[nm]}
                              for nm, pl, ps in zip(names, plans, plan_s)],
+                   "single_form": "fp32, one request per pass, one pass at a time",
+                   "batched_form": f"{args.precision}, continuous batching per plan, plans concurrent",
                    "max_batch_rhs": 32, "hbm_budget_gib": budget / 2 ** 30},
         "serving": {
             "saturation": sat,
@@ -254,6 +263,49 @@ def serving_bench(args) -> int:
         },
     }
     print(json.dumps(line))
+    return 0
+
+
+def precision_study(args) -> int:
+    """Error of each GEMM arithmetic against the float64 direct sum on the K = 32
+    ellipsoid (N = 262,144, 8 right-hand sides, 4,096 sampled targets, seed 404)."""
+    import numpy as np
+    import torch
+
+    from oracle.kernel import direct_sum, rel_l2
+    from paper_1311_4257_amd import dfmm, workloads
+
+    pts, _, cfg = workloads.make_config("ellipsoid32")
+    K, N = cfg["K"], cfg["N"]
+    nrhs = 8
+    f = workloads.densities(N, nrhs, 404)
+    tg = workloads.sample_targets(N, 4096, 404)
+    t = time.perf_counter()
+    ref = direct_sum(pts, f, tg)
+    _log(f"direct sum on {len(tg)} targets: {time.perf_counter() - t:.1f} s")
+    fd = torch.from_numpy(f.astype(np.complex64)).to("cuda:0")
+    rows, u32 = {}, None
+    for name in ("fp32", "fp16x3", "bf16x3"):
+        prec, dtype = PRECISIONS[name]
+        plan = dfmm.Plan(pts, K, eps=1e-4, cache_dir=CACHE_DIR, device=0, precision=prec)
+        u = plan.apply(fd)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            plan.apply(fd, u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        un = u.cpu().numpy().astype(np.complex128)
+        if u32 is None:
+            u32 = un
+        rows[name] = {"dtype": dtype, "rel_l2_err": rel_l2(un[:, tg], ref),
+                      "max_rhs_rel_l2_err": max(rel_l2(un[k:k + 1, tg], ref[k:k + 1]) for k in range(nrhs)),
+                      "rel_l2_diff_vs_fp32": rel_l2(un, u32), "ms_per_apply": ms,
+                      "matvecs_per_s": N * nrhs / (ms * 1e-3)}
+        _log(f"{name}: {json.dumps(rows[name])}")
+        plan.close()
+    print(json.dumps({"study": "precision", "workload": "ellipsoid32 (16, 8, 4), K=32, N=262144, nrhs=8, eps=1e-4, "
+                      "4096 targets (seed 404) against the float64 direct sum", "results": rows}))
     return 0
 
 
@@ -272,6 +324,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
                     help="arithmetic of the translation GEMMs (fp32, or split 16-bit products)")
     ap.add_argument("--requests", type=int, default=2000, help="requests per serving run")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="error per GEMM arithmetic on the K=32 ellipsoid with 8 rhs")
     args = ap.parse_args()
     if args.traffic_summary:
         rec = traffic_summary(*args.traffic_summary)
@@ -287,6 +341,8 @@ def main() -> int:
 
     if args.serve:
         return serving_bench(args)
+    if args.precision_study:
+        return precision_study(args)
 
     import numpy as np
     import torch
