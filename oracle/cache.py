@@ -21,6 +21,19 @@ def _key(tau: float, w_hi: int, cache_dir: str) -> str:
     return os.path.join(cache_dir, f"oracle_opset_{tau:.3e}_{w_hi}_{h}.npz")
 
 
+def cached_taus(w_hi: int, cache_dir: str = DEFAULT_DIR) -> list:
+    """The tau values whose (tau, w_hi) operator set is cached for the current oracle source."""
+    if not os.path.isdir(cache_dir):
+        return []
+    out = []
+    for t in sorted(os.listdir(cache_dir)):
+        parts = t[len("oracle_opset_"):-len(".npz")].split("_") if t.startswith("oracle_opset_") else []
+        if len(parts) == 3 and parts[1] == str(w_hi) and os.path.join(cache_dir, t) == _key(float(parts[0]), w_hi,
+                                                                                              cache_dir):
+            out.append(float(parts[0]))
+    return out
+
+
 def oracle_opset(tau: float, w_hi: int, cache_dir: str = DEFAULT_DIR) -> O.OpSet:
     """The oracle's skeletons for (tau, w_hi), built once and cached."""
     fn = _key(tau, w_hi, cache_dir)
