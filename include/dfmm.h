@@ -122,7 +122,7 @@ void dfmm_options_default(dfmm_options* opt);
  * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
  * every level (Section 2.2), the wedge labels, the needed directions and the
  * translation tables, all resident on the device.  Synchronous.
- * The skeletons use tau = 0.1 eps (eps >= 1e-5) or 0.05 eps.  Plans with
+ * The skeletons use tau = 0.1 eps (eps >= 1e-5) or 0.03 eps.  Plans with
  * eps < 1e-5 (or an operator set with tau < 3e-6) are "precise": the
  * near-field distances, 1/r and products are float64, the directional
  * operators are stored as float32 hi + lo parts, and every translation GEMM adds

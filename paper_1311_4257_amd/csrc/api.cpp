@@ -55,8 +55,9 @@ bool is_pow2(double K) {
 // K = 32 4:2:1 ellipsoid with 262,144 points, but 8.9 tau on the same
 // ellipsoid with 131,072 points, so tau = 0.1 eps.  Below 1e-5 the float32
 // translations (~4e-7 with split operators and float64 partial sums) also take
-// a share of the budget, so tau = 0.05 eps there.
-double tau_for_eps(double eps) { return eps >= 1e-5 ? 0.1 * eps : 0.05 * eps; }
+// a share of the budget: at tau = 5e-8 the K = 16 sphere gave 7.6e-7 and the
+// 131,072-point ellipsoid 1.07e-6, so tau = 0.03 eps there.
+double tau_for_eps(double eps) { return eps >= 1e-5 ? 0.1 * eps : 0.03 * eps; }
 
 int dir_count(double w, int* e) {
   if (w == 0.5) {

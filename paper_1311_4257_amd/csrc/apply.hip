@@ -843,7 +843,7 @@ constexpr int kNearMfmaMinRhs = 4;  // fast plans with at least this many rhs ta
 constexpr int NM_NW = 4;    // waves per workgroup
 constexpr int NM_MAXT = 4;  // row tiles per wave
 constexpr int NM_TB = 8 * NM_NW * NM_MAXT;  // targets per workgroup (128)
-template <int NCT>
+template <int NCT, int PREC>
 __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restrict__ phi, const float4* __restrict__ plo,
                                                           const int* __restrict__ lstart,
                                                           const int* __restrict__ nstart, const int* __restrict__ nsrc,
@@ -857,6 +857,7 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
   __shared__ float2 sg[NM_NW * 8 * GS];
   __shared__ int sj[NM_SC];
   __shared__ int nb_beg[64], nb_off[65];
+  __shared__ int fexp[NCOL];  // 16-bit plans: scale exponent of each staged density column
   const int b = blockIdx.x;
   const int c0 = int(blockIdx.y) * NCOL;
   const int s0 = lstart[b] + int(blockIdx.z) * NM_TB;
@@ -929,6 +930,33 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
       sf[e] = (j >= 0 && c0 + c < nrhs) ? fs[int64_t(j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
     }
     __syncthreads();
+    if constexpr (PREC != 0) {  // densities as (hi re | hi im, lo re | lo im) words, scaled per column
+      if (threadIdx.x < NCOL) {
+        int e = 0;
+        if constexpr (PREC == PREC_F16) {
+          float mx = 0.f;
+          for (int i = 0; i < NM_SC; ++i) {
+            const float2 v = sf[i * NCOL + threadIdx.x];
+            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+          }
+          if (mx > 0.f) {
+            int E;
+            (void)frexpf(mx, &E);
+            e = 14 - E;
+          }
+        }
+        fexp[threadIdx.x] = e;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
+        const int x = fexp[e % NCOL];
+        const float2 v = sf[e];
+        unsigned hi, lo;
+        split_pair<PREC>(ldexpf(v.x, x), ldexpf(v.y, x), hi, lo);
+        sf[e] = make_float2(__uint_as_float(hi), __uint_as_float(lo));
+      }
+      __syncthreads();
+    }
     const bool sval = lane < fill;
     const float4 h = sh[lane], l = sq[lane];
 #pragma unroll
@@ -936,16 +964,80 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
       const int rt = w + NM_NW * i;
       if (rt >= ntiles) break;
       // G for this tile's 8 targets and this lane's source
+      float2 gv[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const float4 a = th[rt * 8 + t], c = tq[rt * 8 + t];
-        float2 g = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
-        if (!sval || s0 + rt * 8 + t >= s1) g = make_float2(0.f, 0.f);
+        gv[t] = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
+        if (!sval || s0 + rt * 8 + t >= s1) gv[t] = make_float2(0.f, 0.f);
+      }
+      int eg = 0;  // 16-bit plans: the tile's scale exponent (largest |G| below 2^14)
+      if constexpr (PREC == PREC_F16) {
+        float mx = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) mx = fmaxf(mx, fmaxf(fabsf(gv[t].x), fabsf(gv[t].y)));
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+        if (mx > 0.f) {
+          int E;
+          (void)frexpf(mx, &E);
+          eg = 14 - E;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        float2 g = gv[t];
+        if constexpr (PREC != 0) {  // (hi re | hi im, lo re | lo im) words
+          unsigned hi, lo;
+          split_pair<PREC>(ldexpf(g.x, eg), ldexpf(g.y, eg), hi, lo);
+          g = make_float2(__uint_as_float(hi), __uint_as_float(lo));
+        }
         gw[t * GS + lane] = g;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if constexpr (PREC != 0) {
+        // products: one 16x16x32 MFMA per term covers 16 sources; lane k-group kk
+        // holds sources 4 kk .. 4 kk + 3 of the block, (Re, Im) each
+        float osc[NCT];
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) osc[c] = ldexpf(1.0f, -(eg + fexp[c * 16 + rr]));
+        constexpr unsigned SG = 0x80000000u;
+#pragma unroll 1
+        for (int q = 0; q < NM_SC / 16; ++q) {
+          const int sb = 16 * q + 4 * kk;
+          unsigned ah[4], al[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float2 g = gw[tr * GS + sb + e];
+            const unsigned h = __float_as_uint(g.x), o = __float_as_uint(g.y);
+            ah[e] = rodd ? rot16(h) : (h ^ SG);  // even row (Re G, -Im G), odd row (Im G, Re G)
+            al[e] = rodd ? rot16(o) : (o ^ SG);
+          }
+          const v4u av = {ah[0], ah[1], ah[2], ah[3]}, aw = {al[0], al[1], al[2], al[3]};
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            unsigned bh[4], bl[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const float2 f = sf[(sb + e) * NCOL + c * 16 + rr];
+              bh[e] = __float_as_uint(f.x);
+              bl[e] = __float_as_uint(f.y);
+            }
+            const v4u bv = {bh[0], bh[1], bh[2], bh[3]}, bw = {bl[0], bl[1], bl[2], bl[3]};
+            v4f a = mfma16<PREC>(av, bv, v4f{0.f, 0.f, 0.f, 0.f});
+            a = mfma16<PREC>(av, bw, a);
+            a = mfma16<PREC>(aw, bv, a);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a64[i][c][r] += double(a[r] * osc[c]);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        continue;
+      }
       // products: MFMA step q covers sources 2q, 2q + 1
 #pragma unroll 4
       for (int q = 0; q < NM_SC / 2; ++q) {
@@ -1468,15 +1560,19 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     if (nrhs == 1) DFMM_NEAR(true, 1); else DFMM_NEAR(true, 8);
   } else if (nrhs >= kNearMfmaMinRhs) {
     const dim3 grid(unsigned(nleaf), unsigned((nrhs + 31) / 32), unsigned((P.max_leaf_pts + NM_TB - 1) / NM_TB));
-    if (nrhs <= 16)
-      hipLaunchKernelGGL(k_near_mfma<1>, dim3(unsigned(nleaf), unsigned((nrhs + 15) / 16), grid.z), dim3(64 * NM_NW), 0,
-                         S.side, P.pthi.as<float4>(), P.ptlo.as<float4>(), P.leaf_start.as<int>(),
-                         P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(), nrhs, N,
-                         S.unear.as<double2>());
-    else
-      hipLaunchKernelGGL(k_near_mfma<2>, grid, dim3(64 * NM_NW), 0, S.side, P.pthi.as<float4>(), P.ptlo.as<float4>(),
-                         P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(), S.fs.as<float2>(),
-                         nrhs, N, S.unear.as<double2>());
+    const dim3 grid1(unsigned(nleaf), unsigned((nrhs + 15) / 16), grid.z);
+#define DFMM_NEARM(NCT, PR, G)                                                                                   \
+  hipLaunchKernelGGL((k_near_mfma<NCT, PR>), G, dim3(64 * NM_NW), 0, S.side, P.pthi.as<float4>(),               \
+                     P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),   \
+                     S.fs.as<float2>(), nrhs, N, S.unear.as<double2>())
+    if (P.prec == DFMM_PREC_FP16X3) {
+      if (nrhs <= 16) DFMM_NEARM(1, PREC_F16, grid1); else DFMM_NEARM(2, PREC_F16, grid);
+    } else if (P.prec == DFMM_PREC_BF16X3) {
+      if (nrhs <= 16) DFMM_NEARM(1, PREC_BF16, grid1); else DFMM_NEARM(2, PREC_BF16, grid);
+    } else {
+      if (nrhs <= 16) DFMM_NEARM(1, 0, grid1); else DFMM_NEARM(2, 0, grid);
+    }
+#undef DFMM_NEARM
   } else {
     if (nrhs == 1) DFMM_NEAR(false, 1); else DFMM_NEAR(false, 8);
   }

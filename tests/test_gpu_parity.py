@@ -58,16 +58,38 @@ def _compare_structure(plan, st):
         assert np.array_equal(plan.export(dfmm.EXPORT_IN_SLOTS, l), st.in_slots[l]), l
 
 
-@pytest.mark.parametrize("name,N", [("sphere4", 4096), ("sphere16", 16384)])
+def _structure_points(name, N):
+    if name == "ellipsoid32":  # the serving mix's 4:2:1 ellipsoid in a K = 32 box
+        return workloads.serving_points("ellipsoid", 32.0, N, 55), 32.0
+    pts, _, cfg = workloads.make_config(name, N=N)
+    return pts, cfg["K"]
+
+
+@pytest.mark.parametrize("name,N", [("sphere4", 4096), ("sphere16", 16384), ("ellipsoid32", 131072)])
 def test_structure_bit_exact(cuda, name, N):
     """Tree, lists, wedges and needed slots equal the oracle's bit for bit
     (the skeletons play no part here: the library builds its own)."""
-    pts, _, cfg = workloads.make_config(name, N=N)
-    st = build_structure(pts, cfg["K"])
-    plan = _dfmm().Plan(pts, cfg["K"], eps=cfg["eps"], cache_dir=CACHE, device=0)
+    pts, K = _structure_points(name, N)
+    st = build_structure(pts, K)
+    plan = _dfmm().Plan(pts, K, eps=1e-4, cache_dir=CACHE, device=0)
     _compare_structure(plan, st)
     info = plan.info()
     assert info.w_top == st.w_top
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_flat_ellipsoid_meets_eps(cuda, eps):
+    """The 4:2:1 ellipsoid of the serving mix (K = 32, N = 131,072, 129 points per
+    square wavelength): the plan with the largest far-field share of the
+    potential, closest to the eps bound."""
+    pts = workloads.serving_points("ellipsoid", 32.0, 131072, 55)
+    f = workloads.densities(len(pts), 2, 604)
+    plan = _dfmm().Plan(pts, 32.0, eps=eps, cache_dir=CACHE, device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    tg = workloads.sample_targets(len(pts), 512, 704)
+    err = rel_l2(u.astype(np.complex128)[:, tg], direct_sum(pts, f, tg))
+    print(f"ellipsoid K=32 N=131072 eps={eps:g}: rel L2 {err:.2e}")
+    assert err <= eps
 
 
 @pytest.mark.parametrize("tau", [1e-4, 1e-6])
@@ -262,3 +284,21 @@ def test_split_precision_plans(cuda, nrhs):
     assert all(e <= 1e-4 for e in errs.values())
     with pytest.raises(dfmm.DfmmError):
         dfmm.Plan(pts[:512] / 2, 4.0, eps=1e-6, cache_dir=CACHE, device=0, precision=dfmm.PREC_FP16X3)
+
+
+@pytest.mark.parametrize("prec,nrhs,bound", [(1, 8, 1e-6), (1, 40, 1e-6), (2, 8, 1e-4)])
+def test_near_field_split_precision(cuda, prec, nrhs, bound):
+    """The MFMA near field with split 16-bit products (tile-scaled G, column-scaled
+    densities) on the two-leaf geometry with pairs 1e-3 .. 1e-2 apart: FP16X3 to
+    float32 level, BF16X3 to its 16 bits, against the direct sum."""
+    rng = np.random.default_rng(11)
+    a = rng.uniform(0.02, 0.48, (120, 3))
+    b = rng.uniform(0.02, 0.48, (120, 3)) + np.array([0.5, 0.0, 0.0])
+    close = a[:40] + rng.normal(0, 1, (40, 3)) * 3e-3
+    pts = np.concatenate([a, b, np.clip(close, 0.001, 0.499)])
+    f = (rng.standard_normal((nrhs, len(pts))) + 1j * rng.standard_normal((nrhs, len(pts)))).astype(np.complex128)
+    plan = _dfmm().Plan(pts, 4.0, eps=1e-4, cache_dir=CACHE, device=0, precision=prec)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
+    err = rel_l2(u, direct_sum(pts, f, np.arange(len(pts))))
+    print(f"near field only, precision {prec}, nrhs={nrhs}: rel L2 {err:.2e}")
+    assert err < bound
