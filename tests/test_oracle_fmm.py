@@ -105,3 +105,18 @@ def test_planted_mistakes_break_the_pins(case4, monkeypatch):
     st2.lists[st2.tree.D].src = st2.lists[st2.tree.D].src[:0]
     st2.lists[st2.tree.D].offset = st2.lists[st2.tree.D].offset[:0]
     assert rel_l2(F.fmm_apply(st2, ops, f), ref) > 1e-2
+
+
+def test_cached_taus_lists_only_current_sets(tmp_path):
+    """The baseline's lookup of cached oracle skeleton sets: a set counts only for
+    its w_hi and the current oracle source hash."""
+    import os
+
+    from oracle.cache import _key, cached_taus
+
+    for tau, w in [(1e-5, 4), (1e-3, 1), (2e-4, 4)]:
+        open(_key(tau, w, str(tmp_path)), "wb").close()
+    open(os.path.join(str(tmp_path), "oracle_opset_1.000e-06_4_0000000000.npz"), "wb").close()  # stale source
+    assert sorted(cached_taus(4, str(tmp_path))) == [1e-5, 2e-4]
+    assert cached_taus(1, str(tmp_path)) == [1e-3]
+    assert cached_taus(2, str(tmp_path)) == []
