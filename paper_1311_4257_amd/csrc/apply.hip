@@ -1383,7 +1383,7 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
   if (nrhs <= S.cap) return;
   DFMM_HIP(hipDeviceSynchronize());  // earlier applies may still read the old buffers
   const WsSizes z = ws_sizes(P, nrhs);
-  S.cap = nrhs;
+  S.cap = 0;  // a failed allocation below leaves the workspace to be rebuilt by the next apply
   S.fs.alloc(z.fs);
   S.unear.alloc(z.unear);
   S.flf.alloc(z.flf);
@@ -1397,6 +1397,7 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
     S.U.back()->alloc(z.U[e]);
   }
   S.Y.alloc(z.Y);
+  S.cap = nrhs;
 }
 
 // ---- tuning record: the chosen (tile width, M-slices, LDS operator) per launch,
