@@ -178,7 +178,9 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
         for (int k = 0; k < RC; ++k)
           if (k < nk) cfma(acc[k], v, fs[int64_t(j) * nrhs + k0 + k]);
       }
-      for (int k = 0; k < nk; ++k) clf[(int64_t(b) * nrhs + k0 + k) * R + p] = acc[k];
+#pragma unroll
+      for (int k = 0; k < RC; ++k)
+        if (k < nk) clf[(int64_t(b) * nrhs + k0 + k) * R + p] = acc[k];
     }
   }
 }
@@ -1121,6 +1123,54 @@ __global__ void __launch_bounds__(L2T_BS) k_l2t(const float2* __restrict__ W, co
   }
 }
 
+// L2T for many right-hand sides: one block per leaf stages the leaf's incoming
+// potentials of kc right-hand sides in LDS once, instead of every target
+// re-reading them for every right-hand side; 16 lanes per target and the same
+// summation order as k_l2t.
+__global__ void __launch_bounds__(L2T_BS) k_l2t_leaf(const float2* __restrict__ W, const float2* __restrict__ ulf,
+                                                      const int* __restrict__ lstart,
+                                                      const double2* __restrict__ unear,
+                                                      const int* __restrict__ perm, int R, int nrhs, int kc,
+                                                      int64_t N, const ReqTable Q) {
+  extern __shared__ float2 us[];  // [kc][R]
+  const int b = blockIdx.x;
+  const int s0 = lstart[b], s1 = lstart[b + 1];
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int nq = (R - l + 15) / 16;
+  for (int k0 = 0; k0 < nrhs; k0 += kc) {
+    const int nk = min(kc, nrhs - k0);
+    __syncthreads();  // the previous rows are consumed
+    const float2* src = ulf + (int64_t(b) * nrhs + k0) * R;
+    for (int i = threadIdx.x; i < nk * R; i += L2T_BS) us[i] = src[i];
+    __syncthreads();
+    for (int t = s0 + g; t < s1; t += L2T_BS / 16) {
+      float2 w[L2T_QMAX];
+#pragma unroll
+      for (int i = 0; i < L2T_QMAX; ++i)
+        if (i < nq) w[i] = W[int64_t(t) * R + l + 16 * i];
+      const int64_t o = perm[t];
+      for (int k = 0; k < nk; ++k) {
+        const float2* ur = us + k * R;
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < L2T_QMAX; ++i)
+          if (i < nq) cfma(acc, w[i], ur[l + 16 * i]);
+#pragma unroll
+        for (int m = 8; m > 0; m >>= 1) {
+          acc.x += __shfl_xor(acc.x, m, 16);
+          acc.y += __shfl_xor(acc.y, m, 16);
+        }
+        if (l == 0) {
+          const int kk = k0 + k;
+          const double2 nf = unear[int64_t(kk) * N + t];
+          const int r = req_of(Q, kk);
+          Q.u[r][int64_t(kk - Q.k0[r]) * N + o] = make_float2(float(double(acc.x) + nf.x), float(double(acc.y) + nf.y));
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_zero(float2* __restrict__ p, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = make_float2(0.f, 0.f);
@@ -1583,8 +1633,11 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   if (nrhs == 1)
     hipLaunchKernelGGL(k_s2m<1>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
-  else
+  else if (nrhs < 24)
     hipLaunchKernelGGL(k_s2m<8>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+  else  // one pass over the weights for up to 32 right-hand sides
+    hipLaunchKernelGGL(k_s2m<32>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
   mark(ST_S2M);
   // HF-M2M, fine to coarse
@@ -1639,9 +1692,16 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   }
   DFMM_HIP(hipStreamWaitEvent(st, S.join, 0));
   if (Rl > 16 * L2T_QMAX) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank too large for L2T"};
-  hipLaunchKernelGGL(k_l2t, dim3(nblocks(N * 16, L2T_BS)), dim3(L2T_BS), 0, st, P.lf.W.as<float2>(),
-                     S.ulf.as<float2>(), P.leaf_of.as<int>(), S.unear.as<double2>(), P.perm_d.as<int>(), Rl, nrhs, N,
-                     R);
+  if (nrhs >= 4) {
+    const int kc = std::min(nrhs, std::max(1, int((48 << 10) / (sizeof(float2) * Rl))));
+    hipLaunchKernelGGL(k_l2t_leaf, dim3(unsigned(nleaf)), dim3(L2T_BS), sizeof(float2) * size_t(kc) * Rl, st,
+                       P.lf.W.as<float2>(), S.ulf.as<float2>(), P.leaf_start.as<int>(), S.unear.as<double2>(),
+                       P.perm_d.as<int>(), Rl, nrhs, kc, N, R);
+  } else {
+    hipLaunchKernelGGL(k_l2t, dim3(nblocks(N * 16, L2T_BS)), dim3(L2T_BS), 0, st, P.lf.W.as<float2>(),
+                       S.ulf.as<float2>(), P.leaf_of.as<int>(), S.unear.as<double2>(), P.perm_d.as<int>(), Rl, nrhs,
+                       N, R);
+  }
   mark(ST_LEAF);
   DFMM_HIP(hipGetLastError());
 }
