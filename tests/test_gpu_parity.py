@@ -303,3 +303,40 @@ def test_near_field_split_precision(cuda, prec, nrhs, bound):
     err = rel_l2(u, direct_sum(pts, f, np.arange(len(pts))))
     print(f"near field only, precision {prec}, nrhs={nrhs}: rel L2 {err:.2e}")
     assert err < bound
+
+
+def test_degenerate_inputs(cuda):
+    """Edge cases of the boundary: one point (u = 0 exactly), coincident points
+    (G := 0 at r = 0), points exactly on |p| = K/2 including the positive axis
+    tips (clamped into the last box), and domains too small for any HF level
+    (K = 1 and 2: only the LF level, or only the near field), against the
+    direct sum."""
+    dfmm = _dfmm()
+    rng = np.random.default_rng(21)
+
+    def run(pts, K, nrhs=2):
+        f = (rng.standard_normal((nrhs, len(pts))) + 1j * rng.standard_normal((nrhs, len(pts))))
+        plan = dfmm.Plan(pts, K, eps=1e-4, cache_dir=CACHE, device=0)
+        u = plan.apply(_to_dev(f, cuda)).cpu().numpy().astype(np.complex128)
+        return u, direct_sum(pts, f.astype(np.complex64).astype(np.complex128), np.arange(len(pts))), plan
+
+    u, ref, _ = run(np.array([[0.3, -0.2, 0.1]]), 2.0)
+    assert np.all(u == 0)
+    u, ref, _ = run(np.array([[0.25, 0.25, 0.25]] * 3), 2.0)  # three coincident points
+    assert np.all(u == 0)
+    pts = np.concatenate([np.array([[0.1, 0.1, 0.1]] * 2), rng.uniform(-0.5, 0.5, (30, 3))])
+    u, ref, _ = run(pts, 2.0)
+    assert rel_l2(u, ref) < 1e-6
+    K = 8.0
+    axis = np.array([[K / 2, 0, 0], [-K / 2, 0, 0], [0, K / 2, 0], [0, -K / 2, 0], [0, 0, K / 2], [0, 0, -K / 2]])
+    pts = np.concatenate([axis, workloads.sphere_points(3000, K, 22)])
+    u, ref, plan = run(pts, K)
+    err = rel_l2(u, ref)
+    print(f"boundary points K=8: rel L2 {err:.2e}, w_top {plan.info().w_top}")
+    assert err <= 1e-4
+    for K, n in ((1.0, 40), (2.0, 600)):
+        pts = workloads.sphere_points(n, K, 23)
+        u, ref, plan = run(pts, K, nrhs=5)
+        err = rel_l2(u, ref)
+        print(f"K={K:g} N={n}: rel L2 {err:.2e}, w_top {plan.info().w_top}, depth {plan.info().depth}")
+        assert err <= 1e-4
