@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <string>
@@ -272,7 +273,8 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
                                            const int* __restrict__ gops, const int* __restrict__ gv0,
                                            const int* __restrict__ vsrc, const int* __restrict__ vdst,
                                            const int* __restrict__ chunk_grp, const int* __restrict__ chunk_c0,
-                                           int nrhs, const float2* __restrict__ X, float2* __restrict__ Y) {
+                                           int nrhs, const float2* __restrict__ X, float2* __restrict__ Y,
+                                           int chunk, int slice, int nslices) {
   static_assert(!(ACC64 && PREC), "split 16-bit products are for fast plans");
   extern __shared__ float4 xs[];
   constexpr int NC = NT * 16;
@@ -285,14 +287,14 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j = lane & 15, kr = lane >> 4;
   const bool odd = (j & 1) != 0;
-  const int g = chunk_grp[blockIdx.x];
+  const int g = chunk_grp[chunk];
   const int Mg = gmk[2 * g], Kr = gmk[2 * g + 1];  // this group's operator size
   const int Kg = kp(Kr);                 // packed K (Kr + zero columns in 16-bit plans)
   const int Q4 = Kg / 8;                 // k-steps per tile (K_g / 2 real k per quarter, 4 per step)
   const int nM = Mg / 8, nMall = M / 8;  // 16-row real M-tiles with data / in the vector stride
-  const int m0 = wave + NW * int(blockIdx.y), mstep = NW * int(gridDim.y);
+  const int m0 = wave + NW * slice, mstep = NW * nslices;
   const int mcnt = m0 < nM ? (nM - m0 + mstep - 1) / mstep : 0;
-  const int64_t c0 = chunk_c0[blockIdx.x];
+  const int64_t c0 = chunk_c0[chunk];
   const int vbeg = gv0[g];
   const int64_t ncol = int64_t(gv0[g + 1] - vbeg) * nrhs;
   const int nc = int(min<int64_t>(NC, ncol - c0));
@@ -421,12 +423,12 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
     }
   }
   if (ALDS) {
-    const int tmax = nM > NW * int(blockIdx.y) ? (nM - NW * int(blockIdx.y) + mstep - 1) / mstep : 0;
+    const int tmax = nM > NW * slice ? (nM - NW * slice + mstep - 1) / mstep : 0;
     const int nel = 4 * tmax * tile4;
     const int dblk = BS / tile4, doff = BS % tile4;
     int blk = int(threadIdx.x) / tile4, off = int(threadIdx.x) % tile4;
     for (int idx = int(threadIdx.x); idx < nel; idx += BS) {
-      const int m = (blk % NW) + NW * int(blockIdx.y) + mstep * (blk / NW);
+      const int m = (blk % NW) + NW * slice + mstep * (blk / NW);
       as[idx] = m < nM ? Aop[int64_t(m) * tile4 + off] : make_float4(0.f, 0.f, 0.f, 0.f);
       blk += dblk;
       off += doff;
@@ -647,11 +649,44 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
 // translations (M2L of Algorithm 1) from the pair-form tree transfers (M2M and L2L).
 template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 __global__ void __launch_bounds__(64 * NW) k_m2l(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS, int(blockIdx.x), int(blockIdx.y), int(gridDim.y));
 }
 template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 __global__ void __launch_bounds__(64 * NW) k_transfer(DFMM_GG_PARAMS) {
-  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS);
+  ggemm_tile<NT, ALDS, ACC64, NW, PREC>(DFMM_GG_ARGS, int(blockIdx.x), int(blockIdx.y), int(gridDim.y));
+}
+
+// All M2L launches of an apply (every HF level and the leaf level) in one
+// launch: they read only the upward pass's outputs, so their chunks can share
+// the GPU (the HBM-bound HF chunks beside the compute-bound leaf-level ones).
+// A chunk names its problem and M-slice; each problem writes its own pair
+// scratch, reduced afterwards in the order of the separate launches.
+constexpr int kMaxProbs = 8;
+struct GgProb {
+  const float4* A;
+  const int64_t* aoff;
+  const int* aexp;
+  const int* gmk;
+  const int* gops;
+  const int* gv0;
+  const int* vsrc;
+  const int* vdst;
+  const float2* X;
+  float2* Y;
+  int M, K, split, slices;
+};
+struct GgProbs {
+  GgProb p[kMaxProbs];
+};
+template <int NT, int NW, int PREC>
+__global__ void __launch_bounds__(64 * NW) k_m2l_fused(const GgProbs P, const int* __restrict__ chunk_ps,
+                                                        const int* __restrict__ chunk_grp,
+                                                        const int* __restrict__ chunk_c0, int nrhs) {
+  const int c = int(blockIdx.x);
+  const int ps = chunk_ps[c];  // problem | slice << 4
+  const GgProb& q = P.p[ps & 15];
+  ggemm_tile<NT, false, false, NW, PREC>(q.A, q.aoff, q.aexp, q.gmk, q.M, q.K, q.split, q.gops, q.gv0, q.vsrc,
+                                         q.vdst, chunk_grp, chunk_c0, nrhs, q.X, q.Y, c, ps >> 4, q.slices);
 }
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
@@ -1203,18 +1238,44 @@ struct Launch {        // one grouped-GEMM launch prepared for the current nrhs
   DevBuf grp, col0;
 };
 
+// All M2L launches of an apply fused into one k_m2l_fused launch, when the
+// tuner finds that faster than the separate launches.
+struct Fused {
+  int nt = 0;                 // 16-column tiles per workgroup; 0: separate launches
+  int64_t nchunks = 0;
+  DevBuf ps, grp, col0;       // per chunk: problem | slice << 4, group, first column
+  std::vector<int64_t> yoff;  // per problem: offset (float2) of its pair outputs in the fused scratch
+};
+
 // The GEMM launches of one nrhs (chunk tables and tuned shapes).
 struct LaunchSet {
   std::vector<Launch> m2m, l2l, m2l;  // per HF level
   Launch lf_m2l;
+  Fused fused;
 };
+
+// The M2L problems of a plan in apply order: HF levels from the top down, then
+// the leaf level (level -1).
+static std::vector<const GGemm*> m2l_problems(const dfmm_plan_s& P, std::vector<int>* level = nullptr) {
+  std::vector<const GGemm*> v;
+  for (int e = int(P.hf.size()) - 1; e >= 0; --e)
+    if (P.hf[size_t(e)].m2l.ngroups > 0) {
+      v.push_back(&P.hf[size_t(e)].m2l);
+      if (level) level->push_back(e);
+    }
+  if (P.lf.m2l.ngroups > 0) {
+    v.push_back(&P.lf.m2l);
+    if (level) level->push_back(-1);
+  }
+  return v;
+}
 
 // Workspace of a plan: buffers sized for the largest nrhs applied so far
 // (grow-only), launch sets per nrhs.
 struct ApplyState {
   int cap = 0;
   std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
-  DevBuf fs, flf, ulf, Y, unear;
+  DevBuf fs, flf, ulf, Y, Yf, unear;  // Y: pair scratch; Yf: the fused M2L's, one region per level
   std::map<int, std::unique_ptr<LaunchSet>> sets;
   // second stream for the near field (default priority) and its fork/join events
   hipStream_t side = nullptr;
@@ -1239,20 +1300,17 @@ void destroy_apply_state(ApplyState* s) { delete s; }
 // so the chunk table is laid out such that the workgroups that land on one XCD
 // take a contiguous range of chunks (a group's chunks share that XCD's L2).
 constexpr int kXcds = 8;
-static void xcd_order(std::vector<int32_t>& grp, std::vector<int32_t>& col0) {
-  const int64_t n = int64_t(grp.size());
+static void xcd_order(std::initializer_list<std::vector<int32_t>*> cols) {
+  const int64_t n = int64_t((*cols.begin())->size());
   if (n <= kXcds) return;
   int64_t start[kXcds + 1];
   start[0] = 0;
   for (int x = 0; x < kXcds; ++x) start[x + 1] = start[x] + (n - x + kXcds - 1) / kXcds;  // ids b = x mod 8
-  std::vector<int32_t> g2(n), c2(n);
-  for (int64_t b = 0; b < n; ++b) {
-    const int64_t l = start[b % kXcds] + b / kXcds;
-    g2[b] = grp[l];
-    c2[b] = col0[l];
+  for (std::vector<int32_t>* v : cols) {
+    std::vector<int32_t> w(static_cast<size_t>(n));
+    for (int64_t b = 0; b < n; ++b) w[size_t(b)] = (*v)[size_t(start[b % kXcds] + b / kXcds)];
+    v->swap(w);
   }
-  grp.swap(g2);
-  col0.swap(c2);
 }
 
 // Chunks and grid for one (tile width, M-slices, waves, operator-in-LDS) choice.
@@ -1263,7 +1321,7 @@ static void prepare_cfg(Launch& L, const GGemm& G, int nrhs, int nt, int slices,
   L.alds = alds;
   std::vector<int32_t> grp, col0;
   make_chunks(G, nrhs, L.nt * 16, grp, col0);
-  xcd_order(grp, col0);
+  xcd_order({&grp, &col0});
   L.nchunks = int64_t(grp.size());
   L.slices = slices;
   L.grp.upload(grp);
@@ -1353,6 +1411,78 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
   else launch_nt<1>(L, nrhs, X, Y, st);
 }
 
+// ---- fused M2L launch ----------------------------------------------------------------
+static bool fused_fits(const dfmm_plan_s& P, int nt) {
+  const auto probs = m2l_problems(P);
+  if (P.precise || probs.size() < 2 || probs.size() > size_t(kMaxProbs)) return false;
+  for (const GGemm* G : probs)
+    if (G->T != 1 || !gg_fits(*G, nt, 1, false, 4)) return false;
+  return true;
+}
+
+static void prepare_fused(const dfmm_plan_s& P, int nrhs, int nt, Fused& F) {
+  const auto probs = m2l_problems(P);
+  std::vector<int32_t> ps, grp, col0;
+  F.yoff.clear();
+  int64_t off = 0;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    std::vector<int32_t> g1, c1;
+    make_chunks(*probs[i], nrhs, nt * 16, g1, c1);
+    for (size_t k = 0; k < g1.size(); ++k) {
+      ps.push_back(int32_t(i));
+      grp.push_back(g1[k]);
+      col0.push_back(c1[k]);
+    }
+    F.yoff.push_back(off);
+    off += probs[i]->nvec * probs[i]->M * nrhs;
+  }
+  xcd_order({&ps, &grp, &col0});
+  F.nt = nt;
+  F.nchunks = int64_t(ps.size());
+  F.ps.upload(ps);
+  F.grp.upload(grp);
+  F.col0.upload(col0);
+}
+
+template <int NT, int PREC>
+static void launch_fused_t(const GgProbs& pr, size_t lds, const Fused& F, int nrhs, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_fused<NT, 4, PREC>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kGgDynLds));
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_m2l_fused<NT, 4, PREC>), dim3(unsigned(F.nchunks)), dim3(256), lds, st, pr, F.ps.as<int>(),
+                     F.grp.as<int>(), F.col0.as<int>(), nrhs);
+}
+
+template <int PREC>
+static void launch_fused_p(const GgProbs& pr, size_t lds, const Fused& F, int nrhs, hipStream_t st) {
+  if (F.nt == 4) launch_fused_t<4, PREC>(pr, lds, F, nrhs, st);
+  else if (F.nt == 2) launch_fused_t<2, PREC>(pr, lds, F, nrhs, st);
+  else launch_fused_t<1, PREC>(pr, lds, F, nrhs, st);
+}
+
+// X of problem i: the level's outgoing potentials (the leaves' for the leaf level)
+static void launch_fused(const dfmm_plan_s& P, const ApplyState& S, const Fused& F, int nrhs, hipStream_t st) {
+  if (F.nchunks == 0) return;
+  std::vector<int> level;
+  const auto probs = m2l_problems(P, &level);
+  GgProbs pr{};
+  size_t lds = 0;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    const GGemm& G = *probs[i];
+    const float2* X = level[i] >= 0 ? S.F[size_t(level[i])]->as<float2>() : S.flf.as<float2>();
+    pr.p[i] = GgProb{G.A.as<float4>(), G.aoff.as<int64_t>(), G.aexp.as<int>(), G.gmk.as<int>(), G.ops.as<int>(),
+                     G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), X, S.Yf.as<float2>() + F.yoff[i], G.M,
+                     G.K, G.split, 1};
+    lds = std::max(lds, gg_lds_total(kpad(G.K, G.prec) * G.split, F.nt, gg_mt(G, 1), false));
+  }
+  if (P.prec == DFMM_PREC_FP16X3) launch_fused_p<PREC_F16>(pr, lds, F, nrhs, st);
+  else if (P.prec == DFMM_PREC_BF16X3) launch_fused_p<PREC_BF16>(pr, lds, F, nrhs, st);
+  else launch_fused_p<0>(pr, lds, F, nrhs, st);
+}
+
 // Tile autotuner: time every (tile width, M-slices, waves per workgroup,
 // operator-in-LDS) candidate of one launch on the apply stream (its output goes
 // to the pair scratch Y only) and keep the fastest.  Runs once per plan and nrhs.
@@ -1396,10 +1526,10 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
 
 // Device bytes of each workspace buffer for nrhs right-hand sides.
 struct WsSizes {
-  size_t fs, unear, flf, ulf, Y;
+  size_t fs, unear, flf, ulf, Y, Yf;
   std::vector<size_t> F, U;
   size_t total() const {
-    size_t t = fs + unear + flf + ulf + Y;
+    size_t t = fs + unear + flf + ulf + Y + Yf;
     for (size_t b : F) t += b;
     for (size_t b : U) t += b;
     return t;
@@ -1422,6 +1552,10 @@ static WsSizes ws_sizes(const dfmm_plan_s& P, int nrhs) {
     ymax = std::max<int64_t>(ymax, H.l2l_npairs * H.Rc);
   }
   z.Y = sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs;
+  int64_t yf = 0;  // fast plans: every M2L level's pair outputs side by side (fused launch)
+  if (!P.precise)
+    for (const GGemm* G : m2l_problems(P)) yf += G->nvec * G->M;
+  z.Yf = sizeof(float2) * std::max<int64_t>(1, yf) * nrhs;
   return z;
 }
 
@@ -1447,6 +1581,7 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
     S.U.back()->alloc(z.U[e]);
   }
   S.Y.alloc(z.Y);
+  S.Yf.alloc(z.Yf);
   S.cap = nrhs;
 }
 
@@ -1480,18 +1615,20 @@ static std::string tune_path(const dfmm_plan_s& P, const std::vector<const GGemm
 }
 
 static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const std::vector<const GGemm*>& gs,
-                        int nrhs) {
+                        int nrhs, int* fused_nt) {
   if (path.empty()) return false;
   FILE* fp = std::fopen(path.c_str(), "r");
   if (!fp) return false;
   int n = 0;
-  bool ok = std::fscanf(fp, "dfmm-tune 2 %d", &n) == 1 && n == int(ls.size());
+  bool ok = std::fscanf(fp, "dfmm-tune 3 %d", &n) == 1 && n == int(ls.size());
   std::vector<int> v(4 * size_t(std::max(n, 0)));
   for (int i = 0; ok && i < n; ++i) {
     int* c = &v[4 * size_t(i)];  // tile width, M-slices, operator in LDS, waves
     ok = std::fscanf(fp, "%d %d %d %d", &c[0], &c[1], &c[2], &c[3]) == 4;
     ok = ok && (c[0] == 1 || c[0] == 2 || c[0] == 4) && c[1] >= 1 && c[1] <= 64 && (c[3] == 2 || c[3] == 4);
   }
+  ok = ok && std::fscanf(fp, " fused %d", fused_nt) == 1 &&
+       (*fused_nt == 0 || *fused_nt == 1 || *fused_nt == 2 || *fused_nt == 4);
   std::fclose(fp);
   if (!ok) return false;
   for (int i = 0; i < n; ++i) {
@@ -1502,15 +1639,83 @@ static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const
   return true;
 }
 
-static void save_tuning(const std::string& path, const std::vector<Launch*>& ls) {
+static void save_tuning(const std::string& path, const std::vector<Launch*>& ls, int fused_nt) {
   if (path.empty()) return;
   const std::string tmp = path + ".tmp";
   FILE* fp = std::fopen(tmp.c_str(), "w");
   if (!fp) return;  // the record is an optimisation only
-  std::fprintf(fp, "dfmm-tune 2 %d\n", int(ls.size()));
+  std::fprintf(fp, "dfmm-tune 3 %d\n", int(ls.size()));
   for (const Launch* L : ls) std::fprintf(fp, "%d %d %d %d\n", L->nt, L->slices, L->alds ? 1 : 0, L->nw);
+  std::fprintf(fp, "fused %d\n", fused_nt);
   const bool ok = std::fclose(fp) == 0;
   if (ok) std::rename(tmp.c_str(), path.c_str());
+}
+
+// Fused M2L or separate launches: time the tuned separate M2L launches and the
+// fused launch at each tile width, each with the reductions of the pair outputs
+// (the fused form reduces them after all levels, when they are no longer in
+// cache), 3 runs each on the apply stream, and keep the faster form.  The timed
+// reductions add into the incoming potentials, which every apply overwrites
+// or clears before it adds to them.
+static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS, hipStream_t st) {
+  LS.fused.nt = 0;
+  bool any = false;
+  for (int nt : {1, 2, 4}) any = any || fused_fits(P, nt);
+  if (!any) return;
+  std::vector<int> level;
+  const auto probs = m2l_problems(P, &level);
+  hipEvent_t e0, e1;
+  DFMM_HIP(hipEventCreate(&e0));
+  DFMM_HIP(hipEventCreate(&e1));
+  auto timed = [&](const std::function<void()>& run) {
+    run();  // warm-up
+    DFMM_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) run();
+    DFMM_HIP(hipEventRecord(e1, st));
+    DFMM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DFMM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  auto reduce = [&](size_t i, const float2* Yp) {
+    if (level[i] >= 0) {
+      const HFLevel& H = P.hf[size_t(level[i])];
+      const int RN = H.R * nrhs;
+      hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
+                         H.red_idx.as<int>(), Yp, H.nin, RN, 1, S.U[size_t(level[i])]->as<float2>());
+    } else {
+      const int RN = P.lf.R * nrhs;
+      hipLaunchKernelGGL(k_reduce, dim3(nblocks(P.lf.nleaf * RN, 256)), dim3(256), 0, st,
+                         P.lf.red_start.as<int>(), P.lf.red_idx.as<int>(), Yp, P.lf.nleaf, RN, 1,
+                         S.ulf.as<float2>());
+    }
+  };
+  const float t_sep = timed([&]() {
+    for (size_t i = 0; i < probs.size(); ++i) {
+      const Launch& L = level[i] >= 0 ? LS.m2l[size_t(level[i])] : LS.lf_m2l;
+      const float2* X = level[i] >= 0 ? S.F[size_t(level[i])]->as<float2>() : S.flf.as<float2>();
+      launch_gemm(L, nrhs, X, S.Y.as<float2>(), st);
+      reduce(i, S.Y.as<float2>());
+    }
+  });
+  float best = t_sep;
+  int best_nt = 0;
+  for (int nt : {1, 2, 4}) {
+    if (!fused_fits(P, nt)) continue;
+    prepare_fused(P, nrhs, nt, LS.fused);
+    const float t = timed([&]() {
+      launch_fused(P, S, LS.fused, nrhs, st);
+      for (size_t i = 0; i < probs.size(); ++i) reduce(i, S.Yf.as<float2>() + LS.fused.yoff[i]);
+    });
+    if (t < best) {
+      best = t;
+      best_nt = nt;
+    }
+  }
+  DFMM_HIP(hipEventDestroy(e0));
+  DFMM_HIP(hipEventDestroy(e1));
+  if (best_nt > 0) prepare_fused(P, nrhs, best_nt, LS.fused);
+  else LS.fused = Fused();
 }
 
 // Tune the GEMM launches of nrhs right-hand sides on the apply stream.
@@ -1534,10 +1739,21 @@ static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS
   xs.push_back(S.flf.as<float2>());
   LS.lf_m2l.m2l = true;
   const std::string path = tune_path(P, gs, nrhs);
-  if (load_tuning(path, ls, gs, nrhs)) return;
-  for (size_t i = 0; i < ls.size(); ++i) autotune(*ls[i], *gs[i], nrhs, xs[i], Y, st);
-  const char* env = std::getenv("DFMM_AUTOTUNE");
-  if (!(env && env[0] == '0')) save_tuning(path, ls);
+  int fused_nt = 0;
+  if (load_tuning(path, ls, gs, nrhs, &fused_nt)) {
+    if (fused_nt > 0 && fused_fits(P, fused_nt)) prepare_fused(P, nrhs, fused_nt, LS.fused);
+  } else {
+    for (size_t i = 0; i < ls.size(); ++i) autotune(*ls[i], *gs[i], nrhs, xs[i], Y, st);
+    const char* env = std::getenv("DFMM_AUTOTUNE");
+    const bool tune = !(env && env[0] == '0');
+    if (tune) tune_fused(P, nrhs, S, LS, st);
+    if (tune) save_tuning(path, ls, LS.fused.nt);
+  }
+  // DFMM_FUSED=0 / 1 forces the separate / fused M2L form (tests of both)
+  if (const char* f = std::getenv("DFMM_FUSED")) {
+    if (f[0] == '0') LS.fused = Fused();
+    else if (f[0] == '1' && LS.fused.nt == 0 && fused_fits(P, 2)) prepare_fused(P, nrhs, 2, LS.fused);
+  }
 }
 
 // A launch set for nrhs that is not a power of two takes the tuned shapes of
@@ -1557,6 +1773,7 @@ static void inherit_launches(dfmm_plan_s& P, int nrhs, const LaunchSet& from, La
     take(LS.m2l[e], from.m2l[e], P.hf[e].m2l);
   }
   take(LS.lf_m2l, from.lf_m2l, P.lf.m2l);
+  if (from.fused.nt > 0) prepare_fused(P, nrhs, from.fused.nt, LS.fused);
 }
 
 static LaunchSet& launch_set(dfmm_plan_s& P, ApplyState& S, int nrhs, hipStream_t st) {
@@ -1658,14 +1875,27 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.U[e_top]->as<float2>(), n);
     mark(ST_ZERO);
   }
+  // fused form: every level's M2L in one launch, each into its own pair scratch
+  const bool fused = LS.fused.nt > 0;
+  std::vector<const float2*> ym2l(P.hf.size() + 1, S.Y.as<float2>());  // pair outputs per level (last: LF)
+  if (fused) {
+    std::vector<int> level;
+    const auto probs = m2l_problems(P, &level);
+    for (size_t i = 0; i < probs.size(); ++i)
+      ym2l[level[i] >= 0 ? size_t(level[i]) : P.hf.size()] = S.Yf.as<float2>() + LS.fused.yoff[i];
+    launch_fused(P, S, LS.fused, nrhs, st);
+    mark(ST_M2L);
+  }
   for (int e = e_top; e >= 0; --e) {
     HFLevel& H = P.hf[e];
     if (LS.m2l[e].nchunks > 0) {
-      launch_gemm(LS.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
-      mark(ST_M2L);
+      if (!fused) {
+        launch_gemm(LS.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
+        mark(ST_M2L);
+      }
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
-                         H.red_idx.as<int>(), S.Y.as<float2>(), H.nin, RN, 1, S.U[e]->as<float2>());
+                         H.red_idx.as<int>(), ym2l[size_t(e)], H.nin, RN, 1, S.U[e]->as<float2>());
       mark(ST_REDUCE);
     }
     float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
@@ -1683,11 +1913,13 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   }
   // LF-M2L
   if (LS.lf_m2l.nchunks > 0) {
-    launch_gemm(LS.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
-    mark(ST_LF_M2L);
+    if (!fused) {
+      launch_gemm(LS.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
+      mark(ST_LF_M2L);
+    }
     int RN = Rl * nrhs;
     hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
-                       P.lf.red_idx.as<int>(), S.Y.as<float2>(), nleaf, RN, 1, S.ulf.as<float2>());
+                       P.lf.red_idx.as<int>(), ym2l[P.hf.size()], nleaf, RN, 1, S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
   DFMM_HIP(hipStreamWaitEvent(st, S.join, 0));

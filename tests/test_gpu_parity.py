@@ -340,3 +340,22 @@ def test_degenerate_inputs(cuda):
         err = rel_l2(u, ref)
         print(f"K={K:g} N={n}: rel L2 {err:.2e}, w_top {plan.info().w_top}, depth {plan.info().depth}")
         assert err <= 1e-4
+
+
+@pytest.mark.parametrize("prec,nrhs", [(0, 1), (0, 5), (1, 3)])
+def test_fused_m2l_equals_separate_launches(cuda, prec, nrhs, monkeypatch):
+    """Every level's M2L in one launch (own pair scratch per level, reductions in
+    the same order) gives bitwise the result of the separate launches."""
+    dfmm = _dfmm()
+    pts = workloads.sphere_points(16384, 8.0, 41)
+    f = workloads.densities(len(pts), nrhs, 42)
+    fd = _to_dev(f, cuda)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("DFMM_FUSED", mode)
+        plan = dfmm.Plan(pts, 8.0, eps=1e-4, cache_dir=CACHE, device=0, precision=prec)
+        out[mode] = plan.apply(fd).cpu().numpy()
+        plan.close()
+    assert np.array_equal(out["0"], out["1"])
+    tg = workloads.sample_targets(len(pts), 256, 43)
+    assert rel_l2(out["1"].astype(np.complex128)[:, tg], direct_sum(pts, f, tg)) <= 1e-4
