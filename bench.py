@@ -471,7 +471,8 @@ def main() -> int:
         "ms_per_step_graph_replay": ms_graph,
         "roofline": {
             "bound": "mfma" if mfma_bound else "hbm",
-            "kernel": "k_m2l (grouped M2L GEMM, HF + LF launches)",
+            "kernel": ("k_m2l_fused (every M2L level in one launch)" if stages["lf_m2l"][1] == 0 and per_apply == 1
+                       else "k_m2l (grouped M2L GEMM, one launch per level)"),
             "achieved": achieved,
             "peak": peak,
             "unit": unit,

@@ -139,7 +139,9 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * if nrhs is the largest so far (synchronous allocation) and fixes the GEMM
  * launch shapes for it: for a power of two from the tuning record in the cache
  * directory if one matches, else by timing the candidate shapes on `stream`
- * (waits for them; DFMM_AUTOTUNE=0 takes the default shapes instead); for
+ * (waits for them; DFMM_AUTOTUNE=0 takes the default shapes instead), including
+ * whether the M2L launches of all levels run fused into one (DFMM_FUSED=0 or 1
+ * forces the separate or the fused form); for
  * other nrhs from the power of two below (see dfmm_apply_batch).  Later
  * applies with the same nrhs allocate nothing and do not wait.  The near-field sum runs on a second stream owned by the
  * plan (default priority), forked from and joined back into `stream` with
