@@ -434,7 +434,9 @@ def main() -> int:
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        if rec.get("source_sha1") == gemm_source_hash() and nrhs == 1:
+        # the record holds for the same GEMM sources, workload and launch form
+        if rec.get("source_sha1") == gemm_source_hash() and nrhs == 1 and args.workload == "sphere16" \
+                and eps == 1e-4 and prec == 0 and rec.get("launches") == round(per_apply):
             traffic = rec["bytes_per_launch"]
     per_stage = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]}
     # near-field sum: point pairs (self pairs included, they contribute 0), flops
