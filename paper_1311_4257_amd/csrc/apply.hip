@@ -1244,7 +1244,7 @@ struct Fused {
   int nt = 0;                 // 16-column tiles per workgroup; 0: separate launches
   int64_t nchunks = 0;
   DevBuf ps, grp, col0;       // per chunk: problem | slice << 4, group, first column
-  std::vector<int64_t> yoff;  // per problem: offset (float2) of its pair outputs in the fused scratch
+  std::vector<int64_t> yoff;  // per problem: offset (float2) of its pair outputs in the pair scratch
 };
 
 // The GEMM launches of one nrhs (chunk tables and tuned shapes).
@@ -1270,12 +1270,33 @@ static std::vector<const GGemm*> m2l_problems(const dfmm_plan_s& P, std::vector<
   return v;
 }
 
+// Pair-scratch rows (complex entries per right-hand side): the largest M2M /
+// L2L launch, the largest of every launch, and the transfers' plus every M2L
+// level's (fast plans: the fused M2L form).
+static int64_t pair_rows_transfer(const dfmm_plan_s& P) {
+  int64_t y = 0;
+  for (const auto& H : P.hf) y = std::max({y, H.m2m_npairs * H.R, H.l2l_npairs * H.Rc});
+  return y;
+}
+static int64_t pair_rows_separate(const dfmm_plan_s& P) {
+  int64_t y = std::max(pair_rows_transfer(P), P.lf.npairs * P.lf.R);
+  for (const auto& H : P.hf) y = std::max(y, H.npairs * H.R);
+  return y;
+}
+static int64_t pair_rows_fused(const dfmm_plan_s& P) {
+  if (P.precise) return 0;
+  int64_t y = pair_rows_transfer(P);
+  for (const GGemm* G : m2l_problems(P)) y += G->nvec * G->M;
+  return y;
+}
+
+
 // Workspace of a plan: buffers sized for the largest nrhs applied so far
 // (grow-only), launch sets per nrhs.
 struct ApplyState {
   int cap = 0;
   std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
-  DevBuf fs, flf, ulf, Y, Yf, unear;  // Y: pair scratch; Yf: the fused M2L's, one region per level
+  DevBuf fs, flf, ulf, Y, unear;  // Y: pair scratch (fused form: transfers first, then one region per M2L level)
   std::map<int, std::unique_ptr<LaunchSet>> sets;
   // second stream for the near field (default priority) and its fork/join events
   hipStream_t side = nullptr;
@@ -1424,7 +1445,7 @@ static void prepare_fused(const dfmm_plan_s& P, int nrhs, int nt, Fused& F) {
   const auto probs = m2l_problems(P);
   std::vector<int32_t> ps, grp, col0;
   F.yoff.clear();
-  int64_t off = 0;
+  int64_t off = pair_rows_transfer(P) * nrhs;  // past the transfers' scratch
   for (size_t i = 0; i < probs.size(); ++i) {
     std::vector<int32_t> g1, c1;
     make_chunks(*probs[i], nrhs, nt * 16, g1, c1);
@@ -1474,7 +1495,7 @@ static void launch_fused(const dfmm_plan_s& P, const ApplyState& S, const Fused&
     const GGemm& G = *probs[i];
     const float2* X = level[i] >= 0 ? S.F[size_t(level[i])]->as<float2>() : S.flf.as<float2>();
     pr.p[i] = GgProb{G.A.as<float4>(), G.aoff.as<int64_t>(), G.aexp.as<int>(), G.gmk.as<int>(), G.ops.as<int>(),
-                     G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), X, S.Yf.as<float2>() + F.yoff[i], G.M,
+                     G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), X, S.Y.as<float2>() + F.yoff[i], G.M,
                      G.K, G.split, 1};
     lds = std::max(lds, gg_lds_total(kpad(G.K, G.prec) * G.split, F.nt, gg_mt(G, 1), false));
   }
@@ -1526,10 +1547,10 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
 
 // Device bytes of each workspace buffer for nrhs right-hand sides.
 struct WsSizes {
-  size_t fs, unear, flf, ulf, Y, Yf;
+  size_t fs, unear, flf, ulf, Y;
   std::vector<size_t> F, U;
   size_t total() const {
-    size_t t = fs + unear + flf + ulf + Y + Yf;
+    size_t t = fs + unear + flf + ulf + Y;
     for (size_t b : F) t += b;
     for (size_t b : U) t += b;
     return t;
@@ -1543,19 +1564,13 @@ static WsSizes ws_sizes(const dfmm_plan_s& P, int nrhs) {
   z.unear = sizeof(double2) * N * nrhs;
   z.flf = sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs;
   z.ulf = z.flf;
-  int64_t ymax = P.lf.npairs * P.lf.R;
   for (const auto& H : P.hf) {
     z.F.push_back(sizeof(float2) * std::max<int64_t>(1, H.nout) * H.R * nrhs);
     z.U.push_back(sizeof(float2) * std::max<int64_t>(1, H.nin) * H.R * nrhs);
-    ymax = std::max<int64_t>(ymax, H.npairs * H.R);
-    ymax = std::max<int64_t>(ymax, H.m2m_npairs * H.R);
-    ymax = std::max<int64_t>(ymax, H.l2l_npairs * H.Rc);
   }
-  z.Y = sizeof(float2) * std::max<int64_t>(1, ymax) * nrhs;
-  int64_t yf = 0;  // fast plans: every M2L level's pair outputs side by side (fused launch)
-  if (!P.precise)
-    for (const GGemm* G : m2l_problems(P)) yf += G->nvec * G->M;
-  z.Yf = sizeof(float2) * std::max<int64_t>(1, yf) * nrhs;
+  // separate launches reuse one scratch; the fused form keeps the transfers'
+  // scratch and every M2L level's pair outputs side by side
+  z.Y = sizeof(float2) * std::max<int64_t>(1, std::max(pair_rows_separate(P), pair_rows_fused(P))) * nrhs;
   return z;
 }
 
@@ -1581,7 +1596,6 @@ static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
     S.U.back()->alloc(z.U[e]);
   }
   S.Y.alloc(z.Y);
-  S.Yf.alloc(z.Yf);
   S.cap = nrhs;
 }
 
@@ -1705,7 +1719,7 @@ static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet&
     prepare_fused(P, nrhs, nt, LS.fused);
     const float t = timed([&]() {
       launch_fused(P, S, LS.fused, nrhs, st);
-      for (size_t i = 0; i < probs.size(); ++i) reduce(i, S.Yf.as<float2>() + LS.fused.yoff[i]);
+      for (size_t i = 0; i < probs.size(); ++i) reduce(i, S.Y.as<float2>() + LS.fused.yoff[i]);
     });
     if (t < best) {
       best = t;
@@ -1882,7 +1896,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     std::vector<int> level;
     const auto probs = m2l_problems(P, &level);
     for (size_t i = 0; i < probs.size(); ++i)
-      ym2l[level[i] >= 0 ? size_t(level[i]) : P.hf.size()] = S.Yf.as<float2>() + LS.fused.yoff[i];
+      ym2l[level[i] >= 0 ? size_t(level[i]) : P.hf.size()] = S.Y.as<float2>() + LS.fused.yoff[i];
     launch_fused(P, S, LS.fused, nrhs, st);
     mark(ST_M2L);
   }
