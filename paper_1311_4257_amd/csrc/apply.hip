@@ -17,6 +17,8 @@
 #include <initializer_list>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <set>
 #include <string>
 
 #include "internal.hpp"
@@ -1376,18 +1378,25 @@ constexpr int kGgDynLds = 159 * 1024;
 // M-tiles per wave of the largest group for a given number of M-slices
 static int gg_mt(const GGemm& G, int slices) { return (G.M / 8 + 4 * slices - 1) / (4 * slices); }
 
+// Raise a GEMM kernel's dynamic LDS limit, once per (kernel, device): the
+// attribute belongs to the device that is current when it is set.
+static void ensure_lds_limit(const void* fn) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  DFMM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({fn, dev})) return;
+  DFMM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kGgDynLds));
+  done.insert({fn, dev});
+}
+
 template <int NT, bool ALDS, bool ACC64, int NW, int PREC>
 static void launch_nt_a(const Launch& L, int nrhs, const float2* X, float2* Y, hipStream_t st) {
   const GGemm& G = *L.G;
   const size_t lds = gg_lds_total(kpad(G.K, G.prec) * G.split, NT, gg_mt(G, L.slices), ALDS);
   auto kern = L.m2l ? &k_m2l<NT, ALDS, ACC64, NW, PREC> : &k_transfer<NT, ALDS, ACC64, NW, PREC>;
-  static bool attr = false;
-  if (!attr) {
-    for (auto k : {&k_m2l<NT, ALDS, ACC64, NW, PREC>, &k_transfer<NT, ALDS, ACC64, NW, PREC>})
-      DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   kGgDynLds));
-    attr = true;
-  }
+  ensure_lds_limit(reinterpret_cast<const void*>(kern));
   hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(64 * NW), lds, st,
                      G.A.as<float4>(), G.aoff.as<int64_t>(), G.aexp.as<int>(), G.gmk.as<int>(), G.M, G.K, G.split,
                      G.ops.as<int>(),
@@ -1467,12 +1476,7 @@ static void prepare_fused(const dfmm_plan_s& P, int nrhs, int nt, Fused& F) {
 
 template <int NT, int PREC>
 static void launch_fused_t(const GgProbs& pr, size_t lds, const Fused& F, int nrhs, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    DFMM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_m2l_fused<NT, 4, PREC>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, kGgDynLds));
-    attr = true;
-  }
+  ensure_lds_limit(reinterpret_cast<const void*>(&k_m2l_fused<NT, 4, PREC>));
   hipLaunchKernelGGL((k_m2l_fused<NT, 4, PREC>), dim3(unsigned(F.nchunks)), dim3(256), lds, st, pr, F.ps.as<int>(),
                      F.grp.as<int>(), F.col0.as<int>(), nrhs);
 }
