@@ -276,16 +276,17 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
       if (std::sqrt(x * x + y * y + z * z) > lim)
         return fail(DFMM_EDOMAIN, "point " + std::to_string(i) + " lies outside |p| <= K/2");
     }
+    const bool precise = opt->opset ? (opt->opset->tau < 3e-6) : (opt->eps < 1e-5);
+    if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_BF16X3)
+      return fail(DFMM_EINVAL, "unknown precision");
+    if (opt->precision != DFMM_PREC_FP32 && precise)
+      return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
     int dev = opt->device;
     if (dev < 0) DFMM_HIP(hipGetDevice(&dev));
     DFMM_HIP(hipSetDevice(dev));
     std::unique_ptr<dfmm_plan_s> P(new dfmm_plan_s());
     P->device = dev;
-    P->precise = opt->opset ? (opt->opset->tau < 3e-6) : (opt->eps < 1e-5);
-    if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_BF16X3)
-      return fail(DFMM_EINVAL, "unknown precision");
-    if (opt->precision != DFMM_PREC_FP32 && P->precise)
-      return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
+    P->precise = precise;
     P->prec = opt->precision;
     if (const char* dir = opt->cache_dir ? opt->cache_dir : std::getenv("DFMM_CACHE_DIR")) P->tune_dir = dir;
     PlanCtx ctx{opt, nullptr, nullptr};

@@ -46,6 +46,16 @@ def test_bad_inputs_rejected_on_the_host():
         dfmm.Plan(np.zeros((0, 3)), 4.0)
     with pytest.raises(dfmm.DfmmError, match="EINVAL"):
         dfmm.OpSet.build(1e-4, 3)                  # w_hi not a power of two
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, precision=7)           # unknown GEMM precision
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, eps=1e-6, precision=dfmm.PREC_FP16X3)  # split products need eps >= 1e-5
+    lib = dfmm._lib
+    n = ctypes.c_size_t()
+    assert lib.dfmm_workspace_bytes(None, 1, ctypes.byref(n)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    cnt = (ctypes.c_int * 1)(1)
+    assert lib.dfmm_apply_batch(None, 1, arr, arr, cnt, None) == -1
 
 
 def test_library_skeletons_meet_eq2_on_fresh_samples(tmp_path):
