@@ -134,10 +134,17 @@ def cpu_baseline(pts, f, K, eps_tau, n_sample=16384):
         threads = max(int(x.get("num_threads", 1)) for x in threadpool_info()) if threadpool_info() else 1
     except Exception:
         threads = os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {
         "value": n_sample * fs.shape[0] / dt,
         "unit": "matvecs/s",
         "cores": threads,
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"float64 oracle pass on the first {n_sample} points of the same K=16 sphere "
                   f"(same tree depth, the oracle's skeletons at tau={tau:.1e}), {dt:.2f} s; "
@@ -413,7 +420,10 @@ def main() -> int:
     from oracle.kernel import direct_sum, rel_l2
 
     tg = workloads.sample_targets(N, WORKLOADS[args.workload][1], cfg["check_seed"])
-    err = rel_l2(u.cpu().numpy().astype(np.complex128)[:, tg], direct_sum(pts, f, tg))
+    t_ds = time.perf_counter()
+    ref = direct_sum(pts, f, tg)
+    t_ds = time.perf_counter() - t_ds
+    err = rel_l2(u.cpu().numpy().astype(np.complex128)[:, tg], ref)
 
     m2l_ms = stages["hf_m2l"][0] + stages["lf_m2l"][0]
     m2l_launches = stages["hf_m2l"][1] + stages["lf_m2l"][1]
@@ -492,6 +502,9 @@ def main() -> int:
     }
     if not args.no_cpu_baseline and args.workload == "sphere16":
         out["cpu_baseline"] = cpu_baseline(pts, f, K, info.tau)  # the plan's skeleton tolerance
+        # the float64 direct sum of the accuracy gate, on the same host
+        out["cpu_baseline"]["direct_sum"] = {"targets": len(tg), "sources": N, "nrhs": nrhs,
+                                             "seconds": t_ds, "pairs_per_s": len(tg) * N * nrhs / t_ds}
     print(json.dumps(out))
     return 0
 
