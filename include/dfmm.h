@@ -118,7 +118,8 @@ typedef struct {
 void dfmm_options_default(dfmm_options* opt);
 
 /* Plan for N points (host pointer, N x 3 row-major float64, original order)
- * in a domain of width K with end-to-end target eps (1e-7 <= eps <= 1e-2).
+ * in a domain of width K with end-to-end target eps (1e-6 <= eps <= 1e-2; below
+ * 1e-6 the float32 equivalent densities and check potentials set the floor).
  * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
  * every level (Section 2.2), the wedge labels, the needed directions and the
  * translation tables, all resident on the device.  Synchronous.

@@ -260,8 +260,8 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
     if (!points || !opt) return fail(DFMM_EINVAL, "null points or options");
     if (N < 1 || N > (int64_t(1) << 31) - 1) return fail(DFMM_EINVAL, "N must be in [1, 2^31 - 1]");
     if (!is_pow2(K)) return fail(DFMM_EUNSUPPORTED, "K must be a power of two in [1, 2^20]");
-    if (!opt->opset && !(opt->eps >= 1e-7 && opt->eps <= 1e-2))
-      return fail(DFMM_EUNSUPPORTED, "eps must be in [1e-7, 1e-2]");
+    if (!opt->opset && !(opt->eps >= 1e-6 && opt->eps <= 1e-2))
+      return fail(DFMM_EUNSUPPORTED, "eps must be in [1e-6, 1e-2]");
     if (opt->opset) {
       for (auto& v : opt->opset->hf)
         for (auto& s : v)

@@ -42,6 +42,8 @@ def test_bad_inputs_rejected_on_the_host():
         dfmm.Plan(np.array([[np.nan, 0.0, 0.0]]), 4.0)
     with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
         dfmm.Plan(good, 4.0, eps=0.5)
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 4.0, eps=1e-7)             # below the float32 floor
     with pytest.raises(dfmm.DfmmError, match="EINVAL"):
         dfmm.Plan(np.zeros((0, 3)), 4.0)
     with pytest.raises(dfmm.DfmmError, match="EINVAL"):
