@@ -16,6 +16,8 @@
  *   - Host pointers are read during the call only; the library copies what it
  *     keeps.  Device pointers must stay valid until the work enqueued on the
  *     stream has completed.
+ *   - Calls that work on a plan make its device current for their duration
+ *     and leave the caller's current device as they found it, also on failure.
  */
 #ifndef DFMM_H
 #define DFMM_H

@@ -40,6 +40,26 @@ int guarded(F&& fn) {
   }
 }
 
+// Makes `dev` current for its lifetime and restores the caller's device after,
+// also when the call fails with an exception.
+class DeviceScope {
+ public:
+  explicit DeviceScope(int dev) {
+    DFMM_HIP(hipGetDevice(&prev_));
+    if (prev_ != dev) DFMM_HIP(hipSetDevice(dev));
+    switched_ = prev_ != dev;
+  }
+  ~DeviceScope() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+  DeviceScope(const DeviceScope&) = delete;
+  DeviceScope& operator=(const DeviceScope&) = delete;
+
+ private:
+  int prev_ = 0;
+  bool switched_ = false;
+};
+
 bool is_pow2(double K) {
   if (!(K >= 1.0) || !(K <= 1048576.0)) return false;
   double r = std::round(K);
@@ -283,7 +303,7 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
       return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
     int dev = opt->device;
     if (dev < 0) DFMM_HIP(hipGetDevice(&dev));
-    DFMM_HIP(hipSetDevice(dev));
+    DeviceScope on(dev);
     std::unique_ptr<dfmm_plan_s> P(new dfmm_plan_s());
     P->device = dev;
     P->precise = precise;
@@ -309,11 +329,8 @@ int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream)
     R.u[0] = static_cast<float2*>(u);
     R.k0[0] = 0;
     R.n = 1;
-    int cur = 0;
-    DFMM_HIP(hipGetDevice(&cur));
-    if (cur != plan->device) DFMM_HIP(hipSetDevice(plan->device));
+    DeviceScope on(plan->device);
     run_apply(*plan, R, nrhs, static_cast<hipStream_t>(stream));
-    if (cur != plan->device) DFMM_HIP(hipSetDevice(cur));
     return int(DFMM_OK);
   });
 }
@@ -348,11 +365,8 @@ int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* con
       }
     }
     R.n = nreq;
-    int cur = 0;
-    DFMM_HIP(hipGetDevice(&cur));
-    if (cur != plan->device) DFMM_HIP(hipSetDevice(plan->device));
+    DeviceScope on(plan->device);
     run_apply(*plan, R, total, static_cast<hipStream_t>(stream));
-    if (cur != plan->device) DFMM_HIP(hipSetDevice(cur));
     return int(DFMM_OK);
   });
 }
@@ -416,6 +430,7 @@ int dfmm_set_timing(dfmm_plan_t plan, int applies) {
   return guarded([&]() {
     if (!plan) return fail(DFMM_EINVAL, "null plan");
     if (applies < 0 || applies > 100000) return fail(DFMM_EINVAL, "applies must be in [0, 100000]");
+    DeviceScope on(plan->device);
     delete plan->timer;
     plan->timer = nullptr;
     if (applies > 0) plan->timer = new StageTimer(applies);
@@ -427,6 +442,7 @@ int dfmm_stage_times(dfmm_plan_t plan, double* ms, int64_t* launches, int cap, i
   return guarded([&]() {
     if (!plan || !n || !ms || !launches) return fail(DFMM_EINVAL, "null argument");
     if (!plan->timer) return fail(DFMM_EINVAL, "timing is not enabled on this plan");
+    DeviceScope on(plan->device);
     double t[ST_COUNT];
     int64_t c[ST_COUNT];
     plan->timer->collect(t, c);
