@@ -161,12 +161,15 @@ __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict
 // ---- leaf S2M: outgoing check potentials chk[p] = sum_j V[j][p] f_j ----------------
 // One block per leaf, threads over check points (the weights of consecutive
 // check points are contiguous).  D_LF is folded into the operators that read
-// these potentials.
+// these potentials.  With few right-hand sides the loop over the leaf's
+// sources is bound by load latency, so the weights of SU sources are loaded
+// before any of them is used (the products are still added in source order).
 constexpr int S2M_BS = 128;
 template <int RC>  // right-hand sides per pass
 __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, const float2* __restrict__ V,
                                                  const float2* __restrict__ fs, int R, int nrhs,
                                                  float2* __restrict__ clf) {
+  constexpr int SU = RC <= 8 ? 4 : 1;  // sources per loaded batch
   const int b = blockIdx.x;
   const int s0 = lstart[b], s1 = lstart[b + 1];
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
@@ -175,7 +178,18 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
       float2 acc[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) acc[k] = make_float2(0.f, 0.f);
-      for (int j = s0; j < s1; ++j) {
+      int j = s0;
+      for (; j + SU <= s1; j += SU) {
+        float2 v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) v[u] = V[int64_t(j + u) * R + p];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int k = 0; k < RC; ++k)
+            if (k < nk) cfma(acc[k], v[u], fs[int64_t(j + u) * nrhs + k0 + k]);
+      }
+      for (; j < s1; ++j) {
         const float2 v = V[int64_t(j) * R + p];
 #pragma unroll
         for (int k = 0; k < RC; ++k)
@@ -1886,8 +1900,12 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
                          H.m2m_ri.as<int>(), S.Y.as<float2>(), H.nout, RN, 0, S.F[e]->as<float2>());
     mark(ST_M2M);
   }
-  // HF-M2L (+ reduction) then HF-L2L, coarse to fine
-  if (e_top >= 0) {
+  // HF-M2L (+ reduction) then HF-L2L, coarse to fine.  Below the top level the
+  // M2L sums are added to what L2L wrote; at the top level the reduction
+  // writes every incoming slot itself, so the slots need clearing only when
+  // that level has no M2L pairs.
+  const bool top_m2l = e_top >= 0 && LS.m2l[e_top].nchunks > 0;
+  if (e_top >= 0 && !top_m2l) {
     HFLevel& H = P.hf[e_top];
     int64_t n = std::max<int64_t>(1, H.nin) * H.R * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.U[e_top]->as<float2>(), n);
@@ -1913,7 +1931,8 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
       }
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
-                         H.red_idx.as<int>(), ym2l[size_t(e)], H.nin, RN, 1, S.U[e]->as<float2>());
+                         H.red_idx.as<int>(), ym2l[size_t(e)], H.nin, RN, e == e_top ? 0 : 1,
+                         S.U[e]->as<float2>());
       mark(ST_REDUCE);
     }
     float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
@@ -1924,7 +1943,9 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
                          H.l2l_ri.as<int>(), S.Y.as<float2>(), H.nchild_in, RNc, 0, Uc);
     mark(ST_L2L);
   }
-  if (e_top < 0) {
+  // without HF levels nothing has written the LF incoming slots: the LF
+  // reduction writes them itself, or they are cleared if it does not run
+  if (e_top < 0 && LS.lf_m2l.nchunks == 0) {
     int64_t n = nleaf * Rl * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.ulf.as<float2>(), n);
     mark(ST_ZERO);
@@ -1937,7 +1958,8 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     }
     int RN = Rl * nrhs;
     hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
-                       P.lf.red_idx.as<int>(), ym2l[P.hf.size()], nleaf, RN, 1, S.ulf.as<float2>());
+                       P.lf.red_idx.as<int>(), ym2l[P.hf.size()], nleaf, RN, e_top >= 0 ? 1 : 0,
+                       S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
   DFMM_HIP(hipStreamWaitEvent(st, S.join, 0));
