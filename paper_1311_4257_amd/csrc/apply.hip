@@ -335,26 +335,27 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
   // latency overlaps it.
   const int total = mcnt * Q4;  // flat (tile, k-step) sequence of this wave
   const int lofs = (j >> 1) * 4 + kr;
-  const int64_t tbase0 = ALDS ? int64_t(wave) * tile4 : int64_t(m0) * tile4;
-  const int64_t tjump = ALDS ? int64_t(NW) * tile4 : int64_t(mstep) * tile4;
+  // Offsets are 32-bit (one operator holds far fewer than 2^31 float4) and
+  // strictly increase along the sequence (every advance adds at least 32), so
+  // clamping to the last step's offset repeats it past the end.  The loop
+  // bookkeeping is scalar work that competes with the MFMAs for issue slots,
+  // hence no branches and no 64-bit arithmetic here.
+  const int tbase0 = ALDS ? wave * tile4 : m0 * tile4;
+  const int tjump = ALDS ? NW * tile4 : mstep * tile4;
   const float4* abase = (ALDS ? static_cast<const float4*>(as) : Aop) + lofs;
-  const int64_t last = tbase0 + int64_t(mcnt - 1) * tjump + int64_t(Q4 - 1) * 32;
+  const int last = tbase0 + (mcnt - 1) * tjump + (Q4 - 1) * 32;
+  const int pwrap = tjump - (Q4 - 1) * 32;  // from a tile's last k-step to the next tile's first
   int ps = 0;                 // k-step of the next prefetch within its tile
-  int64_t pofs = tbase0;      // its offset
-  int pi = 0;                 // its flat index
+  int pofs = tbase0;          // its offset
   auto advance = [&]() {
-    ++pi;
-    if (++ps == Q4) {
-      ps = 0;
-      pofs += tjump - int64_t(Q4 - 1) * 32;
-    } else {
-      pofs += 32;
-    }
+    const bool wrap = ++ps == Q4;
+    ps = wrap ? 0 : ps;
+    pofs += wrap ? pwrap : 32;
   };
-  auto fetch = [&]() -> float4 {  // steps pi (even lane) and pi + 1 (odd lane)
-    const int64_t o0 = pi < total ? pofs : last;
+  auto fetch = [&]() -> float4 {  // the next two steps: the even lane's, then the odd lane's
+    const int o0 = min(pofs, last);
     advance();
-    const int64_t o1 = pi < total ? pofs : last;
+    const int o1 = min(pofs, last);
     advance();
     return abase[odd ? o1 : o0];
   };
@@ -579,6 +580,7 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
       av[2] = odd ? v.w : w.z;
       av[3] = odd ? v.z : -w.w;
     };
+    int s2 = 2 % Q4;  // the k-step two ahead of s, within its tile
     auto step = [&](const float (&av)[4], float4 (&b)[NT]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -587,11 +589,9 @@ __device__ __forceinline__ void ggemm_tile(const float4* __restrict__ A, const i
           const float bv = u == 0 ? b[n].x : (u == 1 ? b[n].y : (u == 2 ? b[n].z : b[n].w));
           acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv, acc[n], 0, 0, 0);
         }
-      int s2 = s + 2;  // the k-step two ahead, within its tile
-      if (s2 >= Q4) s2 -= Q4;
-      if (s2 >= Q4) s2 -= Q4;
 #pragma unroll
       for (int n = 0; n < NT; ++n) b[n] = bcol[n * 16 * S4 + s2];
+      s2 = s2 + 1 == Q4 ? 0 : s2 + 1;  // s advances by one step, cyclically within the tile
       if constexpr (ACC64) {
         if ((s & 1) || s + 1 == Q4) {
 #pragma unroll
