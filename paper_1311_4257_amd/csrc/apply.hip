@@ -1451,6 +1451,7 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
   if (!gg_fits(G, L.nt, L.slices, L.alds, L.nw))
     throw Error{DFMM_EUNSUPPORTED, "skeleton rank too large for the GEMM kernel"};
   if (L.nt == 4) launch_nt<4>(L, nrhs, X, Y, st);
+  else if (L.nt == 3) launch_nt<3>(L, nrhs, X, Y, st);
   else if (L.nt == 2) launch_nt<2>(L, nrhs, X, Y, st);
   else launch_nt<1>(L, nrhs, X, Y, st);
 }
@@ -1539,7 +1540,7 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
   bool best_alds = false;
   for (int nw : {4, 2})
   for (int alds = 0; alds < 2; ++alds)
-  for (int nt : {1, 2, 4})
+  for (int nt : {1, 2, 3, 4})
     for (int sl = 1; sl <= std::min(std::max(1, (nM + nw - 1) / nw), 4); ++sl) {
       if (!gg_fits(G, nt, sl, alds != 0, nw)) continue;
       prepare_cfg(L, G, nrhs, nt, sl, nw, alds != 0);
@@ -1652,12 +1653,12 @@ static bool load_tuning(const std::string& path, std::vector<Launch*>& ls, const
   FILE* fp = std::fopen(path.c_str(), "r");
   if (!fp) return false;
   int n = 0;
-  bool ok = std::fscanf(fp, "dfmm-tune 3 %d", &n) == 1 && n == int(ls.size());
+  bool ok = std::fscanf(fp, "dfmm-tune 4 %d", &n) == 1 && n == int(ls.size());
   std::vector<int> v(4 * size_t(std::max(n, 0)));
   for (int i = 0; ok && i < n; ++i) {
     int* c = &v[4 * size_t(i)];  // tile width, M-slices, operator in LDS, waves
     ok = std::fscanf(fp, "%d %d %d %d", &c[0], &c[1], &c[2], &c[3]) == 4;
-    ok = ok && (c[0] == 1 || c[0] == 2 || c[0] == 4) && c[1] >= 1 && c[1] <= 64 && (c[3] == 2 || c[3] == 4);
+    ok = ok && c[0] >= 1 && c[0] <= 4 && c[1] >= 1 && c[1] <= 64 && (c[3] == 2 || c[3] == 4);
   }
   ok = ok && std::fscanf(fp, " fused %d", fused_nt) == 1 &&
        (*fused_nt == 0 || *fused_nt == 1 || *fused_nt == 2 || *fused_nt == 4);
@@ -1676,7 +1677,7 @@ static void save_tuning(const std::string& path, const std::vector<Launch*>& ls,
   const std::string tmp = path + ".tmp";
   FILE* fp = std::fopen(tmp.c_str(), "w");
   if (!fp) return;  // the record is an optimisation only
-  std::fprintf(fp, "dfmm-tune 3 %d\n", int(ls.size()));
+  std::fprintf(fp, "dfmm-tune 4 %d\n", int(ls.size()));
   for (const Launch* L : ls) std::fprintf(fp, "%d %d %d %d\n", L->nt, L->slices, L->alds ? 1 : 0, L->nw);
   std::fprintf(fp, "fused %d\n", fused_nt);
   const bool ok = std::fclose(fp) == 0;
