@@ -232,6 +232,37 @@ def test_repeat_is_bitwise_deterministic(cuda):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_gemm_launch_shapes_do_not_change_results(cuda, tmp_path, nrhs):
+    """Every GEMM launch shape (16-64 columns per workgroup, M-slices, 4- or
+    2-wave workgroups, operator staged in LDS or not, fused M2L) gives the same
+    potentials bit for bit: a shape only regroups whole columns and whole
+    16-row tiles, and every output entry keeps its order of products.  The
+    shapes are forced through the tuning record that the first apply wrote."""
+    import glob
+
+    dfmm = _dfmm()
+    pts, _, cfg = workloads.make_config("sphere4", N=2048)
+    f = workloads.densities(len(pts), nrhs, 707)
+    ops = inject(oracle_opset(1e-3, 1))
+    fd = _to_dev(f, cuda)
+    plan = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0)
+    ref = plan.apply(fd).cpu().numpy()
+    recs = glob.glob(str(tmp_path / "dfmm_tune_*.txt"))
+    assert len(recs) == 1
+    n = int(open(recs[0]).read().split()[2])
+    shapes = [(1, 1, 0, 4, 0), (2, 2, 0, 4, 0), (3, 1, 0, 4, 0), (4, 3, 0, 4, 0), (3, 2, 1, 4, 0),
+              (1, 4, 0, 2, 0), (4, 1, 0, 2, 0), (2, 1, 0, 4, 4), (3, 1, 0, 4, 1)]
+    for nt, sl, alds, nw, fused in shapes:
+        text = f"dfmm-tune 4 {n}\n" + f"{nt} {sl} {alds} {nw}\n" * n + f"fused {fused}\n"
+        with open(recs[0], "w") as fh:
+            fh.write(text)
+        p2 = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0)
+        u = p2.apply(fd).cpu().numpy()
+        assert open(recs[0]).read() == text, "the forced shape was not taken"
+        assert np.array_equal(u, ref), (nt, sl, alds, nw, fused)
+
+
 @pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_sphere16_full_size_sampled_targets(cuda, eps):
     """The benchmark workload (K = 16 sphere, N = 65,536) with the eps = 1e-4 and the
