@@ -232,13 +232,15 @@ def test_repeat_is_bitwise_deterministic(cuda):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("nrhs", [1, 5])
-def test_gemm_launch_shapes_do_not_change_results(cuda, tmp_path, nrhs):
+@pytest.mark.parametrize("nrhs,prec", [(1, 0), (5, 0), (1, 1), (5, 2)])
+def test_gemm_launch_shapes_do_not_change_results(cuda, tmp_path, nrhs, prec):
     """Every GEMM launch shape (16-64 columns per workgroup, M-slices, 4- or
     2-wave workgroups, operator staged in LDS or not, fused M2L) gives the same
-    potentials bit for bit: a shape only regroups whole columns and whole
-    16-row tiles, and every output entry keeps its order of products.  The
-    shapes are forced through the tuning record that the first apply wrote."""
+    potentials bit for bit, in float32 and in the split 16-bit GEMMs: a shape
+    only regroups whole columns and whole 16-row tiles, every output entry
+    keeps its order of products, and the 16-bit scales are per operator and
+    per column.  The shapes are forced through the tuning record that the
+    first apply wrote."""
     import glob
 
     dfmm = _dfmm()
@@ -246,7 +248,7 @@ def test_gemm_launch_shapes_do_not_change_results(cuda, tmp_path, nrhs):
     f = workloads.densities(len(pts), nrhs, 707)
     ops = inject(oracle_opset(1e-3, 1))
     fd = _to_dev(f, cuda)
-    plan = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0)
+    plan = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0, precision=prec)
     ref = plan.apply(fd).cpu().numpy()
     recs = glob.glob(str(tmp_path / "dfmm_tune_*.txt"))
     assert len(recs) == 1
@@ -257,7 +259,7 @@ def test_gemm_launch_shapes_do_not_change_results(cuda, tmp_path, nrhs):
         text = f"dfmm-tune 4 {n}\n" + f"{nt} {sl} {alds} {nw}\n" * n + f"fused {fused}\n"
         with open(recs[0], "w") as fh:
             fh.write(text)
-        p2 = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0)
+        p2 = dfmm.Plan(pts, cfg["K"], opset=ops, cache_dir=str(tmp_path), device=0, precision=prec)
         u = p2.apply(fd).cpu().numpy()
         assert open(recs[0]).read() == text, "the forced shape was not taken"
         assert np.array_equal(u, ref), (nt, sl, alds, nw, fused)
