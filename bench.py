@@ -1,22 +1,27 @@
 """Benchmark: directional FMM matvecs per second on one MI355X.
 
-Workload: N = 65,536 points uniform on a sphere of diameter K = 16 wavelengths
-(seed 2), complex64 densities with real and imaginary parts iid N(0, 1),
-one right-hand side, plan eps = 1e-4.  A step is one dfmm_apply (the whole
-evaluation pass: S2M, HF-M2M, HF-M2L + L2L, LF-M2L, L2T and the near-field
-sum) with inputs and outputs resident in HBM.
+Workload (default): N = 262,144 points on the ellipsoid with semi-axes
+(16, 8, 4) wavelengths in a K = 32 box, uniform in area (seed 3), 32
+right-hand sides of complex64 densities with real and imaginary parts iid
+N(0, 1) (seed 303), plan eps = 1e-4.  ``--workload sphere16`` takes the K = 16
+sphere with N = 65,536 and one right-hand side instead.  A step is one
+dfmm_apply (the whole evaluation pass: S2M, HF-M2M, HF-M2L + L2L, LF-M2L, L2T
+and the near-field sum) with inputs and outputs resident in HBM.
 
 Prints one JSON line.  ``value`` counts only if the relative L2 error against
-the float64 direct sum on 2,048 sampled targets is <= eps (reported as
-``rel_l2_err``).  The roofline entry is for the dominant kernel, the grouped
+the float64 direct sum on 2,048 sampled targets (every right-hand side) is
+<= eps (reported as ``rel_l2_err``).  The roofline entry is for the dominant kernel, the grouped
 M2L GEMM (HF and LF launches): algorithmic flops 8 r_in r_out per (pair, rhs)
 divided by the launch time measured with HIP events on the apply stream over
 a second run of the same number of steps (the events cost a little time, so
 ``value`` comes from the event-free run), against the FP32 matrix peak of
 MI355X (157.3 TFLOP/s), or against 8 TB/s when the algorithmic bytes make
 HBM the lower ceiling.
+The algorithmic bytes of the M2L are the operators once per offset group,
+every source slot read once and every target slot read and written once.
 The CPU baseline times the float64 oracle pass on a bounded sample of the
-same geometry.
+same geometry (the first points of the same point set: same K, same tree
+depth, same right-hand sides).
 
 ``--calib-copy`` adds, after the timed steps, one 256 MiB device-to-device
 copy: the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters.
@@ -54,7 +59,7 @@ WORKLOADS = {
     "sphere16": ("sphere16: N=65536 uniform on a sphere of diameter K=16 (seed 2), complex64 N(0,1) "
                  "densities, nrhs=1", 2048),
     "ellipsoid32": ("ellipsoid32: N=262144 area-uniform on the ellipsoid with semi-axes (16, 8, 4) in a "
-                    "K=32 box (seed 3), complex64 N(0,1) densities, nrhs=32", 256),
+                    "K=32 box (seed 3), complex64 N(0,1) densities, nrhs=32", 2048),
 }
 
 
@@ -105,15 +110,14 @@ def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
     return out
 
 
-def cpu_baseline(pts, f, K, eps_tau, n_sample=16384):
-    """Float64 oracle FMM on the first n_sample points of the same sphere (time of the pass only)."""
+def cpu_baseline(pts, f, K, eps_tau, workload, n_sample):
+    """Float64 oracle FMM on the first n_sample points of the same point set (same
+    K and tree depth, every right-hand side); the time of the pass only."""
     import numpy as np
 
-    from oracle.cache import oracle_opset
+    from oracle.cache import cached_taus, oracle_opset
     from oracle.fmm import fmm_apply
     from oracle.tree import build_structure
-
-    from oracle.cache import cached_taus
 
     sub = pts[:n_sample]
     fs = f[:, :n_sample].astype(np.complex128)
@@ -146,9 +150,9 @@ def cpu_baseline(pts, f, K, eps_tau, n_sample=16384):
         "cores": threads,
         "cpu_model": model,
         "kind": "oracle",
-        "sample": f"float64 oracle pass on the first {n_sample} points of the same K=16 sphere "
-                  f"(same tree depth, the oracle's skeletons at tau={tau:.1e}), {dt:.2f} s; "
-                  f"host has {os.cpu_count()} cores",
+        "sample": f"float64 oracle pass on the first {n_sample} of the {len(pts)} points of {workload} "
+                  f"(same K={K:g}, tree depth {st.tree.D}, w_top {st.w_top}, {fs.shape[0]} rhs; the oracle's "
+                  f"skeletons at tau={tau:.1e}), {dt:.2f} s; host has {os.cpu_count()} cores",
     }
 
 
@@ -331,8 +335,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
-    ap.add_argument("--workload", default="sphere16", choices=sorted(WORKLOADS),
-                    help="the K=16 sphere (default, the headline line) or the K=32 ellipsoid with 32 rhs")
+    ap.add_argument("--workload", default="ellipsoid32", choices=sorted(WORKLOADS),
+                    help="the K=32 ellipsoid with 32 rhs (default, the headline line) or the K=16 sphere")
     ap.add_argument("--eps", type=float, default=None, help="plan eps (default: the workload's)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of one workload")
@@ -500,8 +504,9 @@ def main() -> int:
         "near_field": near,
         "plan_seconds": info.plan_seconds,
     }
-    if not args.no_cpu_baseline and args.workload == "sphere16":
-        out["cpu_baseline"] = cpu_baseline(pts, f, K, info.tau)  # the plan's skeleton tolerance
+    if not args.no_cpu_baseline:
+        n_sample = {"sphere16": 16384, "ellipsoid32": 8192}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(pts, f, K, info.tau, args.workload, n_sample)
         # the float64 direct sum of the accuracy gate, on the same host
         out["cpu_baseline"]["direct_sum"] = {"targets": len(tg), "sources": N, "nrhs": nrhs,
                                              "seconds": t_ds, "pairs_per_s": len(tg) * N * nrhs / t_ds}

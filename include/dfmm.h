@@ -99,7 +99,19 @@ typedef struct {
                              measures (dfmm_tune_*.txt, keyed by launch shapes, nrhs, device) */
   int device;             /* HIP device ordinal; -1 = current device */
   int precision;          /* DFMM_PREC_*: arithmetic of the translation GEMMs (default FP32) */
-  int reserved[6];
+  double leaf_width;      /* width of the octree leaves in wavelengths; 0 = the default 1/2.  The
+                             low-frequency level of Section 2.2 is one uniform level of boxes of
+                             width 1/2 (the adaptive point-count split is not built), so any
+                             other value returns DFMM_EUNSUPPORTED */
+  double tol_factor;      /* skeleton truncation tau = tol_factor * eps (Eq. 2 holds to tau per
+                             translation, Section 2.1; the end-to-end error is a small multiple of
+                             it); 0 = the calibrated default (0.1 for eps >= 1e-5, else 0.03);
+                             must lie in (0, 1]; ignored when opset is given */
+  uint64_t hbm_budget_bytes; /* device bytes the plan may hold (0 = no limit): a plan that would
+                             exceed it returns DFMM_ENOMEM -- checked on the host before any
+                             device allocation against a lower bound of the plan's size (its
+                             points and per-point tables), and again against the built plan */
+  int reserved[4];
 } dfmm_options;
 
 /* Arithmetic of the translation GEMMs (M2M, M2L, L2L) of a plan.  FP32: float32
@@ -116,7 +128,8 @@ typedef struct {
 #define DFMM_PREC_FP16X3 1
 #define DFMM_PREC_BF16X3 2
 
-/* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device. */
+/* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device, FP32,
+ * leaf width 1/2, the calibrated tau rule, no HBM budget. */
 void dfmm_options_default(dfmm_options* opt);
 
 /* Plan for N points (host pointer, N x 3 row-major float64, original order)
@@ -125,7 +138,9 @@ void dfmm_options_default(dfmm_options* opt);
  * Builds the Morton-sorted octree (leaf width 1/2), the interaction lists of
  * every level (Section 2.2), the wedge labels, the needed directions and the
  * translation tables, all resident on the device.  Synchronous.
- * The skeletons use tau = 0.1 eps (eps >= 1e-5) or 0.03 eps.  Plans with
+ * The skeletons use tau = 0.1 eps (eps >= 1e-5) or 0.03 eps (or tol_factor eps,
+ * see dfmm_options); they depend only on tau and the box width, not on the
+ * geometry (Section 2.2), and are cached in the cache directory.  Plans with
  * eps < 1e-5 (or an operator set with tau < 3e-6) are "precise": the
  * near-field distances, 1/r and products are float64, the directional
  * operators are stored as float32 hi + lo parts, and every translation GEMM adds
@@ -179,9 +194,25 @@ int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* con
 
 /* Device bytes of the apply workspace for nrhs right-hand sides (vectors, pair
  * scratch, sorted densities and near-field sums), for admission against an HBM
- * budget; the plan's own memory is dfmm_info.device_bytes.  The workspace is
- * grow-only: it holds the size of the largest nrhs applied so far. */
+ * budget and for sizing the workspace of dfmm_apply_ws; the plan's own memory is
+ * dfmm_info.device_bytes.  The plan-owned workspace of dfmm_apply is grow-only:
+ * it holds the size of the largest nrhs applied so far. */
 int dfmm_workspace_bytes(dfmm_plan_t plan, int nrhs, size_t* bytes);
+
+/* dfmm_apply with a caller-owned workspace: `ws` is a DEVICE pointer to at least
+ * dfmm_workspace_bytes(plan, nrhs) bytes (256-byte aligned; DFMM_EINVAL if null,
+ * misaligned or too small), which the apply uses for every intermediate vector
+ * and which must not be touched until the stream has reached the end of the
+ * apply.  The repeated-call use is the matvec inside an iterative boundary
+ * integral solver (Section 1): several such solves can share one plan, and
+ * their applies may run concurrently, from several host threads and on
+ * several streams, as long as each in-flight apply has its own workspace (the
+ * plan itself is read-only in an apply; the first apply of a new nrhs on a plan
+ * prepares its launch shapes under a lock and may allocate and time them, as
+ * dfmm_apply does).  Everything, the near-field sum included, runs on `stream`.
+ * f, u, nrhs, layout, stream and capture rules as for dfmm_apply; u is
+ * overwritten. */
+int dfmm_apply_ws(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* ws, size_t ws_bytes, void* stream);
 
 void dfmm_destroy(dfmm_plan_t plan);
 
@@ -208,7 +239,8 @@ typedef struct {
   double plan_seconds;
   int64_t device_bytes;   /* device memory held by the plan (without the apply workspace) */
   double bytes_m2l_op;    /* M2L operators (complex64, unpadded r_in x r_out), once per offset group */
-  double bytes_m2l_vec;   /* M2L source reads + output writes, 8 (r_in + r_out) per pair, per right-hand side */
+  double bytes_m2l_vec;   /* M2L vectors per right-hand side: every source slot read once (8 r_out) and
+                             every target slot read and written once (16 r_in), complex64, unpadded */
   double flops_m2l_level[32]; /* flops_m2l_hf / flops_m2l_lf split by level 0..D */
   double tau;             /* skeleton tolerance of the plan's operator set */
 } dfmm_info;

@@ -47,7 +47,13 @@ def oracle_opset(tau: float, w_hi: int, cache_dir: str = DEFAULT_DIR) -> O.OpSet
             w *= 2
         lf = O.Skeleton(a=z["a_lf"], b=z["b_lf"], D=z["D_lf"])
         return O.OpSet(tau=tau, w_hi=w_hi, hf=hf, lf=lf)
-    ops = O.build_opset(tau, w_hi)
+    try:  # the pivoted QRs of the build are large: let BLAS use every core
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=os.cpu_count(), user_api="blas"):
+            ops = O.build_opset(tau, w_hi)
+    except ImportError:
+        ops = O.build_opset(tau, w_hi)
     arrs = {"a_lf": ops.lf.a, "b_lf": ops.lf.b, "D_lf": ops.lf.D}
     for w, sks in ops.hf.items():
         for d, s in enumerate(sks):

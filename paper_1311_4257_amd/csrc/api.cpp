@@ -110,7 +110,7 @@ const OpSetImpl* plan_ops(void* vctx, int w_needed) {
     c.used = c.opt->opset;
     return c.used;
   }
-  double tau = tau_for_eps(c.opt->eps);
+  double tau = c.opt->tol_factor > 0.0 ? c.opt->tol_factor * c.opt->eps : tau_for_eps(c.opt->eps);
   int w_hi = 1;
   while (w_hi < w_needed) w_hi *= 2;
   const char* dir = c.opt->cache_dir ? c.opt->cache_dir : std::getenv("DFMM_CACHE_DIR");
@@ -296,7 +296,19 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
       if (std::sqrt(x * x + y * y + z * z) > lim)
         return fail(DFMM_EDOMAIN, "point " + std::to_string(i) + " lies outside |p| <= K/2");
     }
-    const bool precise = opt->opset ? (opt->opset->tau < 3e-6) : (opt->eps < 1e-5);
+    if (!(opt->leaf_width == 0.0 || opt->leaf_width == 0.5))
+      return fail(DFMM_EUNSUPPORTED, "leaf_width must be 1/2 (0 = default): the low-frequency level is one "
+                                     "uniform level of width 1/2");
+    if (!opt->opset && !(opt->tol_factor == 0.0 || (opt->tol_factor > 0.0 && opt->tol_factor <= 1.0)))
+      return fail(DFMM_EINVAL, "tol_factor must be in (0, 1] (0 = default)");
+    // HBM budget, checked before any device call: sorted points (hi + lo float4
+    // pairs), the float64 copy of the input, permutation and leaf index per point
+    if (opt->hbm_budget_bytes > 0 && uint64_t(N) * 64u > opt->hbm_budget_bytes)
+      return fail(DFMM_ENOMEM, "the plan needs at least " + std::to_string(uint64_t(N) * 64u) +
+                                   " device bytes; hbm_budget_bytes is " + std::to_string(opt->hbm_budget_bytes));
+    const double tau_plan = opt->opset ? opt->opset->tau
+                                       : (opt->tol_factor > 0.0 ? opt->tol_factor * opt->eps : tau_for_eps(opt->eps));
+    const bool precise = tau_plan < 3e-6;
     if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_BF16X3)
       return fail(DFMM_EINVAL, "unknown precision");
     if (opt->precision != DFMM_PREC_FP32 && precise)
@@ -311,6 +323,9 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
     if (const char* dir = opt->cache_dir ? opt->cache_dir : std::getenv("DFMM_CACHE_DIR")) P->tune_dir = dir;
     PlanCtx ctx{opt, nullptr, nullptr};
     build_plan(*P, points, N, K, &plan_ops, &ctx);
+    if (opt->hbm_budget_bytes > 0 && uint64_t(P->info.device_bytes) > opt->hbm_budget_bytes)
+      return fail(DFMM_ENOMEM, "the plan holds " + std::to_string(P->info.device_bytes) +
+                                   " device bytes; hbm_budget_bytes is " + std::to_string(opt->hbm_budget_bytes));
     *out = P.release();
     return int(DFMM_OK);
   });
@@ -330,7 +345,7 @@ int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream)
     R.k0[0] = 0;
     R.n = 1;
     DeviceScope on(plan->device);
-    run_apply(*plan, R, nrhs, static_cast<hipStream_t>(stream));
+    run_apply(*plan, R, nrhs, static_cast<hipStream_t>(stream), nullptr, 0, false);
     return int(DFMM_OK);
   });
 }
@@ -366,7 +381,30 @@ int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* con
     }
     R.n = nreq;
     DeviceScope on(plan->device);
-    run_apply(*plan, R, total, static_cast<hipStream_t>(stream));
+    run_apply(*plan, R, total, static_cast<hipStream_t>(stream), nullptr, 0, false);
+    return int(DFMM_OK);
+  });
+}
+
+int dfmm_apply_ws(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&]() {
+    if (!plan || !f || !u || !ws) return fail(DFMM_EINVAL, "null plan, vector or workspace");
+    if (nrhs < 1 || nrhs > 4096) return fail(DFMM_EINVAL, "nrhs must be in [1, 4096]");
+    if (reinterpret_cast<uintptr_t>(ws) % kWsAlign != 0) return fail(DFMM_EINVAL, "workspace not 256-byte aligned");
+    const char* fb = static_cast<const char*>(f);
+    const char* ub = static_cast<const char*>(u);
+    const char* wb = static_cast<const char*>(ws);
+    size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
+    if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
+    if ((wb < ub + bytes && ub < wb + ws_bytes) || (wb < fb + bytes && fb < wb + ws_bytes))
+      return fail(DFMM_EINVAL, "the workspace overlaps f or u");
+    ReqTable R{};
+    R.f[0] = static_cast<const float2*>(f);
+    R.u[0] = static_cast<float2*>(u);
+    R.k0[0] = 0;
+    R.n = 1;
+    DeviceScope on(plan->device);
+    run_apply(*plan, R, nrhs, static_cast<hipStream_t>(stream), ws, ws_bytes, false);
     return int(DFMM_OK);
   });
 }

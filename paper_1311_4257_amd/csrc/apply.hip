@@ -707,6 +707,218 @@ __global__ void __launch_bounds__(64 * NW) k_m2l_fused(const GgProbs P, const in
 #undef DFMM_GG_PARAMS
 #undef DFMM_GG_ARGS
 
+// ---- slot-form GEMM: every output slot sums its terms in registers ---------------
+// A workgroup owns one output vector (a slot, 16 NT of its right-hand sides)
+// and one wave per 16-row M-tile of it.  It walks the slot's terms in their
+// fixed order: each term's source columns are staged in LDS (double-buffered:
+// the next term's columns are loaded into registers while this term's
+// products run, and stored after them), and each wave holds the whole tile of
+// the term's operator in registers, loaded one term ahead.  A term's products
+// accumulate in float32 MFMA chains (one operator row against the column, as
+// in the pair form) and are added into float64 sums across terms, so the slot's
+// sum has the rounding of the pair form's fixed-order reduction without its
+// stored pair outputs.  The terms of a launch are of two kinds with their own
+// operator and source arrays (a level's M2L pairs and its L2L terms).
+struct SlotArgs {
+  const int* order;   // launch order of the groups
+  const int* t0;      // term range of each group
+  const int* gm;      // padded rows of each group's operators
+  const int4* terms;  // (operator float4 offset, source vector, K | split << 12 | kind << 14, 0)
+  const float4* A0;
+  const float4* A1;
+  const float2* X0;
+  const float2* X1;
+  int KX0, KX1;       // row strides of the two kinds' source vectors
+  int M;              // row stride of the output vectors
+  int cpg;            // column chunks per group
+  int S4;             // LDS column stride in float4
+  int waves;          // waves per workgroup (M-tiles per slice)
+};
+constexpr int SLOT_UB = 2;  // staged float4 per thread and term
+
+template <int NT, int PMAX>
+__device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* __restrict__ Y) {
+  constexpr int NC = NT * 16;
+  extern __shared__ float4 xs[];  // two buffers of NC columns, S4 float4 each
+  const int BS = 64 * a.waves;
+  const int tid = int(threadIdx.x);
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int j = lane & 15, kr = lane >> 4;
+  const bool odd = (j & 1) != 0;
+  const int chunk = int(blockIdx.x);
+  const int g = a.order[chunk / a.cpg];
+  const int c0 = (chunk % a.cpg) * NC;
+  const int nc = min(NC, nrhs - c0);
+  const int tb = a.t0[g], te = a.t0[g + 1];
+  const int nM = a.gm[g] / 8;
+  const int m = int(blockIdx.y) * a.waves + wave;
+  const bool act = m < nM;  // wave-uniform: this wave's tile has operator rows
+  const int S4 = a.S4;
+  const int lofs = (j >> 1) * 4 + kr;
+
+  struct Tm {
+    const float4* A;
+    const float2* X;  // column c0 of the source slot
+    int KX, Kg, split;
+  };
+  auto decode = [&](int t) {
+    const int4 e = a.terms[t];
+    const int kind = (e.z >> 14) & 1;
+    Tm r;
+    r.KX = kind ? a.KX1 : a.KX0;
+    r.A = (kind ? a.A1 : a.A0) + e.x;
+    r.X = (kind ? a.X1 : a.X0) + (int64_t(e.y) * nrhs + c0) * r.KX;
+    r.Kg = e.z & 0xFFF;
+    r.split = (e.z >> 12) & 3;
+    return r;
+  };
+  float4 xv[SLOT_UB];
+  auto x_load = [&](const Tm& T) {  // this thread's share of the term's columns
+    const int per_col = T.Kg / 2, pcs = per_col / T.split, nel = NC * per_col;
+#pragma unroll
+    for (int u = 0; u < SLOT_UB; ++u) {
+      const int idx = tid + u * BS;
+      xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < nel) {
+        const int col = idx / per_col, q4 = idx - col * per_col;
+        if (col < nc)
+          xv[u] = reinterpret_cast<const float4*>(T.X + int64_t(col) * T.KX)[q4 < pcs ? q4 : q4 - pcs];
+      }
+    }
+  };
+  auto x_store = [&](int buf, const Tm& T) {
+    const int per_col = T.Kg / 2, nel = NC * per_col;
+    float4* xb = xs + buf * NC * S4;
+#pragma unroll
+    for (int u = 0; u < SLOT_UB; ++u) {
+      const int idx = tid + u * BS;
+      if (idx < nel) {
+        const int col = idx / per_col, q4 = idx - col * per_col;
+        xb[col * S4 + q4] = xv[u];
+      }
+    }
+  };
+  // this wave's tile of the term's operator: pair p holds k-steps 2p (even lane)
+  // and 2p + 1 (odd lane; the last step again past an odd end)
+  auto op_load = [&](const Tm& T, float4 (&r)[PMAX]) {
+    const int Q4 = T.Kg / 8;
+    const float4* base = T.A + m * (Q4 * 32) + lofs;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+      if (2 * p < Q4) r[p] = base[min(2 * p + (odd ? 1 : 0), Q4 - 1) * 32];
+  };
+  double a64[NT][4];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a64[n][q] = 0.0;
+  auto compute = [&](const Tm& T, const float4 (&r)[PMAX], int buf) {
+    const int Q4 = T.Kg / 8;
+    const float4* bcol = xs + buf * NC * S4 + j * S4 + kr * Q4;
+    v4f acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+      if (2 * p < Q4) {
+        const float4 v = r[p], w = swap_pair(v);
+        // the complex A fragments as real rows (even row: Re, -Im; odd row: Im, Re)
+        const float a0[4] = {odd ? w.y : v.x, odd ? w.x : -v.y, odd ? w.w : v.z, odd ? w.z : -v.w};
+        const float a1[4] = {odd ? v.y : w.x, odd ? v.x : -w.y, odd ? v.w : w.z, odd ? v.z : -w.w};
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const float4 b = bcol[n * 16 * S4 + 2 * p];
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b.x, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b.y, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b.z, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b.w, acc[n], 0, 0, 0);
+        }
+        if (2 * p + 1 < Q4) {
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const float4 b = bcol[n * 16 * S4 + 2 * p + 1];
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b.x, acc[n], 0, 0, 0);
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b.y, acc[n], 0, 0, 0);
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b.z, acc[n], 0, 0, 0);
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b.w, acc[n], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a64[n][q] += double(acc[n][q]);
+  };
+
+  if (tb < te) {
+    float4 ra[PMAX], rb[PMAX];
+    Tm T = decode(tb);
+    if (act) op_load(T, ra);
+    x_load(T);
+    x_store(0, T);
+    __syncthreads();
+    // two terms per iteration, so that the operator registers alternate statically
+    for (int t = tb;;) {
+      {
+        const bool more = t + 1 < te;
+        Tm Tn = T;
+        if (more) {
+          Tn = decode(t + 1);
+          if (act) op_load(Tn, rb);
+          x_load(Tn);
+        }
+        if (act) compute(T, ra, 0);
+        if (more) x_store(1, Tn);
+        __syncthreads();
+        if (!more) break;
+        T = Tn;
+        ++t;
+      }
+      {
+        const bool more = t + 1 < te;
+        Tm Tn = T;
+        if (more) {
+          Tn = decode(t + 1);
+          if (act) op_load(Tn, ra);
+          x_load(Tn);
+        }
+        if (act) compute(T, rb, 1);
+        if (more) x_store(0, Tn);
+        __syncthreads();
+        if (!more) break;
+        T = Tn;
+        ++t;
+      }
+    }
+  }
+  // lane (j, kr) holds real rows 4 kr .. 4 kr + 3 (complex rows 2 kr, 2 kr + 1) of
+  // tile m for column j of each column tile; tiles past M_g are written as zeros
+  if (m < a.M / 8) {
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int col = n * 16 + j;
+      if (col < nc) {
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (act) o = make_float4(float(a64[n][0]), float(a64[n][1]), float(a64[n][2]), float(a64[n][3]));
+        reinterpret_cast<float4*>(Y + (int64_t(g) * nrhs + c0 + col) * a.M + 8 * m + 2 * kr)[0] = o;
+      }
+    }
+  }
+}
+
+// The slot form under two names, so that kernel traces separate the upward
+// transfers (M2M) from the downward pass (M2L pairs and L2L terms of a level).
+template <int NT, int PMAX>
+__global__ void __launch_bounds__(1024) k_m2m_slot(const SlotArgs a, int nrhs, float2* __restrict__ Y) {
+  slot_gemm<NT, PMAX>(a, nrhs, Y);
+}
+template <int NT, int PMAX>
+__global__ void __launch_bounds__(1024) k_m2l_slot(const SlotArgs a, int nrhs, float2* __restrict__ Y) {
+  slot_gemm<NT, PMAX>(a, nrhs, Y);
+}
+
 // ---- U[slot] (+)= sum of Y over the pairs of the slot -------------------------------
 __global__ void k_reduce(const int* __restrict__ rs, const int* __restrict__ ri, const float2* __restrict__ Y,
                          int64_t nslot, int RN, int accumulate, float2* __restrict__ U) {
@@ -1263,11 +1475,25 @@ struct Fused {
   std::vector<int64_t> yoff;  // per problem: offset (float2) of its pair outputs in the pair scratch
 };
 
+// One slot-form launch prepared for the current nrhs.
+struct SlotLaunch {
+  const SlotGemm* S = nullptr;
+  int nt = 1;          // 16-column tiles per workgroup
+  int slices = 1;      // M-slices (grid y)
+  int waves = 1;       // waves per workgroup
+  int pmax = 8;        // operator pairs per lane held in registers (>= K / 16)
+  int cpg = 1;         // column chunks per group
+  int64_t nchunks = 0;
+};
+
 // The GEMM launches of one nrhs (chunk tables and tuned shapes).
 struct LaunchSet {
-  std::vector<Launch> m2m, l2l, m2l;  // per HF level
+  std::vector<Launch> m2m, l2l, m2l;  // per HF level (pair form)
   Launch lf_m2l;
   Fused fused;
+  bool slot = false;                  // slot form: M2M, and M2L + L2L per level, without pair outputs
+  std::vector<SlotLaunch> up, down;   // per HF level
+  SlotLaunch lf_down;
 };
 
 // The M2L problems of a plan in apply order: HF levels from the top down, then
@@ -1307,12 +1533,29 @@ static int64_t pair_rows_fused(const dfmm_plan_s& P) {
 }
 
 
-// Workspace of a plan: buffers sized for the largest nrhs applied so far
-// (grow-only), launch sets per nrhs.
+// A device pointer with the accessor of DevBuf.
+struct WsPtr {
+  void* p = nullptr;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+// The buffers of one apply, carved out of a workspace by ws_layout.
+struct Ws {
+  WsPtr fs, unear, flf, ulf, Y;
+  std::vector<WsPtr> F, U;  // per HF level
+};
+
+// Plan state of the applies: the plan-owned workspace of dfmm_apply (grow-only,
+// sized for the largest nrhs seen), the launch sets per nrhs and the second
+// stream of the near field.  `mu` guards all of it: dfmm_apply_ws may be
+// called from several threads on one plan.
 struct ApplyState {
-  int cap = 0;
-  std::vector<std::unique_ptr<DevBuf>> F, U;  // per HF level
-  DevBuf fs, flf, ulf, Y, unear;  // Y: pair scratch (fused form: transfers first, then one region per M2L level)
+  std::mutex mu;
+  DevBuf buf;                 // plan-owned workspace
+  std::vector<DevBuf> retired;  // workspaces replaced after a graph capture (captured graphs hold them)
+  bool captured = false;      // an apply of this plan has been captured into a graph
   std::map<int, std::unique_ptr<LaunchSet>> sets;
   // second stream for the near field (default priority) and its fork/join events
   hipStream_t side = nullptr;
@@ -1456,6 +1699,85 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
   else launch_nt<1>(L, nrhs, X, Y, st);
 }
 
+// ---- slot-form launches ----------------------------------------------------------------
+constexpr int kSlotMinRhs = 16;  // fast float32 plans take the slot form from this many rhs
+
+static size_t slot_lds_bytes(const SlotGemm& S, int nt) {
+  return size_t(2) * size_t(nt * 16) * size_t(gg_stride(S.Kmax)) * sizeof(float);
+}
+
+// nt column tiles; one wave per M-tile (at most 16 per workgroup: larger ranks
+// take more M-slices), and enough waves to stage a term's columns
+static bool prepare_slot(SlotLaunch& L, const SlotGemm& S, int nrhs, int nt) {
+  L.S = &S;
+  L.nt = nt;
+  const int NC = 16 * nt;
+  L.cpg = (nrhs + NC - 1) / NC;
+  L.nchunks = S.ngroups * L.cpg;
+  const int nMall = std::max(1, S.M / 8);
+  L.slices = (nMall + 15) / 16;
+  L.waves = (nMall + L.slices - 1) / L.slices;
+  const int need = (NC * (S.Kmax / 2) + 64 * SLOT_UB - 1) / (64 * SLOT_UB);
+  L.waves = std::max(L.waves, need);
+  L.pmax = S.Kmax <= 64 ? 4 : (S.Kmax <= 112 ? 7 : 8);
+  return L.waves <= 16 && S.Kmax <= 128 && slot_lds_bytes(S, nt) <= size_t(kGgDynLds);
+}
+
+// The slot form serves fast float32 plans with at least kSlotMinRhs right-hand
+// sides (DFMM_SLOT=0 forces the pair form, =1 allows it from 1 rhs).
+static bool use_slot(const dfmm_plan_s& P, int nrhs) {
+  if (P.precise || P.prec != DFMM_PREC_FP32) return false;
+  int minr = kSlotMinRhs;
+  if (const char* e = std::getenv("DFMM_SLOT")) {
+    if (e[0] == '0') return false;
+    if (e[0] == '1') minr = 1;
+  }
+  if (nrhs < minr) return false;
+  const int nt = nrhs >= 32 ? 2 : 1;
+  SlotLaunch tmp;
+  for (const auto& H : P.hf)
+    if (!prepare_slot(tmp, H.up, nrhs, nt) || !prepare_slot(tmp, H.down, nrhs, nt)) return false;
+  return prepare_slot(tmp, P.lf.down, nrhs, nt);
+}
+
+template <int NT, int PMAX>
+static void launch_slot_t(const SlotLaunch& L, const SlotArgs& a, int nrhs, float2* Y, bool m2l, hipStream_t st) {
+  const size_t lds = slot_lds_bytes(*L.S, NT);
+  auto kern = m2l ? &k_m2l_slot<NT, PMAX> : &k_m2m_slot<NT, PMAX>;
+  ensure_lds_limit(reinterpret_cast<const void*>(kern));
+  hipLaunchKernelGGL(kern, dim3(unsigned(L.nchunks), unsigned(L.slices)), dim3(64 * L.waves), lds, st, a, nrhs, Y);
+}
+
+// kind 0: operators A0 on source vectors X0 (row stride KX0); kind 1 likewise
+static void launch_slot(const SlotLaunch& L, const float4* A0, const float2* X0, int KX0, const float4* A1,
+                        const float2* X1, int KX1, int nrhs, float2* Y, bool m2l, hipStream_t st) {
+  if (L.nchunks == 0) return;
+  const SlotGemm& S = *L.S;
+  SlotArgs a{S.order.as<int>(), S.t0.as<int>(), S.gm.as<int>(), S.terms.as<int4>(), A0, A1 ? A1 : A0, X0,
+             X1 ? X1 : X0, KX0, X1 ? KX1 : KX0, S.M, L.cpg, gg_stride(S.Kmax) / 4, L.waves};
+  if (L.nt == 2) {
+    if (L.pmax == 4) launch_slot_t<2, 4>(L, a, nrhs, Y, m2l, st);
+    else if (L.pmax == 7) launch_slot_t<2, 7>(L, a, nrhs, Y, m2l, st);
+    else launch_slot_t<2, 8>(L, a, nrhs, Y, m2l, st);
+  } else {
+    if (L.pmax == 4) launch_slot_t<1, 4>(L, a, nrhs, Y, m2l, st);
+    else if (L.pmax == 7) launch_slot_t<1, 7>(L, a, nrhs, Y, m2l, st);
+    else launch_slot_t<1, 8>(L, a, nrhs, Y, m2l, st);
+  }
+}
+
+static void prepare_slot_set(const dfmm_plan_s& P, int nrhs, LaunchSet& LS) {
+  const int nt = nrhs >= 32 ? 2 : 1;
+  LS.slot = true;
+  LS.up.resize(P.hf.size());
+  LS.down.resize(P.hf.size());
+  for (size_t e = 0; e < P.hf.size(); ++e) {
+    prepare_slot(LS.up[e], P.hf[e].up, nrhs, nt);
+    prepare_slot(LS.down[e], P.hf[e].down, nrhs, nt);
+  }
+  prepare_slot(LS.lf_down, P.lf.down, nrhs, nt);
+}
+
 // ---- fused M2L launch ----------------------------------------------------------------
 static bool fused_fits(const dfmm_plan_s& P, int nt) {
   const auto probs = m2l_problems(P);
@@ -1504,7 +1826,7 @@ static void launch_fused_p(const GgProbs& pr, size_t lds, const Fused& F, int nr
 }
 
 // X of problem i: the level's outgoing potentials (the leaves' for the leaf level)
-static void launch_fused(const dfmm_plan_s& P, const ApplyState& S, const Fused& F, int nrhs, hipStream_t st) {
+static void launch_fused(const dfmm_plan_s& P, const Ws& S, const Fused& F, int nrhs, hipStream_t st) {
   if (F.nchunks == 0) return;
   std::vector<int> level;
   const auto probs = m2l_problems(P, &level);
@@ -1512,7 +1834,7 @@ static void launch_fused(const dfmm_plan_s& P, const ApplyState& S, const Fused&
   size_t lds = 0;
   for (size_t i = 0; i < probs.size(); ++i) {
     const GGemm& G = *probs[i];
-    const float2* X = level[i] >= 0 ? S.F[size_t(level[i])]->as<float2>() : S.flf.as<float2>();
+    const float2* X = level[i] >= 0 ? S.F[size_t(level[i])].as<float2>() : S.flf.as<float2>();
     pr.p[i] = GgProb{G.A.as<float4>(), G.aoff.as<int64_t>(), G.aexp.as<int>(), G.gmk.as<int>(), G.ops.as<int>(),
                      G.v0.as<int>(), G.vsrc.as<int>(), G.vdst.as<int>(), X, S.Y.as<float2>() + F.yoff[i], G.M,
                      G.K, G.split, 1};
@@ -1564,58 +1886,63 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
   prepare_cfg(L, G, nrhs, best_nt, best_sl, best_nw, best_alds);
 }
 
-// Device bytes of each workspace buffer for nrhs right-hand sides.
-struct WsSizes {
-  size_t fs, unear, flf, ulf, Y;
-  std::vector<size_t> F, U;
-  size_t total() const {
-    size_t t = fs + unear + flf + ulf + Y;
-    for (size_t b : F) t += b;
-    for (size_t b : U) t += b;
-    return t;
-  }
-};
-
-static WsSizes ws_sizes(const dfmm_plan_s& P, int nrhs) {
-  WsSizes z;
-  const int64_t N = P.N;
-  z.fs = sizeof(float2) * N * nrhs;
-  z.unear = sizeof(double2) * N * nrhs;
-  z.flf = sizeof(float2) * P.lf.nleaf * P.lf.R * nrhs;
-  z.ulf = z.flf;
+// The sizes the workspace of a plan depends on.
+static WsShape ws_shape(const dfmm_plan_s& P) {
+  WsShape z;
+  z.N = P.N;
+  z.nleaf = P.lf.nleaf;
+  z.Rlf = P.lf.R;
   for (const auto& H : P.hf) {
-    z.F.push_back(sizeof(float2) * std::max<int64_t>(1, H.nout) * H.R * nrhs);
-    z.U.push_back(sizeof(float2) * std::max<int64_t>(1, H.nin) * H.R * nrhs);
+    z.nout.push_back(H.nout);
+    z.nin.push_back(H.nin);
+    z.R.push_back(H.R);
   }
   // separate launches reuse one scratch; the fused form keeps the transfers'
   // scratch and every M2L level's pair outputs side by side
-  z.Y = sizeof(float2) * std::max<int64_t>(1, std::max(pair_rows_separate(P), pair_rows_fused(P))) * nrhs;
+  z.pair_rows = std::max(pair_rows_separate(P), pair_rows_fused(P));
   return z;
 }
 
-size_t workspace_bytes(const dfmm_plan_s& P, int nrhs) { return ws_sizes(P, nrhs).total(); }
-
-// Grow the buffers to nrhs right-hand sides (the launch sets do not hold
-// buffer addresses, so they stay valid).
-static void ensure_workspace(dfmm_plan_s& P, int nrhs, ApplyState& S) {
-  if (nrhs <= S.cap) return;
-  DFMM_HIP(hipDeviceSynchronize());  // earlier applies may still read the old buffers
-  const WsSizes z = ws_sizes(P, nrhs);
-  S.cap = 0;  // a failed allocation below leaves the workspace to be rebuilt by the next apply
-  S.fs.alloc(z.fs);
-  S.unear.alloc(z.unear);
-  S.flf.alloc(z.flf);
-  S.ulf.alloc(z.ulf);
-  S.F.clear();
-  S.U.clear();
-  for (size_t e = 0; e < P.hf.size(); ++e) {
-    S.F.emplace_back(new DevBuf());
-    S.U.emplace_back(new DevBuf());
-    S.F.back()->alloc(z.F[e]);
-    S.U.back()->alloc(z.U[e]);
+// Layout for nrhs: with pair scratch unless the launch set of nrhs (the one
+// that exists, else the one that would be made) takes the slot form.  The
+// caller holds the plan's apply lock if the plan has an apply state.
+static WsLayout plan_layout(const dfmm_plan_s& P, int nrhs) {
+  bool slot = use_slot(P, nrhs);
+  if (P.ws) {
+    auto it = P.ws->sets.find(nrhs);
+    if (it != P.ws->sets.end()) slot = it->second->slot;
   }
-  S.Y.alloc(z.Y);
-  S.cap = nrhs;
+  return ws_layout(ws_shape(P), nrhs, !slot);
+}
+
+size_t workspace_bytes(const dfmm_plan_s& P, int nrhs) {
+  if (!P.ws) return plan_layout(P, nrhs).total;
+  std::lock_guard<std::mutex> lock(P.ws->mu);
+  return plan_layout(P, nrhs).total;
+}
+
+static Ws carve(const WsLayout& L, void* base) {
+  char* b = static_cast<char*>(base);
+  Ws W;
+  W.fs.p = b + L.fs;
+  W.unear.p = b + L.unear;
+  W.flf.p = b + L.flf;
+  W.ulf.p = b + L.ulf;
+  W.Y.p = b + L.Y;
+  for (size_t o : L.F) W.F.push_back(WsPtr{b + o});
+  for (size_t o : L.U) W.U.push_back(WsPtr{b + o});
+  return W;
+}
+
+// Grow the plan-owned workspace to `bytes` (the launch sets hold no buffer
+// addresses, so they stay valid).  The old buffer is freed once earlier applies
+// are done with it, or kept until the plan is destroyed if an apply has been
+// captured into a graph (the graph still addresses it).
+static void ensure_workspace(ApplyState& S, size_t bytes) {
+  if (S.buf.p && S.buf.bytes >= bytes) return;
+  DFMM_HIP(hipDeviceSynchronize());  // earlier applies may still use the old buffer
+  if (S.captured && S.buf.p) S.retired.push_back(std::move(S.buf));
+  S.buf.alloc(bytes);
 }
 
 // ---- tuning record: the chosen (tile width, M-slices, LDS operator) per launch,
@@ -1690,7 +2017,7 @@ static void save_tuning(const std::string& path, const std::vector<Launch*>& ls,
 // cache), 3 runs each on the apply stream, and keep the faster form.  The timed
 // reductions add into the incoming potentials, which every apply overwrites
 // or clears before it adds to them.
-static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS, hipStream_t st) {
+static void tune_fused(const dfmm_plan_s& P, int nrhs, const Ws& S, LaunchSet& LS, hipStream_t st) {
   LS.fused.nt = 0;
   bool any = false;
   for (int nt : {1, 2, 4}) any = any || fused_fits(P, nt);
@@ -1715,7 +2042,7 @@ static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet&
       const HFLevel& H = P.hf[size_t(level[i])];
       const int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
-                         H.red_idx.as<int>(), Yp, H.nin, RN, 1, S.U[size_t(level[i])]->as<float2>());
+                         H.red_idx.as<int>(), Yp, H.nin, RN, 1, S.U[size_t(level[i])].as<float2>());
     } else {
       const int RN = P.lf.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(P.lf.nleaf * RN, 256)), dim3(256), 0, st,
@@ -1726,7 +2053,7 @@ static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet&
   const float t_sep = timed([&]() {
     for (size_t i = 0; i < probs.size(); ++i) {
       const Launch& L = level[i] >= 0 ? LS.m2l[size_t(level[i])] : LS.lf_m2l;
-      const float2* X = level[i] >= 0 ? S.F[size_t(level[i])]->as<float2>() : S.flf.as<float2>();
+      const float2* X = level[i] >= 0 ? S.F[size_t(level[i])].as<float2>() : S.flf.as<float2>();
       launch_gemm(L, nrhs, X, S.Y.as<float2>(), st);
       reduce(i, S.Y.as<float2>());
     }
@@ -1752,7 +2079,7 @@ static void tune_fused(const dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet&
 }
 
 // Tune the GEMM launches of nrhs right-hand sides on the apply stream.
-static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS, hipStream_t st) {
+static void tune_launches(dfmm_plan_s& P, int nrhs, const Ws& S, LaunchSet& LS, hipStream_t st) {
   float2* Y = S.Y.as<float2>();
   std::vector<Launch*> ls;
   std::vector<const GGemm*> gs;
@@ -1761,10 +2088,10 @@ static void tune_launches(dfmm_plan_s& P, int nrhs, ApplyState& S, LaunchSet& LS
   LS.l2l.resize(P.hf.size());
   LS.m2l.resize(P.hf.size());
   for (size_t e = 0; e < P.hf.size(); ++e) {
-    const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
+    const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1].as<float2>();
     ls.insert(ls.end(), {&LS.m2m[e], &LS.l2l[e], &LS.m2l[e]});
     gs.insert(gs.end(), {&P.hf[e].m2m, &P.hf[e].l2l, &P.hf[e].m2l});
-    xs.insert(xs.end(), {Fc, S.U[e]->as<float2>(), S.F[e]->as<float2>()});
+    xs.insert(xs.end(), {Fc, S.U[e].as<float2>(), S.F[e].as<float2>()});
     LS.m2l[e].m2l = true;
   }
   ls.push_back(&LS.lf_m2l);
@@ -1809,37 +2136,59 @@ static void inherit_launches(dfmm_plan_s& P, int nrhs, const LaunchSet& from, La
   if (from.fused.nt > 0) prepare_fused(P, nrhs, from.fused.nt, LS.fused);
 }
 
-static LaunchSet& launch_set(dfmm_plan_s& P, ApplyState& S, int nrhs, hipStream_t st) {
-  auto it = S.sets.find(nrhs);
-  if (it != S.sets.end()) return *it->second;
+static LaunchSet& launch_set(dfmm_plan_s& P, ApplyState& AS, const Ws& S, int nrhs, hipStream_t st) {
+  auto it = AS.sets.find(nrhs);
+  if (it != AS.sets.end()) return *it->second;
   std::unique_ptr<LaunchSet> ls(new LaunchSet());
-  if ((nrhs & (nrhs - 1)) == 0) {
+  if (use_slot(P, nrhs)) {
+    prepare_slot_set(P, nrhs, *ls);
+  } else if ((nrhs & (nrhs - 1)) == 0) {
     tune_launches(P, nrhs, S, *ls, st);
   } else {
     int p2 = 1;
     while (2 * p2 < nrhs) p2 *= 2;
-    inherit_launches(P, nrhs, launch_set(P, S, p2, st), *ls);
+    const LaunchSet& from = launch_set(P, AS, S, p2, st);
+    if (from.slot) prepare_slot_set(P, nrhs, *ls);  // no tuned shapes to inherit
+    else inherit_launches(P, nrhs, from, *ls);
   }
-  return *S.sets.emplace(nrhs, std::move(ls)).first->second;
+  return *AS.sets.emplace(nrhs, std::move(ls)).first->second;
 }
 
-void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
+void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void* ws, size_t ws_bytes,
+               bool existing_only) {
   // under stream capture only launches, event records and event waits may be
   // issued: the workspace, the tuning and the side stream must already exist
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   DFMM_HIP(hipStreamIsCapturing(st, &cap));
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  if (capturing && (!P.ws || P.ws->cap < nrhs || !P.ws->sets.count(nrhs) || !P.ws->side))
-    throw Error{DFMM_EINVAL, "dfmm_apply under stream capture needs an earlier uncaptured apply with the same nrhs"};
-  if (!P.ws) P.ws = new ApplyState();
-  ApplyState& S = *P.ws;
-  ensure_workspace(P, nrhs, S);
-  LaunchSet& LS = launch_set(P, S, nrhs, st);
+  const bool own = ws == nullptr;  // plan-owned workspace (dfmm_apply) or the caller's
+  if (!P.ws) {
+    if (capturing || existing_only)
+      throw Error{DFMM_EINVAL, "this apply needs an earlier apply with the same nrhs on the plan"};
+    P.ws = new ApplyState();
+  }
+  ApplyState& AS = *P.ws;
+  std::unique_lock<std::mutex> lock(AS.mu);
+  const WsLayout L = plan_layout(P, nrhs);
+  if (!own && ws_bytes < L.total)
+    throw Error{DFMM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes; this apply needs " +
+                                 std::to_string(L.total)};
+  const bool have_set = AS.sets.count(nrhs) != 0;
+  if ((capturing || existing_only) && (!have_set || (own && (!AS.buf.p || AS.buf.bytes < L.total || !AS.side))))
+    throw Error{DFMM_EINVAL, "dfmm_apply under stream capture (or without allocation) needs an earlier "
+                             "uncaptured apply with the same nrhs"};
+  if (own) ensure_workspace(AS, L.total);
+  const Ws S = carve(L, own ? AS.buf.p : ws);
+  LaunchSet& LS = launch_set(P, AS, S, nrhs, st);
+  if (capturing) AS.captured = true;
+  // the launch set is immutable from here; applies on caller workspaces run
+  // concurrently (the stage timer and the second stream belong to dfmm_apply)
+  if (!own) lock.unlock();
   const int64_t N = P.N;
   const int64_t nleaf = P.lf.nleaf;
   const int Rl = P.lf.R;
   const int e_top = int(P.hf.size()) - 1;
-  StageTimer* tm = P.timer;
+  StageTimer* tm = own ? P.timer : nullptr;
   if (tm && (capturing || !tm->begin_apply(st))) tm = nullptr;  // no stage events inside a graph
   auto mark = [&](int stage) {
     if (tm) tm->mark(stage, st);
@@ -1847,14 +2196,19 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, R, S.fs.as<float2>(),
                      P.perm_d.as<int>(), N, nrhs);
   mark(ST_PERMUTE);
-  // the near field needs only the permuted densities: it runs on the side
-  // stream while the far-field passes run on st
-  S.ensure_side();
-  DFMM_HIP(hipEventRecord(S.fork, st));
-  DFMM_HIP(hipStreamWaitEvent(S.side, S.fork, 0));
-  if (tm) tm->side_begin(S.side);
+  // the near field needs only the permuted densities: it runs on the plan's
+  // second stream while the far-field passes run on st (on st itself when the
+  // workspace is the caller's)
+  hipStream_t nst = st;
+  if (own) {
+    AS.ensure_side();
+    DFMM_HIP(hipEventRecord(AS.fork, st));
+    DFMM_HIP(hipStreamWaitEvent(AS.side, AS.fork, 0));
+    nst = AS.side;
+    if (tm) tm->side_begin(nst);
+  }
 #define DFMM_NEAR(PREC, RCV)                                                                                   \
-  hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, S.side, P.pthi.as<float4>(), \
+  hipLaunchKernelGGL((k_leaf_eval<PREC, RCV>), dim3(unsigned(nleaf)), dim3(EV_BS), 0, nst, P.pthi.as<float4>(), \
                      P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),    \
                      S.fs.as<float2>(), nrhs, N, S.unear.as<double2>())
   if (P.precise) {
@@ -1863,7 +2217,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     const dim3 grid(unsigned(nleaf), unsigned((nrhs + 31) / 32), unsigned((P.max_leaf_pts + NM_TB - 1) / NM_TB));
     const dim3 grid1(unsigned(nleaf), unsigned((nrhs + 15) / 16), grid.z);
 #define DFMM_NEARM(NCT, PR, G)                                                                                   \
-  hipLaunchKernelGGL((k_near_mfma<NCT, PR>), G, dim3(64 * NM_NW), 0, S.side, P.pthi.as<float4>(),               \
+  hipLaunchKernelGGL((k_near_mfma<NCT, PR>), G, dim3(64 * NM_NW), 0, nst, P.pthi.as<float4>(),               \
                      P.ptlo.as<float4>(), P.leaf_start.as<int>(), P.near_start.as<int>(), P.near_src.as<int>(),   \
                      S.fs.as<float2>(), nrhs, N, S.unear.as<double2>())
     if (P.prec == DFMM_PREC_FP16X3) {
@@ -1878,8 +2232,12 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     if (nrhs == 1) DFMM_NEAR(false, 1); else DFMM_NEAR(false, 8);
   }
 #undef DFMM_NEAR
-  if (tm) tm->side_mark(ST_NEAR, S.side);
-  DFMM_HIP(hipEventRecord(S.join, S.side));
+  if (own) {
+    if (tm) tm->side_mark(ST_NEAR, nst);
+    DFMM_HIP(hipEventRecord(AS.join, nst));
+  } else {
+    mark(ST_NEAR);
+  }
   if (nrhs == 1)
     hipLaunchKernelGGL(k_s2m<1>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
@@ -1890,30 +2248,53 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     hipLaunchKernelGGL(k_s2m<32>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
   mark(ST_S2M);
+  if (LS.slot) {
+    // slot form: M2M fine to coarse; then per level, coarse to fine, one launch
+    // sums the M2L pairs and the L2L terms of every incoming slot
+    for (int e = 0; e <= e_top; ++e) {
+      const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1].as<float2>();
+      const int KC = e == 0 ? Rl : P.hf[e - 1].R;
+      launch_slot(LS.up[e], P.hf[e].m2m.A.as<float4>(), Fc, KC, nullptr, nullptr, 0, nrhs,
+                  S.F[e].as<float2>(), false, st);
+      mark(ST_M2M);
+    }
+    for (int e = e_top; e >= 0; --e) {
+      const HFLevel& H = P.hf[e];
+      const bool par = e < e_top;
+      launch_slot(LS.down[e], H.m2l.A.as<float4>(), S.F[e].as<float2>(), H.R,
+                  par ? P.hf[e + 1].l2l.A.as<float4>() : nullptr, par ? S.U[e + 1].as<float2>() : nullptr,
+                  par ? P.hf[e + 1].R : 0, nrhs, S.U[e].as<float2>(), true, st);
+      mark(ST_M2L);
+    }
+    launch_slot(LS.lf_down, P.lf.m2l.A.as<float4>(), S.flf.as<float2>(), Rl,
+                e_top >= 0 ? P.hf[0].l2l.A.as<float4>() : nullptr, e_top >= 0 ? S.U[0].as<float2>() : nullptr,
+                e_top >= 0 ? P.hf[0].R : 0, nrhs, S.ulf.as<float2>(), true, st);
+    mark(ST_LF_M2L);
+  }
   // HF-M2M, fine to coarse
-  for (int e = 0; e <= e_top; ++e) {
+  for (int e = 0; e <= e_top && !LS.slot; ++e) {
     HFLevel& H = P.hf[e];
-    const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1]->as<float2>();
+    const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1].as<float2>();
     launch_gemm(LS.m2m[e], nrhs, Fc, S.Y.as<float2>(), st);
     int RN = H.R * nrhs;
     if (H.nout > 0)
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nout * RN, 256)), dim3(256), 0, st, H.m2m_rs.as<int>(),
-                         H.m2m_ri.as<int>(), S.Y.as<float2>(), H.nout, RN, 0, S.F[e]->as<float2>());
+                         H.m2m_ri.as<int>(), S.Y.as<float2>(), H.nout, RN, 0, S.F[e].as<float2>());
     mark(ST_M2M);
   }
   // HF-M2L (+ reduction) then HF-L2L, coarse to fine.  Below the top level the
   // M2L sums are added to what L2L wrote; at the top level the reduction
   // writes every incoming slot itself, so the slots need clearing only when
   // that level has no M2L pairs.
-  const bool top_m2l = e_top >= 0 && LS.m2l[e_top].nchunks > 0;
-  if (e_top >= 0 && !top_m2l) {
+  const bool top_m2l = e_top >= 0 && !LS.slot && LS.m2l[e_top].nchunks > 0;
+  if (e_top >= 0 && !top_m2l && !LS.slot) {
     HFLevel& H = P.hf[e_top];
     int64_t n = std::max<int64_t>(1, H.nin) * H.R * nrhs;
-    hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.U[e_top]->as<float2>(), n);
+    hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.U[e_top].as<float2>(), n);
     mark(ST_ZERO);
   }
   // fused form: every level's M2L in one launch, each into its own pair scratch
-  const bool fused = LS.fused.nt > 0;
+  const bool fused = !LS.slot && LS.fused.nt > 0;
   std::vector<const float2*> ym2l(P.hf.size() + 1, S.Y.as<float2>());  // pair outputs per level (last: LF)
   if (fused) {
     std::vector<int> level;
@@ -1923,21 +2304,21 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
     launch_fused(P, S, LS.fused, nrhs, st);
     mark(ST_M2L);
   }
-  for (int e = e_top; e >= 0; --e) {
+  for (int e = e_top; e >= 0 && !LS.slot; --e) {
     HFLevel& H = P.hf[e];
     if (LS.m2l[e].nchunks > 0) {
       if (!fused) {
-        launch_gemm(LS.m2l[e], nrhs, S.F[e]->as<float2>(), S.Y.as<float2>(), st);
+        launch_gemm(LS.m2l[e], nrhs, S.F[e].as<float2>(), S.Y.as<float2>(), st);
         mark(ST_M2L);
       }
       int RN = H.R * nrhs;
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nin * RN, 256)), dim3(256), 0, st, H.red_start.as<int>(),
                          H.red_idx.as<int>(), ym2l[size_t(e)], H.nin, RN, e == e_top ? 0 : 1,
-                         S.U[e]->as<float2>());
+                         S.U[e].as<float2>());
       mark(ST_REDUCE);
     }
-    float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1]->as<float2>();
-    launch_gemm(LS.l2l[e], nrhs, S.U[e]->as<float2>(), S.Y.as<float2>(), st);
+    float2* Uc = e == 0 ? S.ulf.as<float2>() : S.U[e - 1].as<float2>();
+    launch_gemm(LS.l2l[e], nrhs, S.U[e].as<float2>(), S.Y.as<float2>(), st);
     int RNc = H.Rc * nrhs;
     if (H.nchild_in > 0)
       hipLaunchKernelGGL(k_reduce, dim3(nblocks(H.nchild_in * RNc, 256)), dim3(256), 0, st, H.l2l_rs.as<int>(),
@@ -1946,13 +2327,13 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
   }
   // without HF levels nothing has written the LF incoming slots: the LF
   // reduction writes them itself, or they are cleared if it does not run
-  if (e_top < 0 && LS.lf_m2l.nchunks == 0) {
+  if (e_top < 0 && !LS.slot && LS.lf_m2l.nchunks == 0) {
     int64_t n = nleaf * Rl * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.ulf.as<float2>(), n);
     mark(ST_ZERO);
   }
   // LF-M2L
-  if (LS.lf_m2l.nchunks > 0) {
+  if (!LS.slot && LS.lf_m2l.nchunks > 0) {
     if (!fused) {
       launch_gemm(LS.lf_m2l, nrhs, S.flf.as<float2>(), S.Y.as<float2>(), st);
       mark(ST_LF_M2L);
@@ -1963,7 +2344,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
                        S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
-  DFMM_HIP(hipStreamWaitEvent(st, S.join, 0));
+  if (own) DFMM_HIP(hipStreamWaitEvent(st, AS.join, 0));
   if (Rl > 16 * L2T_QMAX) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank too large for L2T"};
   if (nrhs >= 4) {
     const int kc = std::min(nrhs, std::max(1, int((48 << 10) / (sizeof(float2) * Rl))));
@@ -1996,59 +2377,38 @@ void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, c
 
 // ---- stage timer -------------------------------------------------------------------
 bool StageTimer::begin_apply(hipStream_t st) {
-  if (used + kPerApply > pool.size()) return false;
-  DFMM_HIP(hipEventRecord(pool[used], st));
-  stage.push_back(-1);
-  from.push_back(used);
-  last_main = used++;
+  const size_t i = book.begin_apply();
+  if (i == StageBook::kNone) return false;
+  DFMM_HIP(hipEventRecord(pool[i], st));
   return true;
 }
 
 void StageTimer::mark(int st_id, hipStream_t st) {
-  if (used >= pool.size()) return;
-  DFMM_HIP(hipEventRecord(pool[used], st));
-  stage.push_back(st_id);
-  from.push_back(last_main);
-  last_main = used++;
+  const size_t i = book.mark(st_id);
+  if (i != StageBook::kNone) DFMM_HIP(hipEventRecord(pool[i], st));
 }
 
 void StageTimer::side_begin(hipStream_t side) {
-  if (used >= pool.size()) return;
-  DFMM_HIP(hipEventRecord(pool[used], side));
-  stage.push_back(-1);
-  from.push_back(used);
-  side_from = used++;
+  const size_t i = book.side_begin();
+  if (i != StageBook::kNone) DFMM_HIP(hipEventRecord(pool[i], side));
 }
 
 void StageTimer::side_mark(int st_id, hipStream_t side) {
-  if (used >= pool.size()) return;
-  DFMM_HIP(hipEventRecord(pool[used], side));
-  stage.push_back(st_id);
-  from.push_back(side_from);
-  ++used;
+  const size_t i = book.side_mark(st_id);
+  if (i != StageBook::kNone) DFMM_HIP(hipEventRecord(pool[i], side));
 }
 
 void StageTimer::collect(double* ms, int64_t* launches) {
-  for (int i = 0; i < ST_COUNT; ++i) {
-    ms[i] = 0.0;
-    launches[i] = 0;
-  }
-  if (used == 0) return;
   // the events carry no system-scope fence: wait for the device, then read them
-  DFMM_HIP(hipDeviceSynchronize());
-  for (size_t i = 0; i < used; ++i) {
-    if (stage[i] < 0) continue;
+  if (book.used > 0) DFMM_HIP(hipDeviceSynchronize());
+  book.collect(ms, launches, ST_COUNT, [&](size_t a, size_t b) {
     float t = 0.f;
-    DFMM_HIP(hipEventElapsedTime(&t, pool[from[i]], pool[i]));
-    ms[stage[i]] += t;
-    launches[stage[i]] += 1;
-  }
-  used = 0;
-  stage.clear();
-  from.clear();
+    DFMM_HIP(hipEventElapsedTime(&t, pool[a], pool[b]));
+    return t;
+  });
 }
 
-StageTimer::StageTimer(int applies) {
+StageTimer::StageTimer(int applies) : book(size_t(applies) * kPerApply, kPerApply) {
   pool.resize(size_t(applies) * kPerApply);
   // timing-only events: without the system-scope release fence, recording one
   // does not write back the L2 between the launches it separates

@@ -6,10 +6,13 @@
 #include <cstdint>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/dfmm.h"
+#include "stagebook.hpp"
+#include "workspace.hpp"
 
 namespace dfmm {
 
@@ -117,7 +120,44 @@ struct GGemm {
   DevBuf vsrc;               // int32[nvec][T]
   DevBuf vdst;               // int32[nvec]
   std::vector<int32_t> v0_h; // host copy of v0 (work chunking)
+  std::vector<int64_t> aoff_h;  // host copy of aoff, per operator index
+  std::vector<int32_t> kpk_h;   // packed K of each operator index (split doubling included)
+  std::vector<double> opflops;  // 8 r_out r_in of each operator index (unpadded ranks)
 };
+
+// ---- slot-form GEMM (many right-hand sides) ------------------------------------
+// Every output vector (a "group": an out-slot for M2M, an in-slot or a leaf for
+// the downward pass) sums its own terms in a fixed order,
+//   Y[g] = sum_t A_kind[op_t] X_kind[src_t],
+// with float64 sums across terms, so no pair outputs are stored and no
+// reduction pass runs.  A term is one pair of the pair form: a child of an M2M
+// slot, an M2L pair or a parent wedge of an L2L slot.  Kind 0 / 1 selects one of
+// two (operator array, source vectors) pairs, so a level's M2L pairs (kind 0)
+// and its L2L terms (kind 1) are summed by one launch into its incoming slots.
+struct SlotTerm {
+  int32_t dst, op, src, kind;
+};
+struct SlotGemm {
+  int M = 0;                 // row stride of the output vectors (padded rank)
+  int Kmax = 8;              // largest packed K of any term (LDS column length)
+  int64_t ngroups = 0, nterms = 0;
+  int max_terms = 0;
+  double flops[2] = {0, 0};  // 8 r_dst r_src per term and rhs by kind (unpadded ranks)
+  DevBuf order;              // int32[ngroups]: launch order, groups with more terms first
+  DevBuf t0;                 // int32[ngroups + 1]: term range of each group
+  DevBuf gm;                 // int32[ngroups]: padded rows M_g of the group's operators
+  DevBuf terms;              // int32[nterms][4]: (operator float4 offset, source vector,
+                             //   packed K | split << 12 | kind << 14, 0)
+};
+// Host view of one kind's operators: float4 offset and packed K (split doubling
+// included) of every operator index, and the split factor.
+struct SlotKind {
+  const GGemm* G = nullptr;  // aoff_h, kpk_h and opflops of the operators (null: no terms of this kind)
+  int split = 1;
+};
+// Term lists -> device tables; terms of a group keep the order given.
+void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int32_t>& gM,
+                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2]);
 
 // Pack an M x K complex matrix (row-major, interleaved float64) into the
 // fragment order read by the GEMM kernel.
@@ -151,6 +191,8 @@ struct HFLevel {
   GGemm m2l;           // pair outputs <- source out-slots, grouped by offset
   DevBuf red_start;    // int32[nin + 1]: CSR of pair outputs per in-slot
   DevBuf red_idx;      // int32[npairs]
+  SlotGemm up;         // slot form of M2M: out-slots <- children
+  SlotGemm down;       // slot form of M2L + L2L: in-slots <- M2L pairs, parent wedges
 };
 
 struct LFLevel {
@@ -164,6 +206,7 @@ struct LFLevel {
   DevBuf W;            // float2[N][R]: L2T weights sum_p G(x_j, c + a_p) D_LF[q][p]
   GGemm m2l;
   DevBuf red_start, red_idx;
+  SlotGemm down;       // slot form of LF-M2L + L2L into the leaves
 };
 
 // Octree with one table per level, boxes in Morton order (host copy).
@@ -226,18 +269,14 @@ enum { ST_PERMUTE = 0, ST_S2M, ST_M2M, ST_M2L, ST_REDUCE, ST_L2L, ST_LF_M2L, ST_
 struct StageTimer {
   static constexpr size_t kPerApply = 64;
   std::vector<hipEvent_t> pool;
-  std::vector<int> stage;           // stage of the interval that ends at each event (-1: none)
-  std::vector<size_t> from;         // the event where that interval starts
-  size_t used = 0;
-  size_t last_main = 0;             // latest event on the apply stream
-  size_t side_from = 0;             // start event of the open side-stream interval
+  StageBook book;                   // which event closes which stage interval
   explicit StageTimer(int applies);
   ~StageTimer();
   bool begin_apply(hipStream_t st);
   void mark(int stage, hipStream_t st);            // interval since the previous apply-stream event
   void side_begin(hipStream_t side);               // opens an interval on the side stream
   void side_mark(int stage, hipStream_t side);     // closes it
-  void collect(double* ms, int64_t* launches);  // sums per stage, then resets
+  void collect(double* ms, int64_t* launches);  // sums per stage (ST_COUNT entries), then resets
 };
 // The requests of one apply: batch columns k0[r] .. k0[r + 1] - 1 (the last
 // request up to nrhs) are request r's right-hand sides, read from f[r] and
@@ -250,8 +289,14 @@ struct ReqTable {
   int k0[kMaxBatch];
   int n;
 };
-void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st);
+// ws: the caller's workspace of ws_bytes (>= workspace_bytes(P, nrhs); everything
+// then runs on st, and calls may overlap) or null (the plan-owned workspace, the
+// near field on the plan's second stream).  existing_only: use only what an
+// earlier apply with this nrhs prepared (no allocation, no tuning).
+void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void* ws, size_t ws_bytes,
+               bool existing_only);
 size_t workspace_bytes(const dfmm_plan_s& P, int nrhs);
+size_t plan_device_bytes(const dfmm_plan_s& P);
 void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT);
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                 const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);

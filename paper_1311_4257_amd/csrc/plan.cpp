@@ -171,9 +171,70 @@ void to_half_ops(std::vector<float>& A, int64_t nops, int64_t stride, int prec, 
   });
 }
 
-namespace {
+void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int32_t>& gM,
+                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2]) {
+  S.M = M;
+  S.ngroups = ngroups;
+  S.nterms = int64_t(terms.size());
+  S.flops[0] = S.flops[1] = 0.0;
+  // terms grouped by destination, each group in the order given
+  std::vector<int32_t> cnt(size_t(ngroups) + 1, 0);
+  for (const SlotTerm& t : terms) {
+    if (t.dst < 0 || t.dst >= ngroups) throw Error{DFMM_EINVAL, "slot term outside its launch"};
+    ++cnt[size_t(t.dst) + 1];
+  }
+  for (int64_t g = 0; g < ngroups; ++g) cnt[size_t(g) + 1] += cnt[size_t(g)];
+  std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1), tab(size_t(4) * terms.size());
+  int kmax = 8;
+  for (const SlotTerm& t : terms) {
+    const SlotKind& k = kinds[t.kind];
+    if (!k.G) throw Error{DFMM_EINVAL, "slot term of a kind without operators"};
+    const int64_t aoff = k.G->aoff_h[size_t(t.op)];
+    const int kp = k.G->kpk_h[size_t(t.op)];
+    if (aoff > INT32_MAX || kp >= (1 << 12) || k.split > 3)
+      throw Error{DFMM_EUNSUPPORTED, "operator table too large for the slot-form GEMM"};
+    int32_t* e = &tab[size_t(4) * size_t(pos[size_t(t.dst)]++)];
+    e[0] = int32_t(aoff);
+    e[1] = t.src;
+    e[2] = kp | (k.split << 12) | (t.kind << 14);
+    e[3] = 0;
+    kmax = std::max(kmax, kp);
+    S.flops[t.kind] += k.G->opflops[size_t(t.op)];
+  }
+  S.Kmax = kmax;
+  S.max_terms = 0;
+  std::vector<int32_t> order(static_cast<size_t>(ngroups));
+  for (int64_t g = 0; g < ngroups; ++g) {
+    order[size_t(g)] = int32_t(g);
+    S.max_terms = std::max(S.max_terms, cnt[size_t(g) + 1] - cnt[size_t(g)]);
+  }
+  // most terms first: the longest groups start early and the launch ends on short ones
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return cnt[size_t(a) + 1] - cnt[size_t(a)] > cnt[size_t(b) + 1] - cnt[size_t(b)];
+  });
+  S.order.upload(order);
+  S.t0.upload(cnt);
+  S.gm.upload(gM);
+  S.terms.upload(tab);
+}
 
-}  // namespace
+// Device bytes held by a plan (every table and operator array; the apply
+// workspace is separate).
+static size_t gg_bytes(const GGemm& G) {
+  return G.aexp.bytes + G.A.bytes + G.aoff.bytes + G.gmk.bytes + G.ops.bytes + G.v0.bytes + G.vsrc.bytes +
+         G.vdst.bytes;
+}
+static size_t slot_bytes(const SlotGemm& S) { return S.order.bytes + S.t0.bytes + S.gm.bytes + S.terms.bytes; }
+size_t plan_device_bytes(const dfmm_plan_s& P) {
+  size_t b = P.pthi.bytes + P.ptlo.bytes + P.perm_d.bytes + P.leaf_start.bytes + P.leaf_of.bytes +
+             P.leaf_center.bytes + P.near_start.bytes + P.near_src.bytes;
+  b += P.lf.a.bytes + P.lf.a64.bytes + P.lf.V.bytes + P.lf.W.bytes + gg_bytes(P.lf.m2l) + P.lf.red_start.bytes +
+       P.lf.red_idx.bytes + slot_bytes(P.lf.down);
+  for (const HFLevel& H : P.hf)
+    b += gg_bytes(H.m2m) + gg_bytes(H.l2l) + gg_bytes(H.m2l) + H.m2m_rs.bytes + H.m2m_ri.bytes + H.l2l_rs.bytes +
+         H.l2l_ri.bytes + H.red_start.bytes + H.red_idx.bytes + slot_bytes(H.up) + slot_bytes(H.down);
+  return b;
+}
 
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                 const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx) {
@@ -291,11 +352,20 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   auto build_m2l = [&](const std::vector<PairRec>& pr, double w, int R,
                        const std::vector<const Skel*>& skin, const SlotIndex* osl, const SlotIndex* isl,
                        int64_t nin, GGemm& G, DevBuf& rs, DevBuf& ri, int64_t& ngroups, double& flops,
-                       int split) {
-    // algorithmic bytes of the launch: each group's operator once (complex64,
-    // unpadded), each pair's source vector read and its output written once
+                       int split, std::vector<SlotTerm>& sterms) {
+    // algorithmic bytes: each group's operator once (complex64, unpadded), each
+    // source slot read once and each target slot read and written once, per rhs
     double& bytes_op = info.bytes_m2l_op;
     double& bytes_vec = info.bytes_m2l_vec;
+    {
+      std::set<std::pair<int64_t, int>> srcs, tgts;
+      for (const PairRec& r : pr) {
+        srcs.insert({r.A, r.dout});
+        tgts.insert({r.B, r.din});
+      }
+      for (const auto& s : srcs) bytes_vec += 8.0 * skin[s.second < 0 ? 0 : s.second]->r;
+      for (const auto& t : tgts) bytes_vec += 16.0 * skin[t.second < 0 ? 0 : t.second]->r;
+    }
     std::map<std::tuple<int64_t, int64_t, int64_t>, std::vector<int64_t>> g;
     for (size_t i = 0; i < pr.size(); ++i) g[{pr[i].nx, pr[i].ny, pr[i].nz}].push_back(int64_t(i));
     ngroups = int64_t(g.size());
@@ -315,8 +385,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
         const PairRec& r = pr[i];
         pos_of[i] = int32_t(vsrc.size());
         vsrc.push_back(int32_t(osl ? osl->at(r.A, r.dout) : r.A));
+        sterms.push_back({int32_t(isl ? isl->at(r.B, r.din) : r.B), int32_t(keys.size() - 1), vsrc.back(), 0});
         flops += 8.0 * skin[r.din < 0 ? 0 : r.din]->r * skin[r.dout < 0 ? 0 : r.dout]->r;
-        bytes_vec += 8.0 * (skin[r.din < 0 ? 0 : r.din]->r + skin[r.dout < 0 ? 0 : r.dout]->r);
       }
       v0.push_back(int32_t(vsrc.size()));
     }
@@ -389,15 +459,26 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     G.v0_h = v0;
     G.vsrc.upload(vsrc);
     G.vdst.upload(vdst);
+    G.aoff_h = aoff;
+    G.kpk_h.resize(size_t(ngroups));
+    G.opflops.resize(size_t(ngroups));
+    for (int64_t gi = 0; gi < ngroups; ++gi) {
+      G.kpk_h[size_t(gi)] = kpad(gmk[2 * gi + 1] / split, P.prec) * split;
+      const PairRec& r = pr[rep[gi]];
+      G.opflops[size_t(gi)] = 8.0 * skin[r.din < 0 ? 0 : r.din]->r * skin[r.dout < 0 ? 0 : r.dout]->r;
+    }
     rs.upload(rstart);
     ri.upload(ridx);
   };
 
+  // slot-form term lists: M2L pairs and L2L terms of the leaves and of every HF level
+  std::vector<SlotTerm> lf_terms;
+  std::vector<std::vector<SlotTerm>> down_terms(size_t(e_top + 1)), up_terms(size_t(e_top + 1));
   {
     std::vector<const Skel*> s1{&sl};
     P.lf.npairs = int64_t(pairs[D].size());
     build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nleaf, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
-              P.lf.ngroups, P.lf.flops, 1);
+              P.lf.ngroups, P.lf.flops, 1, lf_terms);
     info.flops_m2l_lf = P.lf.flops;
     info.flops_m2l_level[D] = P.lf.flops;
   }
@@ -445,6 +526,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     for (auto& s : OS[l].list) dir_used[s.second] = 1;
     for (auto& s : IS[l].list) dir_used[s.second] = 1;
     std::vector<int32_t> op_ms(size_t(ndir) * 8, 8), op_mc(size_t(ndir) * 8, 8);  // padded ranks per op
+    std::vector<double> op_fl(size_t(ndir) * 8, 0.0);  // 8 r_s r_c per op (unpadded)
     double wc = double(w) / 2.0;
     parallel_for(int64_t(ndir) * 8, [&](int64_t id) {
       int d = int(id / 8), o = int(id % 8);
@@ -461,6 +543,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       const int Ms = pad8(s.r), Mc = pad8(c.r);
       op_ms[id] = Ms;
       op_mc[id] = Mc;
+      op_fl[id] = 8.0 * s.r * c.r;
       const int Kpu = kpad(Mc, P.prec), Kpd = kpad(Ms, P.prec);
       std::vector<double> up(size_t(2) * Ms * Kpu, 0.0), dn(size_t(2) * Mc * Kpd, 0.0);
       for (int p = 0; p < s.r; ++p)
@@ -535,6 +618,10 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       G.v0_h = v0;
       G.vsrc.upload(vsrc);
       G.vdst.upload(vdst);
+      G.aoff_h = aoff;
+      G.kpk_h.resize(size_t(nops));
+      for (int64_t op = 0; op < nops; ++op) G.kpk_h[size_t(op)] = kpad(opK[size_t(op)], P.prec) * hf_split;
+      G.opflops = op_fl;
       rs.upload(rstart);
       ri.upload(ridx);
       npairs = G.nvec;
@@ -546,6 +633,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
         for (int64_t c = L.cbeg[b]; c < L.cend[b]; ++c) {
           int32_t src = int32_t(e == 0 ? c : OS[l + 1].at(c, direction_down(d, w)));
           by_op[size_t(d) * 8 + C.octant[c]].push_back({src, int32_t(i)});
+          up_terms[size_t(e)].push_back({int32_t(i), int32_t(size_t(d) * 8 + C.octant[c]), src, 0});
         }
       }
       if (P.prec) {
@@ -565,7 +653,10 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           int64_t p = C.parent[c];
           for (int d = 0; d < 6; ++d) {
             int64_t sidx = IS[l].at(p, d);
-            if (sidx >= 0) by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(c)});
+            if (sidx >= 0) {
+              by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(c)});
+              lf_terms.push_back({int32_t(c), int32_t(size_t(d) * 8 + C.octant[c]), int32_t(sidx), 1});
+            }
           }
         }
       } else {
@@ -580,7 +671,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             for (int dj = 0; dj < 2; ++dj) {
               int d = int((face * w + 2 * ci + di) * w + 2 * cj + dj);
               int64_t sidx = IS[l].at(p, d);
-              if (sidx >= 0) by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(i)});
+              if (sidx >= 0) {
+                by_op[size_t(d) * 8 + C.octant[c]].push_back({int32_t(sidx), int32_t(i)});
+                down_terms[size_t(e - 1)].push_back({int32_t(i), int32_t(size_t(d) * 8 + C.octant[c]),
+                                                     int32_t(sidx), 1});
+              }
             }
         }
       }
@@ -597,10 +692,32 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<const Skel*> sp;
     for (auto& s : sk) sp.push_back(&s);
     build_m2l(pairs[l], double(w), H.R, sp, &OS[l], &IS[l], H.nin, H.m2l, H.red_start, H.red_idx, H.ngroups,
-              H.flops, hf_split);
+              H.flops, hf_split, down_terms[size_t(e)]);
     info.flops_m2l_hf += H.flops;
     info.flops_m2l_level[l] = H.flops;
   }
+  // ---- slot-form tables (fast float32 plans; used from 16 right-hand sides) -------
+  if (!P.precise && P.prec == DFMM_PREC_FP32) {
+    auto slot_m = [&](int l, int64_t n, bool in) {  // padded rows of each slot's skeleton
+      std::vector<int32_t> gm(static_cast<size_t>(n));
+      const int e = D - 1 - l;
+      for (int64_t i = 0; i < n; ++i)
+        gm[size_t(i)] = pad8(ops.hf[e][(in ? IS[l] : OS[l]).list[size_t(i)].second].r);
+      return gm;
+    };
+    for (int e = 0; e <= e_top; ++e) {
+      HFLevel& H = P.hf[size_t(e)];
+      const int l = H.l;
+      SlotKind up[2] = {{&H.m2m, hf_split}, {nullptr, 1}};
+      build_slot_gemm(H.up, H.R, H.nout, slot_m(l, H.nout, false), up_terms[size_t(e)], up);
+      SlotKind dn[2] = {{&H.m2l, hf_split}, {e < e_top ? &P.hf[size_t(e + 1)].l2l : nullptr, hf_split}};
+      build_slot_gemm(H.down, H.R, H.nin, slot_m(l, H.nin, true), down_terms[size_t(e)], dn);
+    }
+    SlotKind dn[2] = {{&P.lf.m2l, 1}, {e_top >= 0 ? &P.hf[0].l2l : nullptr, hf_split}};
+    build_slot_gemm(P.lf.down, Rlf, nleaf, std::vector<int32_t>(size_t(nleaf), Rlf), lf_terms, dn);
+  }
+
+  info.device_bytes = int64_t(plan_device_bytes(P));
   auto t1 = std::chrono::steady_clock::now();
   P.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
   info.plan_seconds = P.plan_seconds;

@@ -37,13 +37,15 @@ ABI_FUNCTIONS = [
     "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
     "dfmm_opset_set", "dfmm_opset_get", "dfmm_opset_info", "dfmm_opset_save", "dfmm_opset_load",
     "dfmm_opset_destroy", "dfmm_options_default", "dfmm_plan", "dfmm_plan_ex", "dfmm_apply",
-    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_destroy", "dfmm_plan_info", "dfmm_export", "dfmm_set_timing", "dfmm_stage_times",
+    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_destroy", "dfmm_plan_info", "dfmm_export",
+    "dfmm_set_timing", "dfmm_stage_times",
 ]
 
 
 class Options(C.Structure):
     _fields_ = [("eps", C.c_double), ("opset", C.c_void_p), ("cache_dir", C.c_char_p),
-                ("device", C.c_int), ("precision", C.c_int), ("reserved", C.c_int * 6)]
+                ("device", C.c_int), ("precision", C.c_int), ("leaf_width", C.c_double),
+                ("tol_factor", C.c_double), ("hbm_budget_bytes", C.c_uint64), ("reserved", C.c_int * 4)]
 
 
 class Info(C.Structure):
@@ -77,6 +79,7 @@ _sig = {
     "dfmm_apply_batch": (C.c_int, [_P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_int), C.c_void_p]),
     "dfmm_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
+    "dfmm_apply_ws": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dfmm_destroy": (None, [_P]),
     "dfmm_plan_info": (C.c_int, [_P, C.POINTER(Info)]),
     "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -173,7 +176,8 @@ class Plan:
     """A resident plan for one point set: dfmm_plan / dfmm_plan_ex."""
 
     def __init__(self, points, K: float, eps: float = 1e-4, opset: OpSet | None = None,
-                 cache_dir: str | None = None, device: int = -1, precision: int = 0):
+                 cache_dir: str | None = None, device: int = -1, precision: int = 0,
+                 leaf_width: float = 0.0, tol_factor: float = 0.0, hbm_budget_bytes: int = 0):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2 or pts.shape[1] != 3:
             raise ValueError("points must be (N, 3)")
@@ -185,6 +189,9 @@ class Plan:
         opt.cache_dir = self._cache
         opt.device = device
         opt.precision = precision
+        opt.leaf_width = leaf_width
+        opt.tol_factor = tol_factor
+        opt.hbm_budget_bytes = hbm_budget_bytes
         h = _P()
         _check(_lib.dfmm_plan_ex(_dptr(pts), pts.shape[0], float(K), C.byref(opt), C.byref(h)))
         self._h = h
@@ -208,6 +215,28 @@ class Plan:
         _check(_lib.dfmm_apply(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u.data_ptr()),
                                f2.shape[0], C.c_void_p(stream.cuda_stream)))
         return u.reshape(-1) if one else u
+
+    def apply_ws(self, f, u, ws, stream=None):
+        """dfmm_apply_ws: u = A f with the caller's workspace ws (a CUDA tensor of at
+        least workspace_bytes(nrhs) bytes, 256-byte aligned); everything runs on
+        ``stream`` (default: the current stream)."""
+        import torch
+
+        one = f.dim() == 1
+        f2 = f.reshape(1, -1) if one else f
+        if f2.dtype != torch.complex64 or not f2.is_cuda or not f2.is_contiguous() or f2.shape[1] != self.N:
+            raise ValueError("f must be a contiguous (nrhs, N) complex64 CUDA tensor")
+        u2 = u.reshape(f2.shape)
+        if u2.dtype != torch.complex64 or not u2.is_contiguous():
+            raise ValueError("u must be a contiguous complex64 tensor shaped like f")
+        if not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("ws must be a contiguous CUDA tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(f2.device)
+        nbytes = ws.numel() * ws.element_size()
+        _check(_lib.dfmm_apply_ws(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u2.data_ptr()), f2.shape[0],
+                                  C.c_void_p(ws.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream)))
+        return u
 
     def apply_batch(self, fs, us, stream=None):
         """One pass over several requests: us[r] = A fs[r] for (nrhs_r, N) complex64

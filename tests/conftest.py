@@ -13,6 +13,22 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
 
 
+@pytest.fixture(scope="session", autouse=True)
+def _one_blas_thread_per_matmul():
+    """The oracle's passes issue many small matrix products; BLAS worker threads
+    only add synchronization to them (and oversubscribe the host when other
+    jobs run), so the tests run BLAS single-threaded.  Building an operator set
+    that is not cached (large pivoted QRs) raises the limit again, see
+    oracle.cache."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        yield
+        return
+    with threadpool_limits(limits=1, user_api="blas"):
+        yield
+
+
 def gpu_available() -> bool:
     try:
         import torch

@@ -52,12 +52,44 @@ def test_bad_inputs_rejected_on_the_host():
         dfmm.Plan(good, 4.0, precision=7)           # unknown GEMM precision
     with pytest.raises(dfmm.DfmmError, match="EINVAL"):
         dfmm.Plan(good, 4.0, eps=1e-6, precision=dfmm.PREC_FP16X3)  # split products need eps >= 1e-5
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 4.0, leaf_width=0.25)       # only the uniform leaf level of width 1/2
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, tol_factor=2.0)        # tau = tol_factor eps needs tol_factor in (0, 1]
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, tol_factor=-0.1)
     lib = dfmm._lib
     n = ctypes.c_size_t()
     assert lib.dfmm_workspace_bytes(None, 1, ctypes.byref(n)) == -1
+    assert lib.dfmm_apply_ws(None, None, None, 1, None, 0, None) == -1
     arr = (ctypes.c_void_p * 1)(None)
     cnt = (ctypes.c_int * 1)(1)
     assert lib.dfmm_apply_batch(None, 1, arr, arr, cnt, None) == -1
+
+
+def test_hbm_budget_refuses_a_plan_before_any_device_call():
+    """hbm_budget_bytes: a plan that cannot fit is refused with DFMM_ENOMEM by a
+    host-side check (this runs on a machine without a GPU, so a device call
+    would fail with DFMM_EDEVICE instead); the message names both sizes."""
+    from paper_1311_4257_amd import dfmm
+    from paper_1311_4257_amd.workloads import sphere_points
+
+    pts = sphere_points(1000, 4.0, seed=1)
+    with pytest.raises(dfmm.DfmmError, match="ENOMEM") as ei:
+        dfmm.Plan(pts, 4.0, hbm_budget_bytes=1000)
+    assert "1000" in str(ei.value) and "hbm_budget_bytes" in str(ei.value)
+    if not _gpu():   # within the budget the plan proceeds to the device
+        with pytest.raises(dfmm.DfmmError, match="EDEVICE|ENOMEM"):
+            dfmm.Plan(pts, 4.0, hbm_budget_bytes=1 << 40)
+
+
+def _gpu() -> bool:
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
 
 
 def test_library_skeletons_meet_eq2_on_fresh_samples(tmp_path):

@@ -283,11 +283,12 @@ def test_sphere16_full_size_sampled_targets(cuda, eps):
 
 def test_ellipsoid32_nrhs32_sampled_targets(cuda):
     """4:2:1 ellipsoid, K = 32, N = 262,144 area-uniform points, 32 right-hand sides in
-    one apply, eps = 1e-4; 512 sampled targets x 32 rhs against the direct sum."""
+    one apply, eps = 1e-4; 2,048 sampled targets (seed 303) x 32 rhs against the
+    direct sum: the benchmark's workload in its launch configuration."""
     pts, f, cfg = workloads.make_config("ellipsoid32")
     plan = _dfmm().Plan(pts, cfg["K"], eps=cfg["eps"], cache_dir=CACHE, device=0)
     u = plan.apply(_to_dev(f, cuda)).cpu().numpy()
-    tg = workloads.sample_targets(len(pts), 512, cfg["check_seed"])
+    tg = workloads.sample_targets(len(pts), cfg["n_check"], cfg["check_seed"])
     ref = direct_sum(pts, f, tg)
     err = rel_l2(u[:, tg], ref)
     worst = max(rel_l2(u[k, tg], ref[k]) for k in range(f.shape[0]))
