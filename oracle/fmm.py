@@ -21,6 +21,15 @@ the pass is, in the order of Algorithm 1 (complex128 throughout):
 
 The near-field sum is not written in Algorithm 1; without it the matvec of
 Eq. 1 would miss every pair of adjacent leaves, so it is added here.
+
+Adaptive trees (leaves on several low-frequency levels, Section 2.2): the
+leaf S2M becomes S2M at every leaf followed by LF-M2M over the low-frequency
+boxes in postorder (children's equivalent densities to the parent's check
+potentials), and the low-frequency part of the downward pass runs level by
+level in preorder: LF-M2L over the level's interaction lists, then LF-L2L into
+the children of non-leaf boxes or L2T at the leaves (Algorithm 1, last loop);
+each low-frequency width has its own non-directional skeleton (``deep``, see
+oracle.adaptive) and the near field follows tree.adaptive_near_lists.
 """
 from __future__ import annotations
 
@@ -35,12 +44,14 @@ def _slot_index(slots: np.ndarray) -> dict:
     return {(int(b), int(d)): i for i, (b, d) in enumerate(slots.tolist())}
 
 
-def fmm_apply(st: Structure, ops: OpSet, f: np.ndarray, stages: dict | None = None) -> np.ndarray:
+def fmm_apply(st: Structure, ops: OpSet, f: np.ndarray, stages: dict | None = None, deep=None) -> np.ndarray:
     """Approximate u = A f for densities f of shape (nrhs, N) (or (N,)), original order.
 
-    ``stages`` (optional dict) receives the intermediate data: 'f_lf', 'u_lf',
-    and per HF level l: ('f', l), ('u', l) arrays indexed like st.out_slots[l] /
-    st.in_slots[l], each of shape (nslots, r, nrhs) (complex128, Morton order).
+    ``stages`` (optional dict) receives the intermediate data: 'f_lf', 'u_lf'
+    (width 1/2), and per HF level l: ('f', l), ('u', l) arrays indexed like
+    st.out_slots[l] / st.in_slots[l], each of shape (nslots, r, nrhs)
+    (complex128, Morton order).  ``deep``: the skeletons of the low-frequency
+    widths 1/4, 1/8, ... of an adaptive tree (oracle.adaptive.deep_lf_skeletons).
     """
     tree = st.tree
     if st.w_top > ops.w_hi:
@@ -51,18 +62,36 @@ def fmm_apply(st: Structure, ops: OpSet, f: np.ndarray, stages: dict | None = No
     nrhs = F.shape[0]
     fs = F[:, tree.perm].T                     # (N, nrhs) sorted order
     D = tree.D
-    leaves = tree.levels[D]
-    cl = tree.centers(D)
-    nleaf = len(cl)
+    Dm = tree.Dmax
+    if Dm > D and (deep is None or len(deep) < Dm - D):
+        raise ValueError("an adaptive tree needs the skeletons of its deeper low-frequency widths")
+    lfsk = {l: (ops.lf if l == D else deep[l - D - 1]) for l in range(D, Dm + 1)}
     lf = ops.lf
     r_lf = lf.r
 
-    # ---- leaf S2M -----------------------------------------------------------
-    f_lf = np.zeros((nleaf, r_lf, nrhs), dtype=np.complex128)
-    for b in range(nleaf):
-        s, e = leaves.start[b], leaves.end[b]
-        chk = green(cl[b] + lf.a, tree.points[s:e]) @ fs[s:e]
-        f_lf[b] = lf.D @ chk
+    # ---- S2M at the leaves and LF-M2M, postorder over the LF boxes ----------
+    flf = {}
+    for l in range(Dm, D - 1, -1):
+        lv = tree.levels[l]
+        sk = lfsk[l]
+        cen = tree.centers(l)
+        if l < Dm:
+            kids = children(tree, l)
+            cc = tree.centers(l + 1)
+            skc = lfsk[l + 1]
+        out = np.zeros((len(cen), sk.r, nrhs), dtype=np.complex128)
+        for b in range(len(cen)):
+            if lv.leaf[b]:
+                s, e = lv.start[b], lv.end[b]
+                chk = green(cen[b] + sk.a, tree.points[s:e]) @ fs[s:e]
+            else:
+                chk = np.zeros((sk.r, nrhs), dtype=np.complex128)
+                for c in kids[b]:
+                    chk += green(cen[b] + sk.a, cc[c] + skc.b) @ flf[l + 1][c]
+            out[b] = sk.D @ chk
+        flf[l] = out
+    f_lf = flf[D]
+    nleaf = len(tree.levels[D].coords)     # boxes of width 1/2
 
     hf_levels = list(range(st.hf_levels[0], D)) if st.hf_levels else []
     fdir, udir = {}, {}
@@ -137,30 +166,52 @@ def fmm_apply(st: Structure, ops: OpSet, f: np.ndarray, stages: dict | None = No
         if l + 1 < D:
             udir[l + 1] = uc
 
-    # ---- LF-M2L -------------------------------------------------------------
-    pl = st.lists[D]
-    if len(pl.tgt):
-        keys, grp = np.unique(pl.offset, axis=0, return_inverse=True)
-        grp = grp.reshape(-1)
-        for g, n in enumerate(keys):
-            sel = np.nonzero(grp == g)[0]
-            T = green(lf.b, n * 0.5 + lf.b)
-            np.add.at(u_lf, pl.tgt[sel], T @ f_lf[pl.src[sel]])
-    if stages is not None:
-        stages["f_lf"] = f_lf
-        stages["u_lf"] = u_lf
-
-    # ---- leaf L2T and near field -------------------------------------------
+    # ---- LF-M2L, then LF-L2L or L2T, preorder over the LF levels -------------
     us = np.zeros_like(fs)
-    for b in range(nleaf):
-        s, e = leaves.start[b], leaves.end[b]
-        g = lf.D.T @ u_lf[b]
-        us[s:e] += green(tree.points[s:e], cl[b] + lf.a) @ g
-    nb = st.near
-    for B, A in zip(nb.tgt.tolist(), nb.src.tolist()):
-        s, e = leaves.start[B], leaves.end[B]
-        s2, e2 = leaves.start[A], leaves.end[A]
-        us[s:e] += green(tree.points[s:e], tree.points[s2:e2]) @ fs[s2:e2]
+    ulf = {D: u_lf}
+    for l in range(D, Dm + 1):
+        lv = tree.levels[l]
+        sk = lfsk[l]
+        w = tree.width(l)
+        u = ulf[l]
+        pl = st.lists[l]
+        if len(pl.tgt):
+            keys, grp = np.unique(pl.offset, axis=0, return_inverse=True)
+            grp = grp.reshape(-1)
+            for g, n in enumerate(keys):
+                sel = np.nonzero(grp == g)[0]
+                T = green(sk.b, n * w + sk.b)
+                np.add.at(u, pl.tgt[sel], T @ flf[l][pl.src[sel]])
+        if l == D and stages is not None:
+            stages["f_lf"] = f_lf
+            stages["u_lf"] = u
+        cen = tree.centers(l)
+        if l < Dm:
+            kids = children(tree, l)
+            cc = tree.centers(l + 1)
+            skc = lfsk[l + 1]
+            ulf[l + 1] = np.zeros((len(cc), skc.r, nrhs), dtype=np.complex128)
+        for b in range(len(cen)):
+            g = sk.D.T @ u[b]                   # incoming equivalent charges at the check points a
+            if lv.leaf[b]:
+                s, e = lv.start[b], lv.end[b]
+                us[s:e] += green(tree.points[s:e], cen[b] + sk.a) @ g
+            else:
+                for c in kids[b]:
+                    ulf[l + 1][c] += green(cc[c] + skc.b, cen[b] + sk.a) @ g
+
+    # ---- near field ------------------------------------------------------------
+    if isinstance(st.near, list):             # adaptive tree: ((l_B, B), (l_A, A)) leaf pairs
+        for (lb, B), (la, A) in st.near:
+            s, e = tree.levels[lb].start[B], tree.levels[lb].end[B]
+            s2, e2 = tree.levels[la].start[A], tree.levels[la].end[A]
+            us[s:e] += green(tree.points[s:e], tree.points[s2:e2]) @ fs[s2:e2]
+    else:
+        leaves = tree.levels[D]
+        for B, A in zip(st.near.tgt.tolist(), st.near.src.tolist()):
+            s, e = leaves.start[B], leaves.end[B]
+            s2, e2 = leaves.start[A], leaves.end[A]
+            us[s:e] += green(tree.points[s:e], tree.points[s2:e2]) @ fs[s2:e2]
 
     u = np.empty_like(F)
     u[:, tree.perm] = us.T

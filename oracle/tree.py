@@ -119,19 +119,29 @@ class Level:
     parent: np.ndarray          # (nb,) index at level l-1 (-1 at the root)
     octant: np.ndarray          # (nb,) child octant within the parent
     index: dict = field(default_factory=dict)   # coords tuple -> box index
+    leaf: np.ndarray = None     # (nb,) bool: the box has no children
 
 
 @dataclass
 class Tree:
     K: float
-    D: int
+    D: int                      # level of width 1/2 (the first low-frequency level)
     points: np.ndarray          # sorted points (N, 3)
     perm: np.ndarray            # perm[s] = original index of sorted point s
-    levels: list
+    levels: list                # levels 0 .. Dmax
+    leaf_max: int = 0           # adaptive split threshold (0: uniform tree, leaves at level D)
 
     @property
     def leaves(self) -> Level:
         return self.levels[self.D]
+
+    @property
+    def Dmax(self) -> int:
+        return len(self.levels) - 1
+
+    def leaf_boxes(self):
+        """(level, box) of every leaf, levels ascending, Morton order within a level."""
+        return [(l, b) for l in range(self.D, self.Dmax + 1) for b in np.nonzero(self.levels[l].leaf)[0].tolist()]
 
     def width(self, l: int) -> float:
         return self.K / 2 ** l
@@ -155,35 +165,59 @@ def check_points(points: np.ndarray, K: float) -> None:
         raise ValueError("point outside |p| <= K/2")
 
 
-def build_tree(points: np.ndarray, K: float) -> Tree:
-    """Morton-sorted octree with leaf width 1/2 and all non-empty boxes per level."""
+def build_tree(points: np.ndarray, K: float, leaf_max: int = 0, extra: int = 3) -> Tree:
+    """Morton-sorted octree with all non-empty boxes per level (Section 2.2).
+
+    Boxes of width >= 1 (high frequency) always split; so do the boxes of width 1
+    into width 1/2.  With leaf_max = 0 the boxes of width 1/2 are the leaves (a
+    uniform tree).  With leaf_max > 0 the low-frequency part is adaptive: a box
+    of width <= 1/2 splits when it holds more than leaf_max points, down to
+    width 2^-(1 + extra) (coincident points cannot be separated further).
+    Points are sorted by the Morton key of their finest-level box, then by
+    original index.
+    """
     check_points(points, K)
     points = np.asarray(points, dtype=np.float64)
     D = int(round(np.log2(2 * K)))
-    ix = leaf_coords(points, K, D)
-    key = morton(ix, D)
+    Dm = D + (extra if leaf_max > 0 else 0)
+    ix = leaf_coords(points, K, Dm)
+    key = morton(ix, Dm)
     perm = np.lexsort((np.arange(len(key)), key))      # by key, then index
     skey = key[perm]
     six = ix[perm]
     levels = []
-    for l in range(D + 1):
-        kl = skey >> (3 * (D - l))
+    split_prev = None
+    for l in range(Dm + 1):
+        kl = skey >> (3 * (Dm - l))
         head = np.ones(len(kl), dtype=bool)
         head[1:] = kl[1:] != kl[:-1]
         start = np.nonzero(head)[0]
         end = np.append(start[1:], len(kl))
-        coords = six[start] >> (D - l)
-        lv = Level(l=l, w=K / 2 ** l, coords=coords, keys=kl[start], start=start,
-                   end=end, parent=np.full(len(start), -1, dtype=np.int64),
-                   octant=np.zeros(len(start), dtype=np.int64))
-        lv.index = {tuple(c): i for i, c in enumerate(coords.tolist())}
+        coords = six[start] >> (Dm - l)
+        keys = kl[start]
+        parent = np.full(len(start), -1, dtype=np.int64)
         if l > 0:
-            up = levels[l - 1]
-            lv.parent = np.searchsorted(up.keys, lv.keys >> 3)
-            o = coords & 1
-            lv.octant = o[:, 0] | (o[:, 1] << 1) | (o[:, 2] << 2)
+            up = levels[l - 1].keys
+            parent = np.minimum(np.searchsorted(up, keys >> 3), len(up) - 1)
+            # boxes whose parent exists and was split
+            keep = (up[parent] == keys >> 3) & split_prev[parent]
+            start, end, coords, keys, parent = start[keep], end[keep], coords[keep], keys[keep], parent[keep]
+        o = coords & 1
+        lv = Level(l=l, w=K / 2 ** l, coords=coords, keys=keys, start=start, end=end, parent=parent,
+                   octant=o[:, 0] | (o[:, 1] << 1) | (o[:, 2] << 2) if l > 0 else np.zeros(len(start), np.int64))
+        lv.index = {tuple(c): i for i, c in enumerate(coords.tolist())}
+        if l < D:
+            split = np.ones(len(start), dtype=bool)
+        elif l < Dm:
+            split = (end - start) > leaf_max
+        else:
+            split = np.zeros(len(start), dtype=bool)
+        lv.leaf = ~split
         levels.append(lv)
-    return Tree(K=K, D=D, points=points[perm], perm=perm, levels=levels)
+        split_prev = split
+        if not split.any():
+            break
+    return Tree(K=K, D=D, points=points[perm], perm=perm, levels=levels, leaf_max=leaf_max)
 
 
 # --------------------------------------------------------------------------
@@ -270,7 +304,13 @@ def interaction_lists(tree: Tree, l: int) -> PairList:
 
 
 def near_lists(tree: Tree) -> PairList:
-    """Near-field (P2P) pairs over leaves: all adjacent non-empty leaves, self included."""
+    """Near-field (P2P) pairs over leaves: all adjacent non-empty leaves, self included.
+
+    For a uniform tree: the adjacent leaves of the same level.  For an adaptive
+    tree (leaves on several levels) see adaptive_near_lists.
+    """
+    if tree.Dmax > tree.D:
+        raise ValueError("adaptive tree: use adaptive_near_lists")
     l = tree.D
     lv = tree.levels[l]
     tg, sr = [], []
@@ -284,6 +324,49 @@ def near_lists(tree: Tree) -> PairList:
                     dir_in=np.full(len(tg), -1), dir_out=np.full(len(tg), -1))
 
 
+def ancestor(tree: Tree, l: int, b: int, m: int) -> int:
+    """Index at level m <= l of the ancestor of box b of level l."""
+    while l > m:
+        b = int(tree.levels[l].parent[b])
+        l -= 1
+    return b
+
+
+def adaptive_near_lists(tree: Tree) -> list:
+    """Near-field pairs of an adaptive tree: ((l_B, B), (l_A, A)) for leaves B, A
+    whose boxes at the coarser of their two levels, m = min(l_A, l_B), are
+    adjacent (or equal).  With the interaction lists of every level (children
+    of the parent's near field that are not in the own near field) this covers
+    every ordered pair of leaves exactly once: walking down from the root, the
+    first level at which the two ancestors are not near holds their
+    interaction pair; if there is none up to level m, the pair is here.  (The
+    kernel-independent FMM's W and X lists are these coarse-fine pairs treated
+    through equivalent densities; here they are summed directly.)  Sorted by
+    target (level, box), then source (level, box).
+    """
+    out = []
+    for lb, b in tree.leaf_boxes():
+        cb = tree.levels[lb].coords[b]
+        srcs = []
+        for la in range(tree.D, tree.Dmax + 1):
+            lvA = tree.levels[la]
+            if la <= lb:
+                ca = cb >> (lb - la)                      # B's ancestor at level la
+                for n in near_offsets(0.5):
+                    a = lvA.index.get(tuple((ca + n).tolist()))
+                    if a is not None and lvA.leaf[a]:
+                        srcs.append((la, a))
+            else:
+                # leaves A below level lb whose ancestor at level lb is adjacent to B
+                for a in np.nonzero(lvA.leaf)[0].tolist():
+                    ca = lvA.coords[a] >> (la - lb)
+                    if np.all(np.abs(ca - cb) <= 1):
+                        srcs.append((la, a))
+        for s in sorted(srcs):
+            out.append(((lb, b), s))
+    return out
+
+
 # --------------------------------------------------------------------------
 # the full plan structure
 # --------------------------------------------------------------------------
@@ -291,8 +374,8 @@ def near_lists(tree: Tree) -> PairList:
 @dataclass
 class Structure:
     tree: Tree
-    lists: dict                 # level -> PairList (HF levels and the leaf level)
-    near: PairList              # P2P pairs
+    lists: dict                 # level -> PairList (HF levels and every low-frequency level)
+    near: object                # P2P pairs: PairList (uniform tree) or adaptive_near_lists' list
     hf_levels: list             # HF levels with a non-empty list, top (largest w) first
     out_slots: dict             # level -> sorted array of (box, dir) rows (needed outgoing)
     in_slots: dict              # level -> sorted array of (box, dir) rows (needed incoming)
@@ -302,17 +385,18 @@ class Structure:
         return int(self.tree.width(self.hf_levels[0])) if self.hf_levels else 0
 
 
-def build_structure(points: np.ndarray, K: float) -> Structure:
+def build_structure(points: np.ndarray, K: float, leaf_max: int = 0, extra: int = 3) -> Structure:
     """Tree, interaction lists on every level, P2P lists and the needed directions.
 
     A direction of a box is needed (outgoing) if some pair reads it or the
     parent's needed outgoing direction maps down to it (HF-M2M input); likewise
     incoming for pairs that write it or for HF-L2L from the parent.
+    leaf_max > 0 makes the low-frequency part adaptive (see build_tree).
     """
-    tree = build_tree(points, K)
+    tree = build_tree(points, K, leaf_max, extra)
     lists = {}
     hf = []
-    for l in range(1, tree.D + 1):
+    for l in range(1, tree.Dmax + 1):
         pl = interaction_lists(tree, l)
         lists[l] = pl
         if tree.width(l) >= 1 and len(pl.tgt):
@@ -338,5 +422,6 @@ def build_structure(points: np.ndarray, K: float) -> Structure:
                 del par
             out_slots[l] = np.array(sorted(outs), dtype=np.int64).reshape(-1, 2)
             in_slots[l] = np.array(sorted(ins), dtype=np.int64).reshape(-1, 2)
-    return Structure(tree=tree, lists=lists, near=near_lists(tree), hf_levels=hf,
+    near = near_lists(tree) if tree.Dmax == tree.D else adaptive_near_lists(tree)
+    return Structure(tree=tree, lists=lists, near=near, hf_levels=hf,
                      out_slots=out_slots, in_slots=in_slots)
