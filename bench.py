@@ -432,7 +432,10 @@ def main() -> int:
     m2l_ms = stages["hf_m2l"][0] + stages["lf_m2l"][0]
     m2l_launches = stages["hf_m2l"][1] + stages["lf_m2l"][1]
     per_apply = m2l_launches / max(1, args.steps)
-    flops_apply = (info.flops_m2l_hf + info.flops_m2l_lf) * nrhs
+    # slot form (from 16 rhs): one launch per level sums the level's M2L pairs and
+    # its L2L terms into every incoming slot, and no reduction launches run
+    slot_form = stages["hf_reduce"][1] == 0 and stages["lf_reduce"][1] == 0 and stages["lf_m2l"][1] > 0
+    flops_apply = (info.flops_m2l_hf + info.flops_m2l_lf + (info.flops_l2l if slot_form else 0.0)) * nrhs
     bytes_apply = info.bytes_m2l_op + info.bytes_m2l_vec * nrhs
     sec = m2l_ms * 1e-3 / args.steps  # M2L launch time per apply
     # the bound is whichever ceiling is lower for these flops and bytes
@@ -458,7 +461,8 @@ def main() -> int:
     nf_sec = stages["near_field"][0] * 1e-3 / args.steps
     nf_pairs = info.near_point_pairs
     nf_flops = nf_pairs * (17 + 8 * nrhs)
-    near = {"kernel": "k_leaf_eval (near field, second stream, overlapping the far-field passes)",
+    near_kernel = "k_near_mfma" if (nrhs >= 4 and eps >= 1e-5) else "k_leaf_eval"
+    near = {"kernel": f"{near_kernel} (near field, second stream, overlapping the far-field passes)",
             "point_pairs": nf_pairs, "ms": nf_sec * 1e3, "pairs_per_s": nf_pairs / nf_sec,
             "tflops": nf_flops / nf_sec / 1e12, "frac_fp32_vector_unpacked": nf_flops / nf_sec / 1e12 / 78.6,
             "frac_fp32_vector_packed": nf_flops / nf_sec / 1e12 / 157.3}
@@ -487,7 +491,9 @@ def main() -> int:
         "ms_per_step_graph_replay": ms_graph,
         "roofline": {
             "bound": "mfma" if mfma_bound else "hbm",
-            "kernel": ("k_m2l_fused (every M2L level in one launch)" if stages["lf_m2l"][1] == 0 and per_apply == 1
+            "kernel": ("k_m2l_slot (per level: every incoming slot sums its M2L pairs and L2L terms; "
+                       "flops of both)" if slot_form else
+                       "k_m2l_fused (every M2L level in one launch)" if stages["lf_m2l"][1] == 0 and per_apply == 1
                        else "k_m2l (grouped M2L GEMM, one launch per level)"),
             "achieved": achieved,
             "peak": peak,
@@ -498,6 +504,8 @@ def main() -> int:
             "avg_launch_us": sec / max(1.0, per_apply) * 1e6,
             "flops_per_launch": flops_apply / max(1.0, per_apply),
             "alg_bytes_per_launch": bytes_apply / max(1.0, per_apply),
+            "l2l_flops_per_apply": info.flops_l2l * nrhs,
+            "m2m_flops_per_apply": info.flops_m2m * nrhs,
             "flops_per_level": {f"w={info.K / 2 ** l:g}": info.flops_m2l_level[l] * nrhs
                                 for l in range(info.depth + 1) if info.flops_m2l_level[l] > 0},
         },

@@ -127,6 +127,20 @@ typedef struct {
 #define DFMM_PREC_FP32 0
 #define DFMM_PREC_FP16X3 1
 #define DFMM_PREC_BF16X3 2
+/* FP64: the whole pass in float64 (Table 1 of the paper goes to eps = 1e-8):
+ * densities f and potentials u are complex128 (interleaved double re, im),
+ * the leaf weights, check potentials and translation operators float64, the
+ * GEMMs on v_mfma_f64_16x16x4f64 and the near-field sum with float64 sin/cos.
+ * Accepts 1e-8 <= eps <= 1e-2; the skeleton tolerance is the float32 rule's
+ * but not below 1e-9.  The middle factors D of Eq. 2 grow like 1/tau, so the
+ * float64 rounding of the check potentials reaches u amplified by ~1/tau, and
+ * the float64 precompute holds Eq. 2 on fresh samples to 3e-8 .. 1e-7 at
+ * tau = 1e-9: an eps = 1e-8 plan gives a relative error of 6e-8 .. 2e-7
+ * against the direct sum (K = 4 and 8 spheres), the floor of this
+ * factorisation in float64.  dfmm_apply and dfmm_apply_ws serve these
+ * plans (workspace from dfmm_workspace_bytes); dfmm_apply_batch returns
+ * DFMM_EUNSUPPORTED for them. */
+#define DFMM_PREC_FP64 3
 
 /* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device, FP32,
  * leaf width 1/2, the calibrated tau rule, no HBM budget. */
@@ -243,6 +257,9 @@ typedef struct {
                              every target slot read and written once (16 r_in), complex64, unpadded */
   double flops_m2l_level[32]; /* flops_m2l_hf / flops_m2l_lf split by level 0..D */
   double tau;             /* skeleton tolerance of the plan's operator set */
+  double flops_m2m;       /* HF-M2M: 8 r_parent r_child per (out-slot, child), per right-hand side */
+  double flops_l2l;       /* HF-L2L (into the leaves too): 8 r_child r_parent per (in-slot, parent wedge),
+                             per right-hand side */
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);

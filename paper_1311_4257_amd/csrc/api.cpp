@@ -1,6 +1,7 @@
 // C ABI of libdfmm (declarations and contracts in include/dfmm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -78,6 +79,12 @@ bool is_pow2(double K) {
 // a share of the budget: at tau = 5e-8 the K = 16 sphere gave 7.6e-7 and the
 // 131,072-point ellipsoid 1.07e-6, so tau = 0.03 eps there.
 double tau_for_eps(double eps) { return eps >= 1e-5 ? 0.1 * eps : 0.03 * eps; }
+// Float64 plans: the same rule, but not below 1e-9.  The skeletons' middle
+// factors D = G(X, b)^+ G(X, Y) G(a, Y)^+ are formed in float64 from matrices of
+// condition ~1/tau; on fresh samples Eq. 2 then holds to about 7 tau at
+// tau = 1e-6, 20 tau at 1e-8, 6e-8 at 1e-9, and worse again below (3e-7 at
+// 1e-10, 4e-6 at 1e-11), so tighter tau buys nothing.
+double tau_for_eps64(double eps) { return std::max(tau_for_eps(eps), 1e-9); }
 
 int dir_count(double w, int* e) {
   if (w == 0.5) {
@@ -110,7 +117,9 @@ const OpSetImpl* plan_ops(void* vctx, int w_needed) {
     c.used = c.opt->opset;
     return c.used;
   }
-  double tau = c.opt->tol_factor > 0.0 ? c.opt->tol_factor * c.opt->eps : tau_for_eps(c.opt->eps);
+  const bool fp64 = c.opt->precision == DFMM_PREC_FP64;
+  double tau = c.opt->tol_factor > 0.0 ? c.opt->tol_factor * c.opt->eps
+                                       : (fp64 ? tau_for_eps64(c.opt->eps) : tau_for_eps(c.opt->eps));
   int w_hi = 1;
   while (w_hi < w_needed) w_hi *= 2;
   const char* dir = c.opt->cache_dir ? c.opt->cache_dir : std::getenv("DFMM_CACHE_DIR");
@@ -280,8 +289,10 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
     if (!points || !opt) return fail(DFMM_EINVAL, "null points or options");
     if (N < 1 || N > (int64_t(1) << 31) - 1) return fail(DFMM_EINVAL, "N must be in [1, 2^31 - 1]");
     if (!is_pow2(K)) return fail(DFMM_EUNSUPPORTED, "K must be a power of two in [1, 2^20]");
-    if (!opt->opset && !(opt->eps >= 1e-6 && opt->eps <= 1e-2))
-      return fail(DFMM_EUNSUPPORTED, "eps must be in [1e-6, 1e-2]");
+    const bool fp64 = opt->precision == DFMM_PREC_FP64;
+    if (!opt->opset && !(opt->eps >= (fp64 ? 1e-8 : 1e-6) && opt->eps <= 1e-2))
+      return fail(DFMM_EUNSUPPORTED, fp64 ? "eps must be in [1e-8, 1e-2] for float64 plans"
+                                          : "eps must be in [1e-6, 1e-2] (float64 plans: from 1e-8)");
     if (opt->opset) {
       for (auto& v : opt->opset->hf)
         for (auto& s : v)
@@ -307,11 +318,14 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
       return fail(DFMM_ENOMEM, "the plan needs at least " + std::to_string(uint64_t(N) * 64u) +
                                    " device bytes; hbm_budget_bytes is " + std::to_string(opt->hbm_budget_bytes));
     const double tau_plan = opt->opset ? opt->opset->tau
-                                       : (opt->tol_factor > 0.0 ? opt->tol_factor * opt->eps : tau_for_eps(opt->eps));
-    const bool precise = tau_plan < 3e-6;
-    if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_BF16X3)
+                            : (opt->tol_factor > 0.0 ? opt->tol_factor * opt->eps
+                                                     : (fp64 ? tau_for_eps64(opt->eps) : tau_for_eps(opt->eps)));
+    // float32 plans below tau 3e-6 are "precise" (split operators, float64 partial
+    // sums); float64 plans need neither
+    const bool precise = !fp64 && tau_plan < 3e-6;
+    if (opt->precision < DFMM_PREC_FP32 || opt->precision > DFMM_PREC_FP64)
       return fail(DFMM_EINVAL, "unknown precision");
-    if (opt->precision != DFMM_PREC_FP32 && precise)
+    if ((opt->precision == DFMM_PREC_FP16X3 || opt->precision == DFMM_PREC_BF16X3) && precise)
       return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
     int dev = opt->device;
     if (dev < 0) DFMM_HIP(hipGetDevice(&dev));
@@ -337,7 +351,7 @@ int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream)
     if (nrhs < 1 || nrhs > 4096) return fail(DFMM_EINVAL, "nrhs must be in [1, 4096]");
     const char* fb = static_cast<const char*>(f);
     const char* ub = static_cast<const char*>(u);
-    size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
+    size_t bytes = size_t(plan->prec == DFMM_PREC_FP64 ? 16 : 8) * size_t(plan->N) * size_t(nrhs);
     if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
     ReqTable R{};
     R.f[0] = static_cast<const float2*>(f);
@@ -355,6 +369,7 @@ int dfmm_apply_batch(dfmm_plan_t plan, int nreq, const void* const* f, void* con
   return guarded([&]() {
     if (!plan || !f || !u || !nrhs) return fail(DFMM_EINVAL, "null plan or array");
     if (nreq < 1 || nreq > DFMM_MAX_BATCH) return fail(DFMM_EINVAL, "nreq must be in [1, DFMM_MAX_BATCH]");
+    if (plan->prec == DFMM_PREC_FP64) return fail(DFMM_EUNSUPPORTED, "float64 plans take dfmm_apply or dfmm_apply_ws");
     ReqTable R{};
     int total = 0;
     const size_t col = size_t(8) * size_t(plan->N);
@@ -394,7 +409,7 @@ int dfmm_apply_ws(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* ws, 
     const char* fb = static_cast<const char*>(f);
     const char* ub = static_cast<const char*>(u);
     const char* wb = static_cast<const char*>(ws);
-    size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
+    size_t bytes = size_t(plan->prec == DFMM_PREC_FP64 ? 16 : 8) * size_t(plan->N) * size_t(nrhs);
     if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
     if ((wb < ub + bytes && ub < wb + ws_bytes) || (wb < fb + bytes && fb < wb + ws_bytes))
       return fail(DFMM_EINVAL, "the workspace overlaps f or u");

@@ -119,11 +119,14 @@ __global__ void k_permute_in(const ReqTable R, float2* __restrict__ fs, const in
 // large and cancel; the product is a well-scaled interpolation weight that
 // float32 holds without loss.  One block per leaf, points in sequence.
 constexpr int LW_BS = 64;
+__device__ __forceinline__ void put_w(float2* p, double re, double im) { *p = make_float2(float(re), float(im)); }
+__device__ __forceinline__ void put_w(double2* p, double re, double im) { *p = make_double2(re, im); }
+template <class WT>  // float2 (float32 plans) or double2 (float64 plans)
 __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict__ pts, const int* __restrict__ lstart,
                                                          const float4* __restrict__ lcen,
                                                          const double4* __restrict__ a_lf,
                                                          const double2* __restrict__ DT, int R, int Ra,
-                                                         float2* __restrict__ V, float2* __restrict__ W) {
+                                                         WT* __restrict__ V, WT* __restrict__ W) {
   extern __shared__ double2 gs[];  // Ra
   const int b = blockIdx.x;
   const float4 c = lcen[b];
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict
         gv = make_double2(cs / r, sn / r);
         gs[p] = gv;
       }
-      V[int64_t(j) * R + p] = make_float2(float(gv.x), float(gv.y));
+      put_w(&V[int64_t(j) * R + p], gv.x, gv.y);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < R; q += LW_BS) {
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict
         wr += gv.x * d.x - gv.y * d.y;
         wi += gv.x * d.y + gv.y * d.x;
       }
-      W[int64_t(j) * R + q] = make_float2(float(wr), float(wi));
+      put_w(&W[int64_t(j) * R + q], wr, wi);
     }
   }
 }
@@ -1720,7 +1723,8 @@ static bool prepare_slot(SlotLaunch& L, const SlotGemm& S, int nrhs, int nt) {
   const int need = (NC * (S.Kmax / 2) + 64 * SLOT_UB - 1) / (64 * SLOT_UB);
   L.waves = std::max(L.waves, need);
   L.pmax = S.Kmax <= 64 ? 4 : (S.Kmax <= 112 ? 7 : 8);
-  return L.waves <= 16 && S.Kmax <= 128 && slot_lds_bytes(S, nt) <= size_t(kGgDynLds);
+  return L.waves <= 16 && S.Kmax <= 128 && S.KXmax <= 128 && !S.split2 &&
+         slot_lds_bytes(S, nt) <= size_t(kGgDynLds);
 }
 
 // The slot form serves fast float32 plans with at least kSlotMinRhs right-hand
@@ -1916,6 +1920,7 @@ static WsLayout plan_layout(const dfmm_plan_s& P, int nrhs) {
 }
 
 size_t workspace_bytes(const dfmm_plan_s& P, int nrhs) {
+  if (P.prec == DFMM_PREC_FP64) return ws_layout(ws_shape64(P), nrhs, false, 16).total;
   if (!P.ws) return plan_layout(P, nrhs).total;
   std::lock_guard<std::mutex> lock(P.ws->mu);
   return plan_layout(P, nrhs).total;
@@ -2169,6 +2174,26 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   }
   ApplyState& AS = *P.ws;
   std::unique_lock<std::mutex> lock(AS.mu);
+  if (P.prec == DFMM_PREC_FP64) {  // the float64 pass: its own kernels, everything on st
+    if (R.n != 1 || existing_only) throw Error{DFMM_EUNSUPPORTED, "float64 plans take dfmm_apply or dfmm_apply_ws"};
+    const size_t need = ws_layout(ws_shape64(P), nrhs, false, 16).total;
+    if (!own && ws_bytes < need)
+      throw Error{DFMM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes; this apply needs " +
+                                   std::to_string(need)};
+    if (own) {
+      hipStreamCaptureStatus c2 = hipStreamCaptureStatusNone;
+      DFMM_HIP(hipStreamIsCapturing(st, &c2));
+      if (c2 != hipStreamCaptureStatusNone && (!AS.buf.p || AS.buf.bytes < need))
+        throw Error{DFMM_EINVAL, "dfmm_apply under stream capture needs an earlier uncaptured apply"};
+      if (c2 != hipStreamCaptureStatusNone) AS.captured = true;
+      ensure_workspace(AS, need);
+    } else {
+      lock.unlock();
+    }
+    run_apply64(P, reinterpret_cast<const double2*>(R.f[0]), reinterpret_cast<double2*>(R.u[0]), nrhs, st,
+                own ? AS.buf.p : ws);
+    return;
+  }
   const WsLayout L = plan_layout(P, nrhs);
   if (!own && ws_bytes < L.total)
     throw Error{DFMM_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes; this apply needs " +
@@ -2366,11 +2391,18 @@ void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, c
   dp.upload(sorted_pts);
   dt.upload(DT);
   const int R = P.lf.R;
-  P.lf.V.alloc(sizeof(float2) * size_t(P.N) * R);
-  P.lf.W.alloc(sizeof(float2) * size_t(P.N) * R);
-  hipLaunchKernelGGL(k_leaf_weights, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
-                     dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
-                     dt.as<double2>(), R, P.lf.r, P.lf.V.as<float2>(), P.lf.W.as<float2>());
+  const bool f64 = P.prec == DFMM_PREC_FP64;
+  const size_t es = f64 ? sizeof(double2) : sizeof(float2);
+  P.lf.V.alloc(es * size_t(P.N) * R);
+  P.lf.W.alloc(es * size_t(P.N) * R);
+  if (f64)
+    hipLaunchKernelGGL(k_leaf_weights<double2>, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
+                       dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
+                       dt.as<double2>(), R, P.lf.r, P.lf.V.as<double2>(), P.lf.W.as<double2>());
+  else
+    hipLaunchKernelGGL(k_leaf_weights<float2>, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
+                       dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
+                       dt.as<double2>(), R, P.lf.r, P.lf.V.as<float2>(), P.lf.W.as<float2>());
   DFMM_HIP(hipGetLastError());
   DFMM_HIP(hipDeviceSynchronize());
 }

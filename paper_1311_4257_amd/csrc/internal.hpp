@@ -140,6 +140,8 @@ struct SlotTerm {
 struct SlotGemm {
   int M = 0;                 // row stride of the output vectors (padded rank)
   int Kmax = 8;              // largest packed K of any term (LDS column length)
+  int KXmax = 8;             // largest row stride of the source vectors (set by the plan)
+  bool split2 = false;       // some term has split operators (not handled by the slot kernel)
   int64_t ngroups = 0, nterms = 0;
   int max_terms = 0;
   double flops[2] = {0, 0};  // 8 r_dst r_src per term and rhs by kind (unpadded ranks)
@@ -157,7 +159,7 @@ struct SlotKind {
 };
 // Term lists -> device tables; terms of a group keep the order given.
 void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int32_t>& gM,
-                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2]);
+                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2], int kx_max);
 
 // Pack an M x K complex matrix (row-major, interleaved float64) into the
 // fragment order read by the GEMM kernel.
@@ -166,7 +168,11 @@ void pack_operator(const double* Tc, int M, int K, float* out);
 // rounding of T and T_lo that of the remainder; out holds 2 M K split floats
 void pack_operator_split(const double* Tc, int M, int K, int split, float* out);
 // K of a packed operator: a multiple of 16 for the 16-bit MFMA (two k-steps per instruction)
-inline int kpad(int K, int prec) { return prec ? (K + 15) / 16 * 16 : K; }
+inline int kpad(int K, int prec) {
+  return (prec == DFMM_PREC_FP16X3 || prec == DFMM_PREC_BF16X3) ? (K + 15) / 16 * 16 : K;
+}
+// pack_operator in float64: the same fragment order, double4 in place of float4
+void pack_operator64(const double* Tc, int M, int K, double* out);
 // Convert nops packed float32 operators (stride floats apart) in place to the
 // hi + lo 16-bit format of prec: each float4 slot (re0, im0, re1, im1) becomes
 // four 32-bit words (hi re0 | hi im0), (hi re1 | hi im1), (lo re0 | lo im0),
@@ -297,6 +303,10 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
                bool existing_only);
 size_t workspace_bytes(const dfmm_plan_s& P, int nrhs);
 size_t plan_device_bytes(const dfmm_plan_s& P);
+// float64 plans: the whole pass in complex128 on a caller-sized workspace
+// (ws_layout(ws_shape64(P), nrhs, false, 16))
+WsShape ws_shape64(const dfmm_plan_s& P);
+void run_apply64(dfmm_plan_s& P, const double2* f, double2* u, int nrhs, hipStream_t st, void* ws);
 void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT);
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                 const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);

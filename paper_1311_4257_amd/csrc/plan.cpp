@@ -71,6 +71,43 @@ void pack_operator(const double* Tc, int M, int K, float* out) {
         }
 }
 
+void pack_operator64(const double* Tc, int M, int K, double* out) {
+  int nm = M / 8, ns = K / 8;
+  for (int m = 0; m < nm; ++m)
+    for (int s4 = 0; s4 < ns; ++s4)
+      for (int ql = 0; ql < 8; ++ql)
+        for (int kr = 0; kr < 4; ++kr) {
+          int q = 8 * m + ql, p0 = kr * (K / 4) + 2 * s4;
+          double* o = out + 4 * ((((size_t(m) * ns + s4) * 8 + ql) * 4) + kr);
+          o[0] = Tc[2 * (size_t(q) * K + p0)];
+          o[1] = Tc[2 * (size_t(q) * K + p0) + 1];
+          o[2] = Tc[2 * (size_t(q) * K + p0 + 1)];
+          o[3] = Tc[2 * (size_t(q) * K + p0 + 1) + 1];
+        }
+}
+
+namespace {
+// Packed operators of one launch, float32 (fragment order of the float32 and
+// 16-bit engines) or float64 (float64 plans); entries at the same offsets.
+struct OpStore {
+  bool f64;
+  std::vector<float> f;
+  std::vector<double> d;
+  OpStore(bool f64_, size_t n) : f64(f64_) {
+    if (f64) d.assign(n, 0.0);
+    else f.assign(n, 0.0f);
+  }
+  void pack(const double* T, int M, int K, int split, size_t off) {
+    if (f64) pack_operator64(T, M, K, d.data() + off);
+    else pack_operator_split(T, M, K, split, f.data() + off);
+  }
+  void upload(DevBuf& b) {
+    if (f64) b.upload(d);
+    else b.upload(f);
+  }
+};
+}  // namespace
+
 void pack_operator_split(const double* Tc, int M, int K, int split, float* out) {
   if (split == 1) {
     pack_operator(Tc, M, K, out);
@@ -172,8 +209,10 @@ void to_half_ops(std::vector<float>& A, int64_t nops, int64_t stride, int prec, 
 }
 
 void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int32_t>& gM,
-                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2]) {
+                     const std::vector<SlotTerm>& terms, const SlotKind kinds[2], int kx_max) {
   S.M = M;
+  S.KXmax = kx_max;
+  S.split2 = false;
   S.ngroups = ngroups;
   S.nterms = int64_t(terms.size());
   S.flops[0] = S.flops[1] = 0.0;
@@ -199,16 +238,16 @@ void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int3
     e[2] = kp | (k.split << 12) | (t.kind << 14);
     e[3] = 0;
     kmax = std::max(kmax, kp);
+    S.split2 = S.split2 || k.split != 1;
     S.flops[t.kind] += k.G->opflops[size_t(t.op)];
   }
   S.Kmax = kmax;
   S.max_terms = 0;
+  for (int64_t g = 0; g < ngroups; ++g) S.max_terms = std::max(S.max_terms, cnt[size_t(g) + 1] - cnt[size_t(g)]);
+  // launch order: the groups with the most terms first (the long ones start
+  // early and the launch ends on short ones)
   std::vector<int32_t> order(static_cast<size_t>(ngroups));
-  for (int64_t g = 0; g < ngroups; ++g) {
-    order[size_t(g)] = int32_t(g);
-    S.max_terms = std::max(S.max_terms, cnt[size_t(g) + 1] - cnt[size_t(g)]);
-  }
-  // most terms first: the longest groups start early and the launch ends on short ones
+  for (int64_t g = 0; g < ngroups; ++g) order[size_t(g)] = int32_t(g);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
     return cnt[size_t(a) + 1] - cnt[size_t(a)] > cnt[size_t(b) + 1] - cnt[size_t(b)];
   });
@@ -248,6 +287,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   P.D = D;
   dfmm_info& info = P.info;
   std::memset(&info, 0, sizeof(info));
+  const bool fp64 = P.prec == DFMM_PREC_FP64;  // float64 operators and vectors
+  const bool half = P.prec == DFMM_PREC_FP16X3 || P.prec == DFMM_PREC_BF16X3;
   info.N = N;
   info.K = K;
   info.depth = D;
@@ -404,7 +445,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     std::vector<int32_t> vdst(vsrc.size());
     for (size_t i = 0; i < vdst.size(); ++i) vdst[i] = int32_t(i);
     const int RK = kpad(R, P.prec);  // packed K of every operator of the launch
-    std::vector<float> At(size_t(2) * R * RK * split * ngroups, 0.0f);
+    OpStore At(fp64, size_t(2) * R * RK * split * ngroups);
     std::vector<int32_t> gmk(size_t(2) * ngroups);
     std::vector<int64_t> aoff(ngroups);
     parallel_for(ngroups, [&](int64_t gi) {
@@ -435,11 +476,11 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           T[2 * (size_t(q) * Kp + j) + 1] = im;
         }
       }
-      pack_operator_split(T.data(), Mg, Kp, split, &At[size_t(2) * R * RK * split * gi]);
+      At.pack(T.data(), Mg, Kp, split, size_t(2) * R * RK * split * gi);
     });
-    if (P.prec) {
+    if (half) {
       std::vector<int32_t> aexp;
-      to_half_ops(At, ngroups, int64_t(2) * R * RK * split, P.prec, aexp);
+      to_half_ops(At.f, ngroups, int64_t(2) * R * RK * split, P.prec, aexp);
       G.aexp.upload(aexp);
     }
     G.prec = P.prec;
@@ -451,7 +492,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     G.ngroups = ngroups;
     G.nvec = int64_t(vsrc.size());
     G.nops = ngroups;
-    G.A.upload(At);
+    At.upload(G.A);
     G.aoff.upload(aoff);
     G.gmk.upload(gmk);
     G.ops.upload(opsv);
@@ -520,8 +561,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     // check potentials to the child's (c = the child skeleton of wedge l).
     int ndir = int(6 * w * w);
     const int KU = kpad(H.Rc, P.prec), KD = kpad(H.R, P.prec);  // packed K of the up / down operators
-    std::vector<float> Mu(size_t(2) * ndir * 8 * H.R * KU * hf_split, 0.0f);
-    std::vector<float> Md(size_t(2) * ndir * 8 * H.Rc * KD * hf_split, 0.0f);
+    OpStore Mu(fp64, size_t(2) * ndir * 8 * H.R * KU * hf_split);
+    OpStore Md(fp64, size_t(2) * ndir * 8 * H.Rc * KD * hf_split);
     std::vector<char> dir_used(ndir, 0);
     for (auto& s : OS[l].list) dir_used[s.second] = 1;
     for (auto& s : IS[l].list) dir_used[s.second] = 1;
@@ -570,8 +611,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           dn[2 * (size_t(j) * Kpd + q)] = re;
           dn[2 * (size_t(j) * Kpd + q) + 1] = im;
         }
-      pack_operator_split(up.data(), Ms, Kpu, hf_split, &Mu[size_t(2) * id * H.R * KU * hf_split]);
-      pack_operator_split(dn.data(), Mc, Kpd, hf_split, &Md[size_t(2) * id * H.Rc * KD * hf_split]);
+      Mu.pack(up.data(), Ms, Kpu, hf_split, size_t(2) * id * H.R * KU * hf_split);
+      Md.pack(dn.data(), Mc, Kpd, hf_split, size_t(2) * id * H.Rc * KD * hf_split);
     });
 
     // HF-M2M and HF-L2L as pair lists: one pair per (parent slot, child), grouped
@@ -636,12 +677,12 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
           up_terms[size_t(e)].push_back({int32_t(i), int32_t(size_t(d) * 8 + C.octant[c]), src, 0});
         }
       }
-      if (P.prec) {
+      if (half) {
         std::vector<int32_t> aexp;
-        to_half_ops(Mu, int64_t(ndir) * 8, int64_t(2) * H.R * KU * hf_split, P.prec, aexp);
+        to_half_ops(Mu.f, int64_t(ndir) * 8, int64_t(2) * H.R * KU * hf_split, P.prec, aexp);
         H.m2m.aexp.upload(aexp);
       }
-      H.m2m.A.upload(Mu);
+      Mu.upload(H.m2m.A);
       finish_pairs(H.m2m, by_op, H.R, H.Rc, int64_t(ndir) * 8, H.nout, H.m2m_rs, H.m2m_ri, H.m2m_npairs, op_ms,
                    op_mc);
     }
@@ -679,12 +720,12 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             }
         }
       }
-      if (P.prec) {
+      if (half) {
         std::vector<int32_t> aexp;
-        to_half_ops(Md, int64_t(ndir) * 8, int64_t(2) * H.Rc * KD * hf_split, P.prec, aexp);
+        to_half_ops(Md.f, int64_t(ndir) * 8, int64_t(2) * H.Rc * KD * hf_split, P.prec, aexp);
         H.l2l.aexp.upload(aexp);
       }
-      H.l2l.A.upload(Md);
+      Md.upload(H.l2l.A);
       finish_pairs(H.l2l, by_op, H.Rc, H.R, int64_t(ndir) * 8, H.nchild_in, H.l2l_rs, H.l2l_ri, H.l2l_npairs,
                    op_mc, op_ms);
     }
@@ -696,8 +737,17 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     info.flops_m2l_hf += H.flops;
     info.flops_m2l_level[l] = H.flops;
   }
+  // algorithmic flops of the tree transfers per right-hand side (8 r_out r_in per term)
+  for (int e = 0; e <= e_top; ++e) {
+    for (const SlotTerm& t : up_terms[size_t(e)]) info.flops_m2m += P.hf[size_t(e)].m2m.opflops[size_t(t.op)];
+    for (const SlotTerm& t : down_terms[size_t(e)])
+      if (t.kind == 1) info.flops_l2l += P.hf[size_t(e + 1)].l2l.opflops[size_t(t.op)];
+  }
+  for (const SlotTerm& t : lf_terms)
+    if (t.kind == 1) info.flops_l2l += P.hf[0].l2l.opflops[size_t(t.op)];
+
   // ---- slot-form tables (fast float32 plans; used from 16 right-hand sides) -------
-  if (!P.precise && P.prec == DFMM_PREC_FP32) {
+  if ((!P.precise && P.prec == DFMM_PREC_FP32) || fp64) {
     auto slot_m = [&](int l, int64_t n, bool in) {  // padded rows of each slot's skeleton
       std::vector<int32_t> gm(static_cast<size_t>(n));
       const int e = D - 1 - l;
@@ -709,12 +759,15 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
       HFLevel& H = P.hf[size_t(e)];
       const int l = H.l;
       SlotKind up[2] = {{&H.m2m, hf_split}, {nullptr, 1}};
-      build_slot_gemm(H.up, H.R, H.nout, slot_m(l, H.nout, false), up_terms[size_t(e)], up);
+      build_slot_gemm(H.up, H.R, H.nout, slot_m(l, H.nout, false), up_terms[size_t(e)], up,
+                      e == 0 ? Rlf : P.hf[size_t(e - 1)].R);
       SlotKind dn[2] = {{&H.m2l, hf_split}, {e < e_top ? &P.hf[size_t(e + 1)].l2l : nullptr, hf_split}};
-      build_slot_gemm(H.down, H.R, H.nin, slot_m(l, H.nin, true), down_terms[size_t(e)], dn);
+      build_slot_gemm(H.down, H.R, H.nin, slot_m(l, H.nin, true), down_terms[size_t(e)], dn,
+                      std::max(H.R, e < e_top ? P.hf[size_t(e + 1)].R : 0));
     }
     SlotKind dn[2] = {{&P.lf.m2l, 1}, {e_top >= 0 ? &P.hf[0].l2l : nullptr, hf_split}};
-    build_slot_gemm(P.lf.down, Rlf, nleaf, std::vector<int32_t>(size_t(nleaf), Rlf), lf_terms, dn);
+    build_slot_gemm(P.lf.down, Rlf, nleaf, std::vector<int32_t>(size_t(nleaf), Rlf), lf_terms, dn,
+                    std::max(Rlf, e_top >= 0 ? P.hf[0].R : 0));
   }
 
   info.device_bytes = int64_t(plan_device_bytes(P));

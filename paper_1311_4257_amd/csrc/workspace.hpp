@@ -22,12 +22,12 @@ struct WsShape {
 };
 
 // Byte offsets of every buffer for nrhs right-hand sides:
-//   fs     complex64 [N][nrhs]        densities in tree order
+//   fs     complex [N][nrhs]          densities in tree order
 //   unear  complex128 [nrhs][N]       near-field sums (tree order)
-//   flf    complex64 [nleaf][nrhs][Rlf]  leaf outgoing check potentials
-//   ulf    complex64 [nleaf][nrhs][Rlf]  leaf incoming check potentials
-//   F[e]   complex64 [nout][nrhs][R]  HF outgoing check potentials of level e
-//   U[e]   complex64 [nin][nrhs][R]   HF incoming check potentials of level e
+//   flf    complex [nleaf][nrhs][Rlf] leaf outgoing check potentials
+//   ulf    complex [nleaf][nrhs][Rlf] leaf incoming check potentials
+//   F[e]   complex [nout][nrhs][R]    HF outgoing check potentials of level e
+//   U[e]   complex [nin][nrhs][R]     HF incoming check potentials of level e
 //   Y      complex64 [pair_rows][nrhs]   pair outputs (pair form only; else empty)
 struct WsLayout {
   size_t fs = 0, unear = 0, flf = 0, ulf = 0, Y = 0;
@@ -45,10 +45,14 @@ inline size_t ws_mul(size_t a, size_t b) {
   return a * b;
 }
 
-inline WsLayout ws_layout(const WsShape& s, int nrhs, bool pair_form) {
+// csize: bytes of one complex entry of the densities and check potentials
+// (8: complex64; 16: complex128 for float64 plans); the near-field sums are
+// complex128 in both.
+inline WsLayout ws_layout(const WsShape& s, int nrhs, bool pair_form, int csize = 8) {
   if (nrhs < 1 || s.N < 0 || s.nleaf < 0 || s.Rlf < 0 || s.nout.size() != s.R.size() ||
-      s.nin.size() != s.R.size())
+      s.nin.size() != s.R.size() || (csize != 8 && csize != 16))
     throw std::invalid_argument("bad workspace shape");
+  const size_t cs = size_t(csize);
   WsLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -58,13 +62,13 @@ inline WsLayout ws_layout(const WsShape& s, int nrhs, bool pair_form) {
     return at;
   };
   const size_t k = size_t(nrhs);
-  L.fs = take(ws_mul(ws_mul(8, size_t(s.N)), k));
+  L.fs = take(ws_mul(ws_mul(cs, size_t(s.N)), k));
   L.unear = take(ws_mul(ws_mul(16, size_t(s.N)), k));
-  const size_t lf = ws_mul(ws_mul(ws_mul(8, size_t(s.nleaf)), size_t(s.Rlf)), k);
+  const size_t lf = ws_mul(ws_mul(ws_mul(cs, size_t(s.nleaf)), size_t(s.Rlf)), k);
   L.flf = take(lf);
   L.ulf = take(lf);
   for (size_t e = 0; e < s.R.size(); ++e) {
-    const size_t r = ws_mul(ws_mul(8, size_t(s.R[e])), k);
+    const size_t r = ws_mul(ws_mul(cs, size_t(s.R[e])), k);
     L.F.push_back(take(ws_mul(r, size_t(s.nout[e] > 0 ? s.nout[e] : 1))));
     L.U.push_back(take(ws_mul(r, size_t(s.nin[e] > 0 ? s.nin[e] : 1))));
   }

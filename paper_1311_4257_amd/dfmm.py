@@ -29,7 +29,7 @@ STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2
           "leaf_eval", "zero", "near_field"]
 
 MAX_BATCH = 32  # DFMM_MAX_BATCH
-PREC_FP32, PREC_FP16X3, PREC_BF16X3 = 0, 1, 2  # DFMM_PREC_*
+PREC_FP32, PREC_FP16X3, PREC_BF16X3, PREC_FP64 = 0, 1, 2, 3  # DFMM_PREC_*
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
 
@@ -37,7 +37,8 @@ ABI_FUNCTIONS = [
     "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
     "dfmm_opset_set", "dfmm_opset_get", "dfmm_opset_info", "dfmm_opset_save", "dfmm_opset_load",
     "dfmm_opset_destroy", "dfmm_options_default", "dfmm_plan", "dfmm_plan_ex", "dfmm_apply",
-    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_destroy", "dfmm_plan_info", "dfmm_export",
+    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_destroy",
+    "dfmm_plan_info", "dfmm_export",
     "dfmm_set_timing", "dfmm_stage_times",
 ]
 
@@ -56,7 +57,8 @@ class Info(C.Structure):
                 ("near_point_pairs", C.c_int64), ("flops_m2l_hf", C.c_double),
                 ("flops_m2l_lf", C.c_double), ("plan_seconds", C.c_double),
                 ("device_bytes", C.c_int64), ("bytes_m2l_op", C.c_double),
-                ("bytes_m2l_vec", C.c_double), ("flops_m2l_level", C.c_double * 32), ("tau", C.c_double)]
+                ("bytes_m2l_vec", C.c_double), ("flops_m2l_level", C.c_double * 32), ("tau", C.c_double),
+                ("flops_m2m", C.c_double), ("flops_l2l", C.c_double)]
 
 
 _P = C.c_void_p
@@ -197,15 +199,22 @@ class Plan:
         self._h = h
         self.N = pts.shape[0]
         self.K = K
+        self.precision = precision
+
+    def _ctype(self):
+        import torch
+
+        return torch.complex128 if self.precision == PREC_FP64 else torch.complex64
 
     def apply(self, f, u=None, stream=None):
-        """u = A f for a (nrhs, N) complex64 CUDA tensor f (or (N,)); returns u."""
+        """u = A f for a (nrhs, N) CUDA tensor f (or (N,)): complex64, or complex128
+        for float64 plans; returns u."""
         import torch
 
         one = f.dim() == 1
         f2 = f.reshape(1, -1) if one else f
-        if f2.dtype != torch.complex64 or not f2.is_cuda or not f2.is_contiguous():
-            raise ValueError("f must be a contiguous complex64 CUDA tensor")
+        if f2.dtype != self._ctype() or not f2.is_cuda or not f2.is_contiguous():
+            raise ValueError(f"f must be a contiguous {self._ctype()} CUDA tensor")
         if f2.shape[1] != self.N:
             raise ValueError("f has the wrong number of points")
         if u is None:
@@ -224,11 +233,11 @@ class Plan:
 
         one = f.dim() == 1
         f2 = f.reshape(1, -1) if one else f
-        if f2.dtype != torch.complex64 or not f2.is_cuda or not f2.is_contiguous() or f2.shape[1] != self.N:
-            raise ValueError("f must be a contiguous (nrhs, N) complex64 CUDA tensor")
+        if f2.dtype != self._ctype() or not f2.is_cuda or not f2.is_contiguous() or f2.shape[1] != self.N:
+            raise ValueError(f"f must be a contiguous (nrhs, N) {self._ctype()} CUDA tensor")
         u2 = u.reshape(f2.shape)
-        if u2.dtype != torch.complex64 or not u2.is_contiguous():
-            raise ValueError("u must be a contiguous complex64 tensor shaped like f")
+        if u2.dtype != f2.dtype or not u2.is_contiguous():
+            raise ValueError("u must be a contiguous tensor shaped and typed like f")
         if not ws.is_cuda or not ws.is_contiguous():
             raise ValueError("ws must be a contiguous CUDA tensor")
         if stream is None:

@@ -15,3 +15,31 @@ def inject(ops: O.OpSet):
             s.set(float(w), d, sk.a, sk.b, sk.D)
     s.set(0.5, 0, ops.lf.a, ops.lf.b, ops.lf.D)
     return s
+
+
+def cached_oracle_pass(key: str, st, ops, f):
+    """The oracle's pass of Algorithm 1 for (structure, skeletons, densities), computed
+    by oracle.fmm only and kept as .npy under tests/.cache, keyed by the caller's
+    key and a hash of the oracle's sources (a change to the oracle recomputes it)."""
+    import hashlib
+    import os
+
+    import numpy as np
+
+    from oracle import fmm as F
+    from oracle.cache import DEFAULT_DIR
+
+    h = hashlib.sha1()
+    root = os.path.dirname(F.__file__)
+    for name in ("fmm.py", "tree.py", "operators.py", "kernel.py"):
+        with open(os.path.join(root, name), "rb") as fh:
+            h.update(fh.read())
+    fn = os.path.join(DEFAULT_DIR, f"oracle_pass_{key}_{h.hexdigest()[:10]}.npy")
+    if os.path.exists(fn):
+        return np.load(fn)
+    u = F.fmm_apply(st, ops, f)
+    os.makedirs(DEFAULT_DIR, exist_ok=True)
+    tmp = fn + ".tmp.npy"
+    np.save(tmp, u)
+    os.replace(tmp, fn)
+    return u

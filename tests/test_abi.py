@@ -30,6 +30,14 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(dfmm.ABI_FUNCTIONS)
 
 
+def test_header_constants_match_the_binding():
+    from paper_1311_4257_amd import dfmm
+
+    src = open(os.path.join(ROOT, "include", "dfmm.h")).read()
+    m = re.search(r"#define DFMM_MAX_BATCH (\d+)", src)
+    assert m and int(m.group(1)) == dfmm.MAX_BATCH
+
+
 def test_bad_inputs_rejected_on_the_host():
     from paper_1311_4257_amd import dfmm
 

@@ -19,7 +19,7 @@ from oracle.fmm import fmm_apply
 from oracle.kernel import direct_sum, rel_l2
 from oracle.tree import build_structure
 from paper_1311_4257_amd import workloads
-from tests.helpers import inject, oracle_opset
+from tests.helpers import cached_oracle_pass, inject, oracle_opset
 
 pytestmark = pytest.mark.gpu
 
@@ -109,3 +109,26 @@ def test_slot_form_column_chunks(cuda):
     u32 = plan.apply(_to_dev(f, cuda)).cpu().numpy()
     u16 = plan.apply(_to_dev(f[8:24], cuda)).cpu().numpy()
     assert rel_l2(u16, u32[8:24]) < 1e-6, rel_l2(u16, u32[8:24])
+
+
+@pytest.fixture(scope="module")
+def k16():
+    pts = workloads.sphere_points(16384, 16.0, seed=16)
+    st = build_structure(pts, 16.0)
+    assert st.w_top == 4
+    ops = oracle_opset(1e-5, 4)
+    f = workloads.densities(len(pts), 32, seed=116)
+    return pts, st, ops, f, cached_oracle_pass("sphere16_16384_s16_f116_tau1e-5_w4", st, ops, f)
+
+
+@pytest.mark.parametrize("nrhs,fused,prec", [(1, "0", 0), (1, "1", 0), (1, "0", 1), (32, "0", 0)])
+def test_injected_k16_matches_oracle(cuda, k16, monkeypatch, nrhs, fused, prec):
+    """K = 16 sphere (HF levels w = 4, 2, 1: M2M 1 -> 2 -> 4 and L2L 4 -> 2 -> 1
+    through the wedge hierarchy, M2L at w = 4, 2, 1), the oracle's tau = 1e-5
+    skeletons (ranks up to 107): pair form at 1 rhs (separate and fused M2L,
+    float32 and FP16X3 GEMMs) and slot form at 32 rhs, against the oracle."""
+    pts, st, ops, f, ref = k16
+    monkeypatch.setenv("DFMM_FUSED", fused)
+    plan = _dfmm().Plan(pts, 16.0, opset=inject(ops), device=0, precision=prec)
+    u = plan.apply(_to_dev(f[:nrhs], cuda)).cpu().numpy()
+    _check(u, ref[:nrhs], f"K=16 injected nrhs={nrhs} fused={fused} prec={prec}")
