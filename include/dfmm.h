@@ -138,8 +138,8 @@ typedef struct {
  * tau = 1e-9: an eps = 1e-8 plan gives a relative error of 6e-8 .. 2e-7
  * against the direct sum (K = 4 and 8 spheres), the floor of this
  * factorisation in float64.  dfmm_apply and dfmm_apply_ws serve these
- * plans (workspace from dfmm_workspace_bytes); dfmm_apply_batch returns
- * DFMM_EUNSUPPORTED for them. */
+ * plans (workspace from dfmm_workspace_bytes); dfmm_apply_batch and
+ * dfmm_apply_noalloc return DFMM_EUNSUPPORTED for them. */
 #define DFMM_PREC_FP64 3
 
 /* Fill *opt with defaults: eps 1e-4, no opset, no cache, current device, FP32,
@@ -227,6 +227,21 @@ int dfmm_workspace_bytes(dfmm_plan_t plan, int nrhs, size_t* bytes);
  * f, u, nrhs, layout, stream and capture rules as for dfmm_apply; u is
  * overwritten. */
 int dfmm_apply_ws(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* ws, size_t ws_bytes, void* stream);
+
+/* dfmm_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no allocator.  Its workspace is a static device array of the library,
+ * DFMM_NOALLOC_MAX_BYTES bytes on every GPU the library runs on, held until the
+ * process ends; an apply whose workspace (dfmm_workspace_bytes) is larger
+ * returns DFMM_EINVAL.  The launch shapes come from an earlier dfmm_apply (or
+ * dfmm_apply_ws / dfmm_apply_batch) with the same nrhs on this plan; without one
+ * the call returns DFMM_EINVAL.  Everything runs on `stream`.  Every call on one
+ * GPU uses that GPU's array, which keeps the last call's contents (no apply
+ * reads workspace memory it has not written): calls that overlap on one GPU --
+ * on different streams, from different threads or plans -- race, so the caller
+ * serializes them.  f, u, nrhs, layout and stream as for dfmm_apply. */
+#define DFMM_NOALLOC_MAX_BYTES (64u << 20)
+int dfmm_apply_noalloc(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
 
 void dfmm_destroy(dfmm_plan_t plan);
 

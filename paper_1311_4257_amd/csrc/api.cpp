@@ -424,6 +424,26 @@ int dfmm_apply_ws(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* ws, 
   });
 }
 
+int dfmm_apply_noalloc(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream) {
+  return guarded([&]() {
+    if (!plan || !f || !u) return fail(DFMM_EINVAL, "null plan or vector");
+    if (plan->prec == DFMM_PREC_FP64) return fail(DFMM_EUNSUPPORTED, "float64 plans take dfmm_apply or dfmm_apply_ws");
+    if (nrhs < 1 || nrhs > 4096) return fail(DFMM_EINVAL, "nrhs must be in [1, 4096]");
+    const char* fb = static_cast<const char*>(f);
+    const char* ub = static_cast<const char*>(u);
+    size_t bytes = size_t(8) * size_t(plan->N) * size_t(nrhs);
+    if (fb < ub + bytes && ub < fb + bytes) return fail(DFMM_EINVAL, "f and u overlap");
+    ReqTable R{};
+    R.f[0] = static_cast<const float2*>(f);
+    R.u[0] = static_cast<float2*>(u);
+    R.k0[0] = 0;
+    R.n = 1;
+    DeviceScope on(plan->device);
+    run_apply_noalloc(*plan, R, nrhs, static_cast<hipStream_t>(stream));
+    return int(DFMM_OK);
+  });
+}
+
 int dfmm_workspace_bytes(dfmm_plan_t plan, int nrhs, size_t* bytes) {
   return guarded([&]() {
     if (!plan || !bytes) return fail(DFMM_EINVAL, "null plan or output");

@@ -2385,6 +2385,34 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   DFMM_HIP(hipGetLastError());
 }
 
+// ---- applies without allocation -------------------------------------------------------
+// The workspace of dfmm_apply_noalloc: a static device array, one per GPU the
+// library runs on, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not the device memory: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+static void* scratch_ptr(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> ptr;  // device ordinal -> address of that device's array
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptr.find(device);
+  if (it != ptr.end()) return it->second;
+  void* p = nullptr;
+  DFMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error{DFMM_EDEVICE, "no device address for the static workspace"};
+  ptr.emplace(device, p);
+  return p;
+}
+
+void run_apply_noalloc(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st) {
+  const size_t need = workspace_bytes(P, nrhs);
+  if (need > kNoAllocBytes)
+    throw Error{DFMM_EINVAL, "this apply needs a workspace of " + std::to_string(need) +
+                                 " bytes; the static workspace holds " + std::to_string(kNoAllocBytes)};
+  run_apply(P, R, nrhs, st, scratch_ptr(P.device), kNoAllocBytes, true);
+}
+
 // ---- plan-time leaf weights ---------------------------------------------------------
 void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT) {
   DevBuf dp, dt;

@@ -302,6 +302,10 @@ struct ReqTable {
 void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void* ws, size_t ws_bytes,
                bool existing_only);
 size_t workspace_bytes(const dfmm_plan_s& P, int nrhs);
+// dfmm_apply_noalloc: run_apply on the static device workspace (kNoAllocBytes),
+// with the launch shapes an earlier apply of this nrhs prepared.
+constexpr size_t kNoAllocBytes = size_t(DFMM_NOALLOC_MAX_BYTES);
+void run_apply_noalloc(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st);
 size_t plan_device_bytes(const dfmm_plan_s& P);
 // float64 plans: the whole pass in complex128 on a caller-sized workspace
 // (ws_layout(ws_shape64(P), nrhs, false, 16))

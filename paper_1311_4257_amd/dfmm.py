@@ -29,6 +29,7 @@ STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2
           "leaf_eval", "zero", "near_field"]
 
 MAX_BATCH = 32  # DFMM_MAX_BATCH
+NOALLOC_MAX_BYTES = 64 << 20  # DFMM_NOALLOC_MAX_BYTES
 PREC_FP32, PREC_FP16X3, PREC_BF16X3, PREC_FP64 = 0, 1, 2, 3  # DFMM_PREC_*
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
@@ -37,7 +38,7 @@ ABI_FUNCTIONS = [
     "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
     "dfmm_opset_set", "dfmm_opset_get", "dfmm_opset_info", "dfmm_opset_save", "dfmm_opset_load",
     "dfmm_opset_destroy", "dfmm_options_default", "dfmm_plan", "dfmm_plan_ex", "dfmm_apply",
-    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_destroy",
+    "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_apply_noalloc", "dfmm_destroy",
     "dfmm_plan_info", "dfmm_export",
     "dfmm_set_timing", "dfmm_stage_times",
 ]
@@ -82,6 +83,7 @@ _sig = {
                                    C.POINTER(C.c_int), C.c_void_p]),
     "dfmm_workspace_bytes": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t)]),
     "dfmm_apply_ws": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dfmm_apply_noalloc": (C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "dfmm_destroy": (None, [_P]),
     "dfmm_plan_info": (C.c_int, [_P, C.POINTER(Info)]),
     "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
@@ -245,6 +247,23 @@ class Plan:
         nbytes = ws.numel() * ws.element_size()
         _check(_lib.dfmm_apply_ws(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u2.data_ptr()), f2.shape[0],
                                   C.c_void_p(ws.data_ptr()), nbytes, C.c_void_p(stream.cuda_stream)))
+        return u
+
+    def apply_noalloc(self, f, u, stream=None):
+        """dfmm_apply_noalloc: u = A f on the library's static device workspace
+        (no allocation); needs an earlier apply with the same nrhs."""
+        import torch
+
+        f2 = f.reshape(1, -1) if f.dim() == 1 else f
+        if f2.dtype != torch.complex64 or not f2.is_cuda or not f2.is_contiguous() or f2.shape[1] != self.N:
+            raise ValueError("f must be a contiguous (nrhs, N) complex64 CUDA tensor")
+        u2 = u.reshape(f2.shape)
+        if u2.dtype != torch.complex64 or not u2.is_contiguous():
+            raise ValueError("u must be a contiguous complex64 tensor shaped like f")
+        if stream is None:
+            stream = torch.cuda.current_stream(f2.device)
+        _check(_lib.dfmm_apply_noalloc(self._h, C.c_void_p(f2.data_ptr()), C.c_void_p(u2.data_ptr()),
+                                       f2.shape[0], C.c_void_p(stream.cuda_stream)))
         return u
 
     def apply_batch(self, fs, us, stream=None):

@@ -34,6 +34,8 @@ def test_header_constants_match_the_binding():
     from paper_1311_4257_amd import dfmm
 
     src = open(os.path.join(ROOT, "include", "dfmm.h")).read()
+    m = re.search(r"#define DFMM_NOALLOC_MAX_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == dfmm.NOALLOC_MAX_BYTES
     m = re.search(r"#define DFMM_MAX_BATCH (\d+)", src)
     assert m and int(m.group(1)) == dfmm.MAX_BATCH
 
@@ -70,6 +72,7 @@ def test_bad_inputs_rejected_on_the_host():
     n = ctypes.c_size_t()
     assert lib.dfmm_workspace_bytes(None, 1, ctypes.byref(n)) == -1
     assert lib.dfmm_apply_ws(None, None, None, 1, None, 0, None) == -1
+    assert lib.dfmm_apply_noalloc(None, None, None, 1, None) == -1
     arr = (ctypes.c_void_p * 1)(None)
     cnt = (ctypes.c_int * 1)(1)
     assert lib.dfmm_apply_batch(None, 1, arr, arr, cnt, None) == -1
