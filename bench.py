@@ -18,16 +18,19 @@ a second run of the same number of steps (the events cost a little time, so
 MI355X (157.3 TFLOP/s), or against 8 TB/s when the algorithmic bytes make
 HBM the lower ceiling.
 The algorithmic bytes of the M2L are the operators once per offset group,
-every source slot read once and every target slot read and written once.
+every source slot read once and every target slot read and written once;
+where the slot form runs (16 rhs and more) its launches also carry the L2L
+terms, whose operators (once each) and parent slots (read once) are added.
 The CPU baseline times the float64 oracle pass on a bounded sample of the
 same geometry (the first points of the same point set: same K, same tree
 depth, same right-hand sides).
 
 ``--calib-copy`` adds, after the timed steps, one 256 MiB device-to-device
 copy: the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters.
-``--traffic-summary FETCH_DIR WRITE_DIR`` turns the CSV
-output of the two counter runs into the traffic record that later runs report
-(while the GEMM sources are unchanged).
+``--traffic-summary FETCH_DIR WRITE_DIR`` (with ``--workload``) turns the CSV
+output of the two counter runs into the workload's traffic record
+(profiles/m2l_traffic_<workload>.json) that later runs of that workload at its
+default eps report, while the GEMM sources are unchanged.
 """
 from __future__ import annotations
 
@@ -47,7 +50,6 @@ PEAK_FP32_MATRIX_TFLOPS = 157.3
 PEAK_F16_MATRIX_TFLOPS = 2500.0  # dense fp16 / bf16 MFMA
 PEAK_HBM_GBS = 8000.0
 CACHE_DIR = os.path.join(ROOT, ".dfmm_cache")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_traffic_sphere16.json")
 # the M2L launch is defined by the tile engine and the operator layout built at plan time
 GEMM_SOURCES = ["paper_1311_4257_amd/csrc/apply.hip", "paper_1311_4257_amd/csrc/plan.cpp"]
 CALIB_BYTES = 256 << 20
@@ -81,6 +83,10 @@ def _counter_rows(d: str):
         for r in csv.DictReader(fh):
             rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
     return rows
+
+
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"m2l_traffic_{workload}.json")
 
 
 def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
@@ -348,8 +354,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.traffic_summary:
         rec = traffic_summary(*args.traffic_summary)
-        os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-        with open(TRAFFIC_FILE, "w") as fh:
+        rec["workload"] = args.workload
+        with open(traffic_file(args.workload), "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
         return 0
@@ -437,6 +443,8 @@ def main() -> int:
     slot_form = stages["hf_reduce"][1] == 0 and stages["lf_reduce"][1] == 0 and stages["lf_m2l"][1] > 0
     flops_apply = (info.flops_m2l_hf + info.flops_m2l_lf + (info.flops_l2l if slot_form else 0.0)) * nrhs
     bytes_apply = info.bytes_m2l_op + info.bytes_m2l_vec * nrhs
+    if slot_form:  # the L2L terms' operators and parent slots
+        bytes_apply += info.bytes_l2l_op + info.bytes_l2l_vec * nrhs
     sec = m2l_ms * 1e-3 / args.steps  # M2L launch time per apply
     # the bound is whichever ceiling is lower for these flops and bytes
     # a contraction is priced at the peak of its own MFMA dtype (16-bit plans: the
@@ -448,12 +456,14 @@ def main() -> int:
     else:
         achieved, peak, unit = bytes_apply / sec / 1e9, PEAK_HBM_GBS, "GB/s"
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
+    tfile = traffic_file(args.workload)
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
             rec = json.load(fh)
-        # the record holds for the same GEMM sources, workload and launch form
-        if rec.get("source_sha1") == gemm_source_hash() and nrhs == 1 and args.workload == "sphere16" \
-                and eps == 1e-4 and prec == 0 and rec.get("launches") == round(per_apply):
+        # the record holds for the same GEMM sources, workload, eps, precision and
+        # launch form (the counter runs use the workload's defaults)
+        if rec.get("source_sha1") == gemm_source_hash() and args.eps is None and prec == 0 \
+                and rec.get("launches") == round(per_apply):
             traffic = rec["bytes_per_launch"]
     per_stage = {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]}
     # near-field sum: point pairs (self pairs included, they contribute 0), flops

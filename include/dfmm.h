@@ -275,6 +275,8 @@ typedef struct {
   double flops_m2m;       /* HF-M2M: 8 r_parent r_child per (out-slot, child), per right-hand side */
   double flops_l2l;       /* HF-L2L (into the leaves too): 8 r_child r_parent per (in-slot, parent wedge),
                              per right-hand side */
+  double bytes_l2l_op;    /* HF-L2L operators used (complex64, unpadded r_child x r_parent), once each */
+  double bytes_l2l_vec;   /* HF-L2L vectors per right-hand side: every parent incoming slot read once */
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);

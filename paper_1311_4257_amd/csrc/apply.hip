@@ -738,11 +738,14 @@ struct SlotArgs {
   int waves;          // waves per workgroup (M-tiles per slice)
 };
 constexpr int SLOT_UB = 2;  // staged float4 per thread and term
+// s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: vmcnt bits 3:0 and
+// 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
 
 template <int NT, int PMAX>
 __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* __restrict__ Y) {
   constexpr int NC = NT * 16;
-  extern __shared__ float4 xs[];  // two buffers of NC columns, S4 float4 each
+  extern __shared__ float4 xs[];  // two buffers of NC columns, S4 float4 each, then the group's terms
   const int BS = 64 * a.waves;
   const int tid = int(threadIdx.x);
   const int lane = tid & 63;
@@ -765,8 +768,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     const float2* X;  // column c0 of the source slot
     int KX, Kg, split;
   };
-  auto decode = [&](int t) {
-    const int4 e = a.terms[t];
+  auto decode = [&](const int4 e) {  // e: the term's table entry
     const int kind = (e.z >> 14) & 1;
     Tm r;
     r.KX = kind ? a.KX1 : a.KX0;
@@ -856,19 +858,28 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
   };
 
   if (tb < te) {
+    // the group's term table in LDS (decoding a term is then one broadcast read)
+    int4* tl = reinterpret_cast<int4*>(xs + 2 * NC * S4);
+    for (int i = tid; i < te - tb; i += BS) tl[i] = a.terms[tb + i];
+    __syncthreads();
     float4 ra[PMAX], rb[PMAX];
-    Tm T = decode(tb);
+    Tm T = decode(tl[0]);
     if (act) op_load(T, ra);
     x_load(T);
     x_store(0, T);
     __syncthreads();
-    // two terms per iteration, so that the operator registers alternate statically
+    // two terms per iteration, so that the operator registers alternate statically.
+    // Each half first retires every load in flight (the operator tile issued one
+    // term earlier) and only then issues the next term's loads: the compiler
+    // cannot count the conditional loads, and without this wait it waits for
+    // the prefetch itself before the first product of the term.
     for (int t = tb;;) {
       {
         const bool more = t + 1 < te;
         Tm Tn = T;
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
         if (more) {
-          Tn = decode(t + 1);
+          Tn = decode(tl[t + 1 - tb]);
           if (act) op_load(Tn, rb);
           x_load(Tn);
         }
@@ -882,8 +893,9 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
       {
         const bool more = t + 1 < te;
         Tm Tn = T;
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
         if (more) {
-          Tn = decode(t + 1);
+          Tn = decode(tl[t + 1 - tb]);
           if (act) op_load(Tn, ra);
           x_load(Tn);
         }
@@ -1706,7 +1718,8 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
 constexpr int kSlotMinRhs = 16;  // fast float32 plans take the slot form from this many rhs
 
 static size_t slot_lds_bytes(const SlotGemm& S, int nt) {
-  return size_t(2) * size_t(nt * 16) * size_t(gg_stride(S.Kmax)) * sizeof(float);
+  return size_t(2) * size_t(nt * 16) * size_t(gg_stride(S.Kmax)) * sizeof(float) +
+         size_t(S.max_terms) * sizeof(int4);
 }
 
 // nt column tiles; one wave per M-tile (at most 16 per workgroup: larger ranks

@@ -720,6 +720,18 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
             }
         }
       }
+      // algorithmic bytes of the L2L terms: each (wedge, octant) operator used
+      // once (complex64, unpadded: 8 r_c r_s bytes, the same number as its
+      // flops) and each parent incoming slot read once per rhs
+      {
+        std::set<int32_t> parents;
+        for (int64_t op = 0; op < int64_t(by_op.size()); ++op) {
+          if (by_op[size_t(op)].empty()) continue;
+          info.bytes_l2l_op += op_fl[size_t(op)];
+          for (auto& sd : by_op[size_t(op)]) parents.insert(sd.first);
+        }
+        for (int32_t sidx : parents) info.bytes_l2l_vec += 8.0 * sk[size_t(IS[l].list[size_t(sidx)].second)].r;
+      }
       if (half) {
         std::vector<int32_t> aexp;
         to_half_ops(Md.f, int64_t(ndir) * 8, int64_t(2) * H.Rc * KD * hf_split, P.prec, aexp);

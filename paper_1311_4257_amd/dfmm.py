@@ -59,7 +59,8 @@ class Info(C.Structure):
                 ("flops_m2l_lf", C.c_double), ("plan_seconds", C.c_double),
                 ("device_bytes", C.c_int64), ("bytes_m2l_op", C.c_double),
                 ("bytes_m2l_vec", C.c_double), ("flops_m2l_level", C.c_double * 32), ("tau", C.c_double),
-                ("flops_m2m", C.c_double), ("flops_l2l", C.c_double)]
+                ("flops_m2m", C.c_double), ("flops_l2l", C.c_double),
+                ("bytes_l2l_op", C.c_double), ("bytes_l2l_vec", C.c_double)]
 
 
 _P = C.c_void_p
