@@ -77,6 +77,35 @@ def test_structure_bit_exact(cuda, name, N):
     assert info.w_top == st.w_top
 
 
+def test_structure_points_on_dyadic_faces(cuda):
+    """Points moved exactly onto box faces, edges and corners of every level
+    (interior faces, the centre and the domain's boundary): the library's float64
+    point -> box rule (interior faces to the upper box, the upper boundary
+    clamped) must give the oracle's permutation, boxes, lists, wedges and
+    slots bit for bit."""
+    K = 8.0
+    pts = workloads.sphere_points(8192, K, seed=71)
+    rng = np.random.default_rng(72)
+    st0 = build_structure(pts, K)
+    D = st0.tree.D
+    snapped = 0
+    for i in rng.choice(len(pts), size=len(pts) // 2, replace=False):
+        for ax in rng.choice(3, size=int(rng.integers(1, 4)), replace=False):
+            lev = int(rng.integers(1, D + 1))
+            h = K / 2 ** lev                           # faces of level lev: multiples of h
+            pts[i, ax] = np.trunc(pts[i, ax] / h) * h  # towards 0, so |p| <= K/2 still holds
+            snapped += 1
+    pts[:4] = [[K / 2, 0, 0], [0, K / 2, 0], [0, 0, K / 2], [0, 0, 0]]   # upper boundary (clamped), centre
+    pts[4:7] = [[-K / 2, 0, 0], [0, -K / 2, 0], [0, 0, -K / 2]]          # lower boundary
+    edges = -K / 2 + (K / 2 ** D) * np.arange(2 ** D + 1)
+    on_face = np.isin(pts, edges).any(axis=1)
+    assert on_face.sum() >= len(pts) // 2 and snapped > len(pts) // 2
+    st = build_structure(pts, K)
+    plan = _dfmm().Plan(pts, K, eps=1e-4, cache_dir=CACHE, device=0)
+    _compare_structure(plan, st)
+    assert plan.info().w_top == st.w_top
+
+
 @pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_flat_ellipsoid_meets_eps(cuda, eps):
     """The 4:2:1 ellipsoid of the serving mix (K = 32, N = 131,072, 129 points per

@@ -37,6 +37,28 @@ def _dens(torch, n, nrhs, gen, cuda):
                          torch.randn((nrhs, n), generator=gen, device=cuda))
 
 
+def test_serving_geometries_meet_eps_against_direct_sum(cuda):
+    """The mix's plans against the float64 direct sum of Eq. 1 (not only against
+    themselves): the 4:2:1 ellipsoid plan of the loop tests on every target, and
+    a union of 8 spheres (the serving mix's third geometry, at K = 16) on 1,024
+    sampled targets, both at eps = 1e-4 with 2 rhs."""
+    import torch
+
+    from oracle.kernel import direct_sum, rel_l2
+    from paper_1311_4257_amd import dfmm
+
+    cases = [(workloads.ellipsoid_points(6000, (4.0, 2.0, 1.0), 3), 8.0, None),   # the plan p1 of _plans()
+             (workloads.sphere_union_points(16384, 16.0, 8, 57), 16.0, workloads.sample_targets(16384, 1024, 58))]
+    for pts, K, tg in cases:
+        plan = dfmm.Plan(pts, K, eps=1e-4, cache_dir=CACHE, device=0)
+        f = workloads.densities(len(pts), 2, seed=59)
+        u = plan.apply(torch.from_numpy(f.astype(np.complex64)).to(cuda)).cpu().numpy()
+        ref = direct_sum(pts, f, tg)
+        err = rel_l2(u if tg is None else u[:, tg], ref)
+        print(f"serving geometry N={len(pts)} K={K}: rel L2 {err:.2e}")
+        assert err <= 1e-4
+
+
 def test_apply_batch_matches_separate_applies(cuda):
     import torch
 
