@@ -60,7 +60,10 @@ const char* dfmm_last_error(void);
  * interaction width is <= w_hi.
  *
  * Width argument: w = 0.5 selects the low-frequency skeleton (dir must be 0);
- * w = 1, 2, 4, ... selects a high-frequency width, dir in [0, 6 w^2).
+ * w = 1/4, 1/8, ..., 1/128 the deeper low-frequency widths of adaptive trees
+ * (dir 0; dfmm_opset_set adds them to a set, dfmm_opset_build builds them
+ * when an adaptive plan first needs them); w = 1, 2, 4, ... selects a
+ * high-frequency width, dir in [0, 6 w^2).
  * Point arrays are r x 3 row-major float64; D is r x r row-major complex128
  * stored as interleaved (re, im) doubles.
  * ---------------------------------------------------------------------- */
@@ -99,10 +102,9 @@ typedef struct {
                              measures (dfmm_tune_*.txt, keyed by launch shapes, nrhs, device) */
   int device;             /* HIP device ordinal; -1 = current device */
   int precision;          /* DFMM_PREC_*: arithmetic of the translation GEMMs (default FP32) */
-  double leaf_width;      /* width of the octree leaves in wavelengths; 0 = the default 1/2.  The
-                             low-frequency level of Section 2.2 is one uniform level of boxes of
-                             width 1/2 (the adaptive point-count split is not built), so any
-                             other value returns DFMM_EUNSUPPORTED */
+  double leaf_width;      /* width of the first low-frequency level in wavelengths; 0 = the default
+                             1/2, the only value accepted (DFMM_EUNSUPPORTED otherwise); finer
+                             leaves come from leaf_max */
   double tol_factor;      /* skeleton truncation tau = tol_factor * eps (Eq. 2 holds to tau per
                              translation, Section 2.1; the end-to-end error is a small multiple of
                              it); 0 = the calibrated default (0.1 for eps >= 1e-5, else 0.03);
@@ -111,7 +113,17 @@ typedef struct {
                              exceed it returns DFMM_ENOMEM -- checked on the host before any
                              device allocation against a lower bound of the plan's size (its
                              points and per-point tables), and again against the built plan */
-  int reserved[4];
+  int leaf_max;           /* adaptive low-frequency tree (Section 2.2): a box of width <= 1/2 splits
+                             while it holds more than leaf_max points, down to lf_levels levels below
+                             width 1/2; each LF width has its own skeleton, LF-M2M / LF-L2L run
+                             between the LF levels and leaves of different sizes that are adjacent
+                             at the coarser one's level are summed directly in the near field.
+                             0 = the uniform tree (all leaves of width 1/2).  Float32 plans with
+                             eps >= 1e-5 only (DFMM_EUNSUPPORTED otherwise); an explicit operator set
+                             must then hold the deeper LF skeletons (dfmm_opset_set with
+                             w = 1/4, 1/8, ...) */
+  int lf_levels;          /* levels below width 1/2 an adaptive tree may reach: 1..6, 0 = 3 */
+  int reserved[2];
 } dfmm_options;
 
 /* Arithmetic of the translation GEMMs (M2M, M2L, L2L) of a plan.  FP32: float32
@@ -277,6 +289,9 @@ typedef struct {
                              per right-hand side */
   double bytes_l2l_op;    /* HF-L2L operators used (complex64, unpadded r_child x r_parent), once each */
   double bytes_l2l_vec;   /* HF-L2L vectors per right-hand side: every parent incoming slot read once */
+  int64_t leaves;         /* leaves (= boxes[depth] in a uniform tree) */
+  int depth_max;          /* deepest level with boxes (> depth in an adaptive tree) */
+  int reserved_i;
 } dfmm_info;
 
 int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);
@@ -287,7 +302,11 @@ int dfmm_plan_info(dfmm_plan_t plan, dfmm_info* info);
  *   DFMM_EXPORT_BOXES       int64[nb][5]: (ix, iy, iz, first point, end point), Morton order
  *   DFMM_EXPORT_PAIRS       int64[np][5]: (B, A, dir_in, dir_out, 0), sorted by (B, A);
  *                           boxes are indices into that level's box table; dirs -1 at the leaves
- *   DFMM_EXPORT_NEAR        int64[np][2]: near-field leaf pairs (B, A), sorted
+ *   DFMM_EXPORT_NEAR        int64[np][2]: near-field leaf pairs (B, A), sorted (leaf indices:
+ *                           level-D boxes in a uniform tree, DFMM_EXPORT_LEAVES rows in an
+ *                           adaptive one)
+ *   DFMM_EXPORT_LEAVES      int64[nleaf][4]: (level, box, first point, end point) of every leaf,
+ *                           in point order (adaptive trees; boxes as in DFMM_EXPORT_BOXES)
  *   DFMM_EXPORT_OUT_SLOTS   int64[ns][2]: needed outgoing (box, dir), sorted
  *   DFMM_EXPORT_IN_SLOTS    int64[ns][2]: needed incoming (box, dir), sorted */
 enum {
@@ -296,7 +315,8 @@ enum {
   DFMM_EXPORT_PAIRS = 3,
   DFMM_EXPORT_NEAR = 4,
   DFMM_EXPORT_OUT_SLOTS = 5,
-  DFMM_EXPORT_IN_SLOTS = 6
+  DFMM_EXPORT_IN_SLOTS = 6,
+  DFMM_EXPORT_LEAVES = 7
 };
 int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes);
 

@@ -86,11 +86,14 @@ double tau_for_eps(double eps) { return eps >= 1e-5 ? 0.1 * eps : 0.03 * eps; }
 // 1e-10, 4e-6 at 1e-11), so tighter tau buys nothing.
 double tau_for_eps64(double eps) { return std::max(tau_for_eps(eps), 1e-9); }
 
+// Directions of width w: w = 1, 2, 4, ... -> 6 w^2 (*e = log2 w); the LF
+// widths w = 1/2, 1/4, ..., 2^-(1 + kMaxLfLevels) -> 1 (*e = -1 - log2(1/(2w))).
 int dir_count(double w, int* e) {
-  if (w == 0.5) {
-    *e = -1;
-    return 1;
-  }
+  for (int k = 0; k <= kMaxLfLevels; ++k)
+    if (w == std::ldexp(0.5, -k)) {
+      *e = -1 - k;
+      return 1;
+    }
   if (!(w >= 1.0)) return -1;
   int ee = 0;
   while (std::ldexp(1.0, ee) < w) ++ee;
@@ -105,11 +108,40 @@ std::string cache_path(const char* dir, double tau, int w_hi) {
   return std::string(dir) + buf;
 }
 
+std::string lf_deep_path(const char* dir, double tau) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "/dfmm_lfdeep_tau%.3e_v1.bin", tau);
+  return std::string(dir) + buf;
+}
+
 struct PlanCtx {
   const dfmm_options* opt;
   std::unique_ptr<OpSetImpl> owned;
   const OpSetImpl* used = nullptr;
 };
+
+// The skeletons of the LF widths 1/4 .. 2^-(1 + n) for an adaptive plan: from
+// the caller's set (which must hold them), else built once and cached.
+const std::vector<Skel>* plan_lf_deep(void* vctx, int n) {
+  PlanCtx& c = *static_cast<PlanCtx*>(vctx);
+  if (c.opt->opset) {
+    const auto& v = c.opt->opset->lf_deep;
+    if (int(v.size()) < n) throw Error{DFMM_EINVAL, "operator set lacks the deeper LF skeletons"};
+    for (int i = 0; i < n; ++i)
+      if (v[size_t(i)].r < 1) throw Error{DFMM_EINVAL, "operator set has unset deeper LF skeletons"};
+    return &v;
+  }
+  OpSetImpl& s = *c.owned;
+  if (int(s.lf_deep.size()) >= n) return &s.lf_deep;
+  const char* dir = c.opt->cache_dir ? c.opt->cache_dir : std::getenv("DFMM_CACHE_DIR");
+  if (dir && load_lf_deep(s, lf_deep_path(dir, s.tau), n)) return &s.lf_deep;
+  build_lf_deep(s, kMaxLfLevels);
+  if (dir) {
+    ::mkdir(dir, 0755);
+    (void)save_lf_deep(s, lf_deep_path(dir, s.tau));
+  }
+  return &s.lf_deep;
+}
 
 const OpSetImpl* plan_ops(void* vctx, int w_needed) {
   PlanCtx& c = *static_cast<PlanCtx*>(vctx);
@@ -209,7 +241,12 @@ static Skel* find_skel(dfmm_opset_t set, double w, int dir) {
   int e = 0;
   int n = dir_count(w, &e);
   if (n < 0 || dir < 0 || dir >= n) return nullptr;
-  if (e < 0) return &set->lf;
+  if (e == -1) return &set->lf;
+  if (e < -1) {  // a deeper LF width: the set grows to hold it
+    const size_t k = size_t(-1 - e);
+    if (set->lf_deep.size() < k) set->lf_deep.resize(k);
+    return &set->lf_deep[k - 1];
+  }
   if (e >= int(set->hf.size())) return nullptr;
   return &set->hf[e][dir];
 }
@@ -231,6 +268,9 @@ int dfmm_opset_set(dfmm_opset_t set, double w, int dir, int r, const double* a, 
 int dfmm_opset_get(dfmm_opset_t set, double w, int dir, int* r, double* a, double* b, double* D) {
   return guarded([&]() {
     if (!set || !r) return fail(DFMM_EINVAL, "bad argument");
+    int e = 0;
+    if (dir_count(w, &e) == 1 && e < -1 && size_t(-1 - e) > set->lf_deep.size())
+      return fail(DFMM_EINVAL, "no such width / direction in this set");
     Skel* s = find_skel(set, w, dir);
     if (!s) return fail(DFMM_EINVAL, "no such width / direction in this set");
     *r = s->r;
@@ -308,8 +348,10 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
         return fail(DFMM_EDOMAIN, "point " + std::to_string(i) + " lies outside |p| <= K/2");
     }
     if (!(opt->leaf_width == 0.0 || opt->leaf_width == 0.5))
-      return fail(DFMM_EUNSUPPORTED, "leaf_width must be 1/2 (0 = default): the low-frequency level is one "
-                                     "uniform level of width 1/2");
+      return fail(DFMM_EUNSUPPORTED, "leaf_width must be 1/2 (0 = default): the first low-frequency level "
+                                     "has width 1/2 (finer leaves come from leaf_max)");
+    if (opt->leaf_max < 0 || opt->lf_levels < 0 || opt->lf_levels > kMaxLfLevels)
+      return fail(DFMM_EINVAL, "leaf_max must be >= 0 and lf_levels in [0, " + std::to_string(kMaxLfLevels) + "]");
     if (!opt->opset && !(opt->tol_factor == 0.0 || (opt->tol_factor > 0.0 && opt->tol_factor <= 1.0)))
       return fail(DFMM_EINVAL, "tol_factor must be in (0, 1] (0 = default)");
     // HBM budget, checked before any device call: sorted points (hi + lo float4
@@ -327,6 +369,8 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
       return fail(DFMM_EINVAL, "unknown precision");
     if ((opt->precision == DFMM_PREC_FP16X3 || opt->precision == DFMM_PREC_BF16X3) && precise)
       return fail(DFMM_EINVAL, "split precision is for eps >= 1e-5 plans");
+    if (opt->leaf_max > 0 && (opt->precision != DFMM_PREC_FP32 || precise))
+      return fail(DFMM_EUNSUPPORTED, "adaptive trees (leaf_max > 0) are for float32 plans with eps >= 1e-5");
     int dev = opt->device;
     if (dev < 0) DFMM_HIP(hipGetDevice(&dev));
     DeviceScope on(dev);
@@ -336,7 +380,9 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
     P->prec = opt->precision;
     if (const char* dir = opt->cache_dir ? opt->cache_dir : std::getenv("DFMM_CACHE_DIR")) P->tune_dir = dir;
     PlanCtx ctx{opt, nullptr, nullptr};
-    build_plan(*P, points, N, K, &plan_ops, &ctx);
+    P->leaf_max = opt->leaf_max;
+    P->lf_levels = opt->leaf_max > 0 ? (opt->lf_levels > 0 ? opt->lf_levels : 3) : 0;
+    build_plan(*P, points, N, K, &plan_ops, &plan_lf_deep, &ctx);
     if (opt->hbm_budget_bytes > 0 && uint64_t(P->info.device_bytes) > opt->hbm_budget_bytes)
       return fail(DFMM_ENOMEM, "the plan holds " + std::to_string(P->info.device_bytes) +
                                    " device bytes; hbm_budget_bytes is " + std::to_string(opt->hbm_budget_bytes));
@@ -477,11 +523,13 @@ int dfmm_export(dfmm_plan_t plan, int what, int level, void* buf, size_t* bytes)
     if (!plan || !bytes) return fail(DFMM_EINVAL, "null argument");
     const std::vector<int64_t>* v = nullptr;
     auto lvl_ok = [&]() { return level >= 0 && level <= plan->D; };
+    auto any_lvl = [&]() { return level >= 0 && level < int(plan->boxes.size()); };  // LF levels below D too
     switch (what) {
       case DFMM_EXPORT_PERM: v = &plan->perm; break;
-      case DFMM_EXPORT_BOXES: if (lvl_ok()) v = &plan->boxes[level]; break;
-      case DFMM_EXPORT_PAIRS: if (lvl_ok()) v = &plan->pairs[level]; break;
+      case DFMM_EXPORT_BOXES: if (any_lvl()) v = &plan->boxes[level]; break;
+      case DFMM_EXPORT_PAIRS: if (any_lvl()) v = &plan->pairs[level]; break;
       case DFMM_EXPORT_NEAR: v = &plan->near; break;
+      case DFMM_EXPORT_LEAVES: v = &plan->leaves; break;
       case DFMM_EXPORT_OUT_SLOTS: if (lvl_ok()) v = &plan->out_slots[level]; break;
       case DFMM_EXPORT_IN_SLOTS: if (lvl_ok()) v = &plan->in_slots[level]; break;
       default: break;

@@ -124,12 +124,18 @@ __device__ __forceinline__ void put_w(double2* p, double re, double im) { *p = m
 template <class WT>  // float2 (float32 plans) or double2 (float64 plans)
 __global__ void __launch_bounds__(LW_BS) k_leaf_weights(const double* __restrict__ pts, const int* __restrict__ lstart,
                                                          const float4* __restrict__ lcen,
-                                                         const double4* __restrict__ a_lf,
-                                                         const double2* __restrict__ DT, int R, int Ra,
-                                                         WT* __restrict__ V, WT* __restrict__ W) {
+                                                         const double4* __restrict__ a_all,
+                                                         const double2* __restrict__ DT_all,
+                                                         const int* __restrict__ ra, const int* __restrict__ sk_of,
+                                                         int R, WT* __restrict__ V, WT* __restrict__ W) {
   extern __shared__ double2 gs[];  // Ra
   const int b = blockIdx.x;
   const float4 c = lcen[b];
+  // this leaf's skeleton (one per LF width): check points at R offsets, D^T at R R
+  const int sk = sk_of[b];
+  const int Ra = ra[sk];
+  const double4* __restrict__ a_lf = a_all + int64_t(sk) * R;
+  const double2* __restrict__ DT = DT_all + int64_t(sk) * R * R;
   for (int j = lstart[b]; j < lstart[b + 1]; ++j) {
     const double x = pts[3 * int64_t(j)] - double(c.x);
     const double y = pts[3 * int64_t(j) + 1] - double(c.y);
@@ -171,9 +177,10 @@ constexpr int S2M_BS = 128;
 template <int RC>  // right-hand sides per pass
 __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, const float2* __restrict__ V,
                                                  const float2* __restrict__ fs, int R, int nrhs,
-                                                 float2* __restrict__ clf) {
+                                                 const int* __restrict__ gid, float2* __restrict__ clf) {
   constexpr int SU = RC <= 8 ? 4 : 1;  // sources per loaded batch
   const int b = blockIdx.x;
+  const int bo = gid ? gid[b] : b;  // the leaf's LF vector (adaptive trees)
   const int s0 = lstart[b], s1 = lstart[b + 1];
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int nk = min(RC, nrhs - k0);
@@ -200,7 +207,7 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
       }
 #pragma unroll
       for (int k = 0; k < RC; ++k)
-        if (k < nk) clf[(int64_t(b) * nrhs + k0 + k) * R + p] = acc[k];
+        if (k < nk) clf[(int64_t(bo) * nrhs + k0 + k) * R + p] = acc[k];
     }
   }
 }
@@ -736,6 +743,7 @@ struct SlotArgs {
   int cpg;            // column chunks per group
   int S4;             // LDS column stride in float4
   int waves;          // waves per workgroup (M-tiles per slice)
+  const int* gdst;    // output vector of each group (null: the group's own index)
 };
 constexpr int SLOT_UB = 2;  // staged float4 per thread and term
 // s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: vmcnt bits 3:0 and
@@ -910,6 +918,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
   }
   // lane (j, kr) holds real rows 4 kr .. 4 kr + 3 (complex rows 2 kr, 2 kr + 1) of
   // tile m for column j of each column tile; tiles past M_g are written as zeros
+  const int gy = a.gdst ? a.gdst[g] : g;
   if (m < a.M / 8) {
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
@@ -917,7 +926,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
       if (col < nc) {
         float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
         if (act) o = make_float4(float(a64[n][0]), float(a64[n][1]), float(a64[n][2]), float(a64[n][3]));
-        reinterpret_cast<float4*>(Y + (int64_t(g) * nrhs + c0 + col) * a.M + 8 * m + 2 * kr)[0] = o;
+        reinterpret_cast<float4*>(Y + (int64_t(gy) * nrhs + c0 + col) * a.M + 8 * m + 2 * kr)[0] = o;
       }
     }
   }
@@ -982,6 +991,9 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 }
 
 constexpr int EV_CHUNK = 256;  // source points staged in LDS at a time
+// near leaves whose point ranges are tabled at a time (the lookup of the leaf
+// holding a staged point searches 32 entries)
+constexpr int NB_CHUNK = 32;
 constexpr int EV_SUM = 16;     // fast plans: products summed in float32 this many at a time
 // Separations come from the hi/lo float parts of the points: the hi parts of a
 // close pair subtract exactly, so even a pair at distance 0.01 keeps its
@@ -1006,26 +1018,9 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
   const int tl = lane & 15, sl = lane >> 4;
   const int s0 = lstart[b], s1 = lstart[b + 1];
   const int n0 = nstart[b];
-  const int nn = min(nstart[b + 1] - n0, EV_BS);  // adjacent leaves (at most 27)
-  // all neighbour ranges at once; offsets by a wave prefix sum
-  {
-    int beg = 0, cnt = 0;
-    if (lane < nn) {
-      const int A = nsrc[n0 + lane];
-      beg = lstart[A];
-      cnt = lstart[A + 1] - beg;
-    }
-    int incl = cnt;
-    for (int d = 1; d < EV_BS; d <<= 1) {
-      const int v = __shfl_up(incl, d, EV_BS);
-      if (lane >= d) incl += v;
-    }
-    nb_beg[lane] = beg;
-    nb_off[lane] = incl - cnt;
-    if (lane == EV_BS - 1) nb_off[EV_BS] = incl;
-  }
-  __syncthreads();
-  const int total = nb_off[nn];
+  // near leaves: 27 at most in a uniform tree, more for a coarse leaf of an
+  // adaptive one; their point ranges are tabled NB_CHUNK leaves at a time
+  const int ntot = nstart[b + 1] - n0;
   for (int k0 = 0; k0 < nrhs; k0 += RC) {
     const int nk = min(RC, nrhs - k0);
     for (int t0 = s0; t0 < s1; t0 += 16) {
@@ -1036,65 +1031,87 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
       double ar[RC], ai[RC];
 #pragma unroll
       for (int k = 0; k < RC; ++k) ar[k] = ai[k] = 0.0;
-      // near field: the adjacent leaves' points are staged in LDS chunk by chunk
-      for (int base = 0; base < total; base += EV_CHUNK) {
-        const int fill = min(EV_CHUNK, total - base);
-        __syncthreads();
-        for (int i = lane; i < fill; i += EV_BS) {
-          const int gidx = base + i;
-          int kk = 0;  // the neighbour holding element gidx: largest kk with nb_off[kk] <= gidx
-#pragma unroll
-          for (int step = 16; step > 0; step >>= 1)
-            if (kk + step < nn && nb_off[kk + step] <= gidx) kk += step;
-          const int j = nb_beg[kk] + (gidx - nb_off[kk]);
-          sh[i] = phi[j];
-          sq[i] = plo[j];
-          for (int k = 0; k < nk; ++k) sf[i * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
+      for (int c0 = 0; c0 < ntot; c0 += NB_CHUNK) {
+        const int nn = min(NB_CHUNK, ntot - c0);
+        __syncthreads();  // the previous tables and points are consumed
+        {  // this chunk's neighbour ranges; offsets by a wave prefix sum
+          int beg = 0, cnt = 0;
+          if (lane < nn) {
+            const int A = nsrc[n0 + c0 + lane];
+            beg = lstart[A];
+            cnt = lstart[A + 1] - beg;
+          }
+          int incl = cnt;
+          for (int d = 1; d < EV_BS; d <<= 1) {
+            const int v = __shfl_up(incl, d, EV_BS);
+            if (lane >= d) incl += v;
+          }
+          nb_beg[lane] = beg;
+          nb_off[lane] = incl - cnt;
+          if (lane == EV_BS - 1) nb_off[EV_BS] = incl;
         }
         __syncthreads();
-        if constexpr (PRECISE) {  // 1/r and the products in float64
-          for (int i = sl; i < fill; i += 4) {
-            const float4 h = sh[i], l = sq[i];
-            const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
-            const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
-            const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
-            const double2 gg = green_d(dx, dy, dz);
+        const int total = nb_off[nn];
+        // the chunk's points are staged in LDS EV_CHUNK at a time
+        for (int base = 0; base < total; base += EV_CHUNK) {
+          const int fill = min(EV_CHUNK, total - base);
+          __syncthreads();
+          for (int i = lane; i < fill; i += EV_BS) {
+            const int gidx = base + i;
+            int kk = 0;  // the neighbour holding element gidx: largest kk with nb_off[kk] <= gidx
 #pragma unroll
-            for (int k = 0; k < RC; ++k) {
-              if (k < nk) {
-                const float2 fk = sf[i * RC + k];
-                ar[k] += gg.x * double(fk.x) - gg.y * double(fk.y);
-                ai[k] += gg.x * double(fk.y) + gg.y * double(fk.x);
-              }
-            }
+            for (int step = 16; step > 0; step >>= 1)
+              if (kk + step < nn && nb_off[kk + step] <= gidx) kk += step;
+            const int j = nb_beg[kk] + (gidx - nb_off[kk]);
+            sh[i] = phi[j];
+            sq[i] = plo[j];
+            for (int k = 0; k < nk; ++k) sf[i * RC + k] = fs[int64_t(j) * nrhs + k0 + k];
           }
-        } else {
-          for (int i0 = sl; i0 < fill; i0 += 4 * EV_SUM) {
-            const int i1 = min(fill, i0 + 4 * EV_SUM);
-            float cr[RC], ci[RC];
-#pragma unroll
-            for (int k = 0; k < RC; ++k) cr[k] = ci[k] = 0.f;
-            for (int i = i0; i < i1; i += 4) {
+          __syncthreads();
+          if constexpr (PRECISE) {  // 1/r and the products in float64
+            for (int i = sl; i < fill; i += 4) {
               const float4 h = sh[i], l = sq[i];
-              const float2 gg = green_f((th.x - h.x) + (tq.x - l.x), (th.y - h.y) + (tq.y - l.y),
-                                        (th.z - h.z) + (tq.z - l.z));
+              const double dx = (double(th.x) - double(h.x)) + (double(tq.x) - double(l.x));
+              const double dy = (double(th.y) - double(h.y)) + (double(tq.y) - double(l.y));
+              const double dz = (double(th.z) - double(h.z)) + (double(tq.z) - double(l.z));
+              const double2 gg = green_d(dx, dy, dz);
 #pragma unroll
               for (int k = 0; k < RC; ++k) {
                 if (k < nk) {
                   const float2 fk = sf[i * RC + k];
-                  cr[k] = fmaf(gg.x, fk.x, fmaf(-gg.y, fk.y, cr[k]));
-                  ci[k] = fmaf(gg.x, fk.y, fmaf(gg.y, fk.x, ci[k]));
+                  ar[k] += gg.x * double(fk.x) - gg.y * double(fk.y);
+                  ai[k] += gg.x * double(fk.y) + gg.y * double(fk.x);
                 }
               }
             }
+          } else {
+            for (int i0 = sl; i0 < fill; i0 += 4 * EV_SUM) {
+              const int i1 = min(fill, i0 + 4 * EV_SUM);
+              float cr[RC], ci[RC];
 #pragma unroll
-            for (int k = 0; k < RC; ++k) {
-              ar[k] += cr[k];
-              ai[k] += ci[k];
+              for (int k = 0; k < RC; ++k) cr[k] = ci[k] = 0.f;
+              for (int i = i0; i < i1; i += 4) {
+                const float4 h = sh[i], l = sq[i];
+                const float2 gg = green_f((th.x - h.x) + (tq.x - l.x), (th.y - h.y) + (tq.y - l.y),
+                                          (th.z - h.z) + (tq.z - l.z));
+#pragma unroll
+                for (int k = 0; k < RC; ++k) {
+                  if (k < nk) {
+                    const float2 fk = sf[i * RC + k];
+                    cr[k] = fmaf(gg.x, fk.x, fmaf(-gg.y, fk.y, cr[k]));
+                    ci[k] = fmaf(gg.x, fk.y, fmaf(gg.y, fk.x, ci[k]));
+                  }
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < RC; ++k) {
+                ar[k] += cr[k];
+                ai[k] += ci[k];
+              }
             }
           }
         }
-      }
+      }  // neighbour chunks
 #pragma unroll
       for (int k = 0; k < RC; ++k) {
         ar[k] += shfl_xor_d(ar[k], 16);
@@ -1146,30 +1163,14 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int n0 = nstart[b];
-  const int nn = min(nstart[b + 1] - n0, 64);  // adjacent leaves (at most 27)
-  if (w == 0) {  // neighbour ranges and their offsets (wave prefix sum)
-    int beg = 0, cnt = 0;
-    if (lane < nn) {
-      const int A = nsrc[n0 + lane];
-      beg = lstart[A];
-      cnt = lstart[A + 1] - beg;
-    }
-    int incl = cnt;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int v = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += v;
-    }
-    nb_beg[lane] = beg;
-    nb_off[lane] = incl - cnt;
-    if (lane == 63) nb_off[64] = incl;
-  }
+  // near leaves: 27 at most in a uniform tree, more for a coarse leaf of an
+  // adaptive one; their point ranges are tabled NB_CHUNK leaves at a time
+  const int ntot = nstart[b + 1] - n0;
   for (int i = threadIdx.x; i < NM_TB; i += 64 * NM_NW) {
     const int t = min(s0 + i, s1 - 1);
     th[i] = phi[t];
     tq[i] = plo[t];
   }
-  __syncthreads();
-  const int total = nb_off[nn];
   const int ntiles = (s1 - s0 + 7) / 8;
   const int rr = lane & 15, kk = lane >> 4;  // A row / B column, k index of this lane
   const int tr = rr >> 1, kp = kk & 1;       // target of the row, Re/Im part of k
@@ -1185,164 +1186,186 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
       for (int r = 0; r < 4; ++r) a64[i][c][r] = 0.0;
     }
   float2* gw = sg + w * 8 * GS;
-  for (int base = 0; base < total; base += NM_SC) {
-    const int fill = min(NM_SC, total - base);
-    __syncthreads();  // the previous chunk is consumed
-    if (threadIdx.x < NM_SC) {
-      const int i = threadIdx.x;
-      int j = -1;
-      if (i < fill) {
-        const int g = base + i;
-        int q = 0;  // the neighbour holding element g: largest q with nb_off[q] <= g
-#pragma unroll
-        for (int step = 16; step > 0; step >>= 1)
-          if (q + step < nn && nb_off[q + step] <= g) q += step;
-        j = nb_beg[q] + (g - nb_off[q]);
-        sh[i] = phi[j];
-        sq[i] = plo[j];
+  for (int c0n = 0; c0n < ntot; c0n += NB_CHUNK) {
+    const int nn = min(NB_CHUNK, ntot - c0n);
+    __syncthreads();  // the previous tables and points are consumed
+    if (w == 0) {  // this chunk's neighbour ranges and their offsets (wave prefix sum)
+      int beg = 0, cnt = 0;
+      if (lane < nn) {
+        const int A = nsrc[n0 + c0n + lane];
+        beg = lstart[A];
+        cnt = lstart[A + 1] - beg;
       }
-      sj[i] = j;
+      int incl = cnt;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+      }
+      nb_beg[lane] = beg;
+      nb_off[lane] = incl - cnt;
+      if (lane == 63) nb_off[64] = incl;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
-      const int i = e / NCOL, c = e % NCOL;
-      const int j = sj[i];
-      sf[e] = (j >= 0 && c0 + c < nrhs) ? fs[int64_t(j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    if constexpr (PREC != 0) {  // densities as (hi re | hi im, lo re | lo im) words, scaled per column
-      if (threadIdx.x < NCOL) {
-        int e = 0;
-        if constexpr (PREC == PREC_F16) {
-          float mx = 0.f;
-          for (int i = 0; i < NM_SC; ++i) {
-            const float2 v = sf[i * NCOL + threadIdx.x];
-            mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
-          }
-          if (mx > 0.f) {
-            int E;
-            (void)frexpf(mx, &E);
-            e = 14 - E;
-          }
+    const int total = nb_off[nn];
+    for (int base = 0; base < total; base += NM_SC) {
+      const int fill = min(NM_SC, total - base);
+      __syncthreads();  // the previous chunk is consumed
+      if (threadIdx.x < NM_SC) {
+        const int i = threadIdx.x;
+        int j = -1;
+        if (i < fill) {
+          const int g = base + i;
+          int q = 0;  // the neighbour holding element g: largest q with nb_off[q] <= g
+#pragma unroll
+          for (int step = 16; step > 0; step >>= 1)
+            if (q + step < nn && nb_off[q + step] <= g) q += step;
+          j = nb_beg[q] + (g - nb_off[q]);
+          sh[i] = phi[j];
+          sq[i] = plo[j];
         }
-        fexp[threadIdx.x] = e;
+        sj[i] = j;
       }
       __syncthreads();
       for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
-        const int x = fexp[e % NCOL];
-        const float2 v = sf[e];
-        unsigned hi, lo;
-        split_pair<PREC>(ldexpf(v.x, x), ldexpf(v.y, x), hi, lo);
-        sf[e] = make_float2(__uint_as_float(hi), __uint_as_float(lo));
+        const int i = e / NCOL, c = e % NCOL;
+        const int j = sj[i];
+        sf[e] = (j >= 0 && c0 + c < nrhs) ? fs[int64_t(j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
       }
       __syncthreads();
-    }
-    const bool sval = lane < fill;
-    const float4 h = sh[lane], l = sq[lane];
-#pragma unroll
-    for (int i = 0; i < NM_MAXT; ++i) {
-      const int rt = w + NM_NW * i;
-      if (rt >= ntiles) break;
-      // G for this tile's 8 targets and this lane's source
-      float2 gv[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float4 a = th[rt * 8 + t], c = tq[rt * 8 + t];
-        gv[t] = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
-        if (!sval || s0 + rt * 8 + t >= s1) gv[t] = make_float2(0.f, 0.f);
-      }
-      int eg = 0;  // 16-bit plans: the tile's scale exponent (largest |G| below 2^14)
-      if constexpr (PREC == PREC_F16) {
-        float mx = 0.f;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) mx = fmaxf(mx, fmaxf(fabsf(gv[t].x), fabsf(gv[t].y)));
-#pragma unroll
-        for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
-        if (mx > 0.f) {
-          int E;
-          (void)frexpf(mx, &E);
-          eg = 14 - E;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        float2 g = gv[t];
-        if constexpr (PREC != 0) {  // (hi re | hi im, lo re | lo im) words
-          unsigned hi, lo;
-          split_pair<PREC>(ldexpf(g.x, eg), ldexpf(g.y, eg), hi, lo);
-          g = make_float2(__uint_as_float(hi), __uint_as_float(lo));
-        }
-        gw[t * GS + lane] = g;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if constexpr (PREC != 0) {
-        // products: one 16x16x32 MFMA per term covers 16 sources; lane k-group kk
-        // holds sources 4 kk .. 4 kk + 3 of the block, (Re, Im) each
-        float osc[NCT];
-#pragma unroll
-        for (int c = 0; c < NCT; ++c) osc[c] = ldexpf(1.0f, -(eg + fexp[c * 16 + rr]));
-        constexpr unsigned SG = 0x80000000u;
-#pragma unroll 1
-        for (int q = 0; q < NM_SC / 16; ++q) {
-          const int sb = 16 * q + 4 * kk;
-          unsigned ah[4], al[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float2 g = gw[tr * GS + sb + e];
-            const unsigned h = __float_as_uint(g.x), o = __float_as_uint(g.y);
-            ah[e] = rodd ? rot16(h) : (h ^ SG);  // even row (Re G, -Im G), odd row (Im G, Re G)
-            al[e] = rodd ? rot16(o) : (o ^ SG);
+      if constexpr (PREC != 0) {  // densities as (hi re | hi im, lo re | lo im) words, scaled per column
+        if (threadIdx.x < NCOL) {
+          int e = 0;
+          if constexpr (PREC == PREC_F16) {
+            float mx = 0.f;
+            for (int i = 0; i < NM_SC; ++i) {
+              const float2 v = sf[i * NCOL + threadIdx.x];
+              mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+            }
+            if (mx > 0.f) {
+              int E;
+              (void)frexpf(mx, &E);
+              e = 14 - E;
+            }
           }
-          const v4u av = {ah[0], ah[1], ah[2], ah[3]}, aw = {al[0], al[1], al[2], al[3]};
+          fexp[threadIdx.x] = e;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
+          const int x = fexp[e % NCOL];
+          const float2 v = sf[e];
+          unsigned hi, lo;
+          split_pair<PREC>(ldexpf(v.x, x), ldexpf(v.y, x), hi, lo);
+          sf[e] = make_float2(__uint_as_float(hi), __uint_as_float(lo));
+        }
+        __syncthreads();
+      }
+      const bool sval = lane < fill;
+      const float4 h = sh[lane], l = sq[lane];
 #pragma unroll
-          for (int c = 0; c < NCT; ++c) {
-            unsigned bh[4], bl[4];
+      for (int i = 0; i < NM_MAXT; ++i) {
+        const int rt = w + NM_NW * i;
+        if (rt >= ntiles) break;
+        // G for this tile's 8 targets and this lane's source
+        float2 gv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float4 a = th[rt * 8 + t], c = tq[rt * 8 + t];
+          gv[t] = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
+          if (!sval || s0 + rt * 8 + t >= s1) gv[t] = make_float2(0.f, 0.f);
+        }
+        int eg = 0;  // 16-bit plans: the tile's scale exponent (largest |G| below 2^14)
+        if constexpr (PREC == PREC_F16) {
+          float mx = 0.f;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) mx = fmaxf(mx, fmaxf(fabsf(gv[t].x), fabsf(gv[t].y)));
+#pragma unroll
+          for (int m = 32; m > 0; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+          if (mx > 0.f) {
+            int E;
+            (void)frexpf(mx, &E);
+            eg = 14 - E;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          float2 g = gv[t];
+          if constexpr (PREC != 0) {  // (hi re | hi im, lo re | lo im) words
+            unsigned hi, lo;
+            split_pair<PREC>(ldexpf(g.x, eg), ldexpf(g.y, eg), hi, lo);
+            g = make_float2(__uint_as_float(hi), __uint_as_float(lo));
+          }
+          gw[t * GS + lane] = g;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if constexpr (PREC != 0) {
+          // products: one 16x16x32 MFMA per term covers 16 sources; lane k-group kk
+          // holds sources 4 kk .. 4 kk + 3 of the block, (Re, Im) each
+          float osc[NCT];
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) osc[c] = ldexpf(1.0f, -(eg + fexp[c * 16 + rr]));
+          constexpr unsigned SG = 0x80000000u;
+#pragma unroll 1
+          for (int q = 0; q < NM_SC / 16; ++q) {
+            const int sb = 16 * q + 4 * kk;
+            unsigned ah[4], al[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const float2 f = sf[(sb + e) * NCOL + c * 16 + rr];
-              bh[e] = __float_as_uint(f.x);
-              bl[e] = __float_as_uint(f.y);
+              const float2 g = gw[tr * GS + sb + e];
+              const unsigned h = __float_as_uint(g.x), o = __float_as_uint(g.y);
+              ah[e] = rodd ? rot16(h) : (h ^ SG);  // even row (Re G, -Im G), odd row (Im G, Re G)
+              al[e] = rodd ? rot16(o) : (o ^ SG);
             }
-            const v4u bv = {bh[0], bh[1], bh[2], bh[3]}, bw = {bl[0], bl[1], bl[2], bl[3]};
-            v4f a = mfma16<PREC>(av, bv, v4f{0.f, 0.f, 0.f, 0.f});
-            a = mfma16<PREC>(av, bw, a);
-            a = mfma16<PREC>(aw, bv, a);
+            const v4u av = {ah[0], ah[1], ah[2], ah[3]}, aw = {al[0], al[1], al[2], al[3]};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a64[i][c][r] += double(a[r] * osc[c]);
+            for (int c = 0; c < NCT; ++c) {
+              unsigned bh[4], bl[4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const float2 f = sf[(sb + e) * NCOL + c * 16 + rr];
+                bh[e] = __float_as_uint(f.x);
+                bl[e] = __float_as_uint(f.y);
+              }
+              const v4u bv = {bh[0], bh[1], bh[2], bh[3]}, bw = {bl[0], bl[1], bl[2], bl[3]};
+              v4f a = mfma16<PREC>(av, bv, v4f{0.f, 0.f, 0.f, 0.f});
+              a = mfma16<PREC>(av, bw, a);
+              a = mfma16<PREC>(aw, bv, a);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) a64[i][c][r] += double(a[r] * osc[c]);
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          continue;
+        }
+        // products: MFMA step q covers sources 2q, 2q + 1
+#pragma unroll 4
+        for (int q = 0; q < NM_SC / 2; ++q) {
+          const int src = 2 * q + (kk >> 1);
+          const float2 g = gw[tr * GS + src];
+          const float av = rodd ? (kp ? g.x : g.y) : (kp ? -g.y : g.x);
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) {
+            const float2 f = sf[src * NCOL + c * 16 + rr];
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, kp ? f.y : f.x, acc[i][c], 0, 0, 0);
+          }
+          if ((q & 7) == 7) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) a64[i][c][r] += double(acc[i][c][r]);
+              acc[i][c] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        continue;
       }
-      // products: MFMA step q covers sources 2q, 2q + 1
-#pragma unroll 4
-      for (int q = 0; q < NM_SC / 2; ++q) {
-        const int src = 2 * q + (kk >> 1);
-        const float2 g = gw[tr * GS + src];
-        const float av = rodd ? (kp ? g.x : g.y) : (kp ? -g.y : g.x);
-#pragma unroll
-        for (int c = 0; c < NCT; ++c) {
-          const float2 f = sf[src * NCOL + c * 16 + rr];
-          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, kp ? f.y : f.x, acc[i][c], 0, 0, 0);
-        }
-        if ((q & 7) == 7) {
-#pragma unroll
-          for (int c = 0; c < NCT; ++c) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a64[i][c][r] += double(acc[i][c][r]);
-            acc[i][c] = v4f{0.f, 0.f, 0.f, 0.f};
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-  }
+  }  // neighbour chunks
   // lane holds rows 4 kk .. 4 kk + 3 = (Re, Im) of targets 2 kk, 2 kk + 1, column rr
 #pragma unroll
   for (int i = 0; i < NM_MAXT; ++i) {
@@ -1406,19 +1429,20 @@ __global__ void __launch_bounds__(L2T_BS) k_l2t(const float2* __restrict__ W, co
 // re-reading them for every right-hand side; 16 lanes per target and the same
 // summation order as k_l2t.
 __global__ void __launch_bounds__(L2T_BS) k_l2t_leaf(const float2* __restrict__ W, const float2* __restrict__ ulf,
-                                                      const int* __restrict__ lstart,
+                                                      const int* __restrict__ lstart, const int* __restrict__ gid,
                                                       const double2* __restrict__ unear,
                                                       const int* __restrict__ perm, int R, int nrhs, int kc,
                                                       int64_t N, const ReqTable Q) {
   extern __shared__ float2 us[];  // [kc][R]
   const int b = blockIdx.x;
+  const int bo = gid ? gid[b] : b;  // the leaf's LF vector (adaptive trees)
   const int s0 = lstart[b], s1 = lstart[b + 1];
   const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
   const int nq = (R - l + 15) / 16;
   for (int k0 = 0; k0 < nrhs; k0 += kc) {
     const int nk = min(kc, nrhs - k0);
     __syncthreads();  // the previous rows are consumed
-    const float2* src = ulf + (int64_t(b) * nrhs + k0) * R;
+    const float2* src = ulf + (int64_t(bo) * nrhs + k0) * R;
     for (int i = threadIdx.x; i < nk * R; i += L2T_BS) us[i] = src[i];
     __syncthreads();
     for (int t = s0 + g; t < s1; t += L2T_BS / 16) {
@@ -1509,6 +1533,7 @@ struct LaunchSet {
   bool slot = false;                  // slot form: M2M, and M2L + L2L per level, without pair outputs
   std::vector<SlotLaunch> up, down;   // per HF level
   SlotLaunch lf_down;
+  std::vector<SlotLaunch> lfd_up, lfd_down;  // per LF level below width 1/2 (adaptive trees)
 };
 
 // The M2L problems of a plan in apply order: HF levels from the top down, then
@@ -1743,6 +1768,15 @@ static bool prepare_slot(SlotLaunch& L, const SlotGemm& S, int nrhs, int nt) {
 // The slot form serves fast float32 plans with at least kSlotMinRhs right-hand
 // sides (DFMM_SLOT=0 forces the pair form, =1 allows it from 1 rhs).
 static bool use_slot(const dfmm_plan_s& P, int nrhs) {
+  if (P.leaf_max > 0) {  // adaptive trees run the LF levels in the slot form only
+    const int nt = nrhs >= 32 ? 2 : 1;
+    SlotLaunch tmp;
+    bool ok = prepare_slot(tmp, P.lf.down, nrhs, nt);
+    for (const auto& H : P.hf) ok = ok && prepare_slot(tmp, H.up, nrhs, nt) && prepare_slot(tmp, H.down, nrhs, nt);
+    for (const auto& Q : P.lfd) ok = ok && prepare_slot(tmp, Q.up, nrhs, nt) && prepare_slot(tmp, Q.down, nrhs, nt);
+    if (!ok) throw Error{DFMM_EUNSUPPORTED, "an adaptive plan's slot-form launches exceed the kernel's limits"};
+    return true;
+  }
   if (P.precise || P.prec != DFMM_PREC_FP32) return false;
   int minr = kSlotMinRhs;
   if (const char* e = std::getenv("DFMM_SLOT")) {
@@ -1767,11 +1801,12 @@ static void launch_slot_t(const SlotLaunch& L, const SlotArgs& a, int nrhs, floa
 
 // kind 0: operators A0 on source vectors X0 (row stride KX0); kind 1 likewise
 static void launch_slot(const SlotLaunch& L, const float4* A0, const float2* X0, int KX0, const float4* A1,
-                        const float2* X1, int KX1, int nrhs, float2* Y, bool m2l, hipStream_t st) {
+                        const float2* X1, int KX1, int nrhs, float2* Y, bool m2l, hipStream_t st,
+                        const int* gdst = nullptr) {
   if (L.nchunks == 0) return;
   const SlotGemm& S = *L.S;
   SlotArgs a{S.order.as<int>(), S.t0.as<int>(), S.gm.as<int>(), S.terms.as<int4>(), A0, A1 ? A1 : A0, X0,
-             X1 ? X1 : X0, KX0, X1 ? KX1 : KX0, S.M, L.cpg, gg_stride(S.Kmax) / 4, L.waves};
+             X1 ? X1 : X0, KX0, X1 ? KX1 : KX0, S.M, L.cpg, gg_stride(S.Kmax) / 4, L.waves, gdst};
   if (L.nt == 2) {
     if (L.pmax == 4) launch_slot_t<2, 4>(L, a, nrhs, Y, m2l, st);
     else if (L.pmax == 7) launch_slot_t<2, 7>(L, a, nrhs, Y, m2l, st);
@@ -1793,6 +1828,12 @@ static void prepare_slot_set(const dfmm_plan_s& P, int nrhs, LaunchSet& LS) {
     prepare_slot(LS.down[e], P.hf[e].down, nrhs, nt);
   }
   prepare_slot(LS.lf_down, P.lf.down, nrhs, nt);
+  LS.lfd_up.resize(P.lfd.size());
+  LS.lfd_down.resize(P.lfd.size());
+  for (size_t k = 0; k < P.lfd.size(); ++k) {
+    prepare_slot(LS.lfd_up[k], P.lfd[k].up, nrhs, nt);
+    prepare_slot(LS.lfd_down[k], P.lfd[k].down, nrhs, nt);
+  }
 }
 
 // ---- fused M2L launch ----------------------------------------------------------------
@@ -1907,7 +1948,7 @@ static void autotune(Launch& L, const GGemm& G, int nrhs, const float2* X, float
 static WsShape ws_shape(const dfmm_plan_s& P) {
   WsShape z;
   z.N = P.N;
-  z.nleaf = P.lf.nleaf;
+  z.nleaf = P.nlfbox;
   z.Rlf = P.lf.R;
   for (const auto& H : P.hf) {
     z.nout.push_back(H.nout);
@@ -2063,8 +2104,8 @@ static void tune_fused(const dfmm_plan_s& P, int nrhs, const Ws& S, LaunchSet& L
                          H.red_idx.as<int>(), Yp, H.nin, RN, 1, S.U[size_t(level[i])].as<float2>());
     } else {
       const int RN = P.lf.R * nrhs;
-      hipLaunchKernelGGL(k_reduce, dim3(nblocks(P.lf.nleaf * RN, 256)), dim3(256), 0, st,
-                         P.lf.red_start.as<int>(), P.lf.red_idx.as<int>(), Yp, P.lf.nleaf, RN, 1,
+      hipLaunchKernelGGL(k_reduce, dim3(nblocks(P.lf.nbox * RN, 256)), dim3(256), 0, st,
+                         P.lf.red_start.as<int>(), P.lf.red_idx.as<int>(), Yp, P.lf.nbox, RN, 1,
                          S.ulf.as<float2>());
     }
   };
@@ -2226,6 +2267,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   const int64_t nleaf = P.lf.nleaf;
   const int Rl = P.lf.R;
   const int e_top = int(P.hf.size()) - 1;
+  const int* gid = P.leaf_gid.p ? P.leaf_gid.as<int>() : nullptr;  // leaf -> LF vector (adaptive)
   StageTimer* tm = own ? P.timer : nullptr;
   if (tm && (capturing || !tm->begin_apply(st))) tm = nullptr;  // no stage events inside a graph
   auto mark = [&](int stage) {
@@ -2278,17 +2320,24 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   }
   if (nrhs == 1)
     hipLaunchKernelGGL(k_s2m<1>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
-                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid, S.flf.as<float2>());
   else if (nrhs < 24)
     hipLaunchKernelGGL(k_s2m<8>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
-                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid, S.flf.as<float2>());
   else  // one pass over the weights for up to 32 right-hand sides
     hipLaunchKernelGGL(k_s2m<32>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
-                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, S.flf.as<float2>());
+                       P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid, S.flf.as<float2>());
   mark(ST_S2M);
   if (LS.slot) {
     // slot form: M2M fine to coarse; then per level, coarse to fine, one launch
-    // sums the M2L pairs and the L2L terms of every incoming slot
+    // sums the M2L pairs and the L2L terms of every incoming slot.  Adaptive
+    // trees first run LF-M2M from the deepest LF level up to width 1/2.
+    for (int k = int(P.lfd.size()) - 1; k >= 0; --k) {
+      const LFDeep& Q = P.lfd[size_t(k)];
+      launch_slot(LS.lfd_up[size_t(k)], Q.m2m.A.as<float4>(), S.flf.as<float2>(), Rl, nullptr, nullptr, 0, nrhs,
+                  S.flf.as<float2>(), false, st, Q.up_dst.as<int>());
+      mark(ST_M2M);
+    }
     for (int e = 0; e <= e_top; ++e) {
       const float2* Fc = e == 0 ? S.flf.as<float2>() : S.F[e - 1].as<float2>();
       const int KC = e == 0 ? Rl : P.hf[e - 1].R;
@@ -2308,6 +2357,13 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
                 e_top >= 0 ? P.hf[0].l2l.A.as<float4>() : nullptr, e_top >= 0 ? S.U[0].as<float2>() : nullptr,
                 e_top >= 0 ? P.hf[0].R : 0, nrhs, S.ulf.as<float2>(), true, st);
     mark(ST_LF_M2L);
+    // adaptive trees: LF-M2L + LF-L2L of each deeper level into its boxes' LF vectors
+    for (size_t k = 0; k < P.lfd.size(); ++k) {
+      const LFDeep& Q = P.lfd[k];
+      launch_slot(LS.lfd_down[k], Q.m2l.A.as<float4>(), S.flf.as<float2>(), Rl, Q.l2l.A.as<float4>(),
+                  S.ulf.as<float2>(), Rl, nrhs, S.ulf.as<float2>() + Q.base * nrhs * Rl, true, st);
+      mark(ST_LF_M2L);
+    }
   }
   // HF-M2M, fine to coarse
   for (int e = 0; e <= e_top && !LS.slot; ++e) {
@@ -2366,7 +2422,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   // without HF levels nothing has written the LF incoming slots: the LF
   // reduction writes them itself, or they are cleared if it does not run
   if (e_top < 0 && !LS.slot && LS.lf_m2l.nchunks == 0) {
-    int64_t n = nleaf * Rl * nrhs;
+    int64_t n = P.lf.nbox * Rl * nrhs;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, st, S.ulf.as<float2>(), n);
     mark(ST_ZERO);
   }
@@ -2377,8 +2433,8 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
       mark(ST_LF_M2L);
     }
     int RN = Rl * nrhs;
-    hipLaunchKernelGGL(k_reduce, dim3(nblocks(nleaf * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
-                       P.lf.red_idx.as<int>(), ym2l[P.hf.size()], nleaf, RN, e_top >= 0 ? 1 : 0,
+    hipLaunchKernelGGL(k_reduce, dim3(nblocks(P.lf.nbox * RN, 256)), dim3(256), 0, st, P.lf.red_start.as<int>(),
+                       P.lf.red_idx.as<int>(), ym2l[P.hf.size()], P.lf.nbox, RN, e_top >= 0 ? 1 : 0,
                        S.ulf.as<float2>());
     mark(ST_LF_REDUCE);
   }
@@ -2387,7 +2443,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   if (nrhs >= 4) {
     const int kc = std::min(nrhs, std::max(1, int((48 << 10) / (sizeof(float2) * Rl))));
     hipLaunchKernelGGL(k_l2t_leaf, dim3(unsigned(nleaf)), dim3(L2T_BS), sizeof(float2) * size_t(kc) * Rl, st,
-                       P.lf.W.as<float2>(), S.ulf.as<float2>(), P.leaf_start.as<int>(), S.unear.as<double2>(),
+                       P.lf.W.as<float2>(), S.ulf.as<float2>(), P.leaf_start.as<int>(), gid, S.unear.as<double2>(),
                        P.perm_d.as<int>(), Rl, nrhs, kc, N, R);
   } else {
     hipLaunchKernelGGL(k_l2t, dim3(nblocks(N * 16, L2T_BS)), dim3(L2T_BS), 0, st, P.lf.W.as<float2>(),
@@ -2427,11 +2483,20 @@ void run_apply_noalloc(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t 
 }
 
 // ---- plan-time leaf weights ---------------------------------------------------------
-void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT) {
-  DevBuf dp, dt;
+void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT,
+                        const std::vector<int32_t>& ra, const std::vector<int32_t>& sk_of) {
+  const int R = P.lf.R;
+  if (int64_t(sk_of.size()) != P.lf.nleaf || DT.size() != size_t(2) * R * R * ra.size())
+    throw Error{DFMM_EINVAL, "leaf weight tables of the wrong size"};
+  for (int32_t k : sk_of)
+    if (k < 0 || k >= int32_t(ra.size())) throw Error{DFMM_EINVAL, "leaf skeleton index out of range"};
+  for (int32_t r : ra)
+    if (r < 1 || r > R) throw Error{DFMM_EINVAL, "LF skeleton rank out of range"};
+  DevBuf dp, dt, dra, dsk;
   dp.upload(sorted_pts);
   dt.upload(DT);
-  const int R = P.lf.R;
+  dra.upload(ra);
+  dsk.upload(sk_of);
   const bool f64 = P.prec == DFMM_PREC_FP64;
   const size_t es = f64 ? sizeof(double2) : sizeof(float2);
   P.lf.V.alloc(es * size_t(P.N) * R);
@@ -2439,11 +2504,12 @@ void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, c
   if (f64)
     hipLaunchKernelGGL(k_leaf_weights<double2>, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
                        dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
-                       dt.as<double2>(), R, P.lf.r, P.lf.V.as<double2>(), P.lf.W.as<double2>());
+                       dt.as<double2>(), dra.as<int>(), dsk.as<int>(), R, P.lf.V.as<double2>(),
+                       P.lf.W.as<double2>());
   else
     hipLaunchKernelGGL(k_leaf_weights<float2>, dim3(unsigned(P.lf.nleaf)), dim3(LW_BS), sizeof(double2) * R, 0,
                        dp.as<double>(), P.leaf_start.as<int>(), P.leaf_center.as<float4>(), P.lf.a64.as<double4>(),
-                       dt.as<double2>(), R, P.lf.r, P.lf.V.as<float2>(), P.lf.W.as<float2>());
+                       dt.as<double2>(), dra.as<int>(), dsk.as<int>(), R, P.lf.V.as<float2>(), P.lf.W.as<float2>());
   DFMM_HIP(hipGetLastError());
   DFMM_HIP(hipDeviceSynchronize());
 }

@@ -44,6 +44,7 @@ struct dfmm_opset_s {
   int w_hi = 1;
   std::vector<std::vector<dfmm::Skel>> hf;  // [log2 w][dir]
   dfmm::Skel lf;
+  std::vector<dfmm::Skel> lf_deep;  // low-frequency widths 1/4, 1/8, ... (adaptive trees)
 };
 
 namespace dfmm {
@@ -51,6 +52,12 @@ using OpSetImpl = dfmm_opset_s;
 void build_opset(OpSetImpl& set);
 bool save_opset(const OpSetImpl& set, const std::string& path);
 bool load_opset(OpSetImpl& set, const std::string& path);
+// Skeletons of the LF widths 1/4, ..., 2^-(1 + n) (Eq. 2, one per width): extends
+// set.lf_deep to n entries from set.lf; cached as a file of its own.
+void build_lf_deep(OpSetImpl& set, int n);
+bool save_lf_deep(const OpSetImpl& set, const std::string& path);
+bool load_lf_deep(OpSetImpl& set, const std::string& path, int n);
+constexpr int kMaxLfLevels = 6;  // LF levels below width 1/2 an adaptive tree may reach
 
 // ---- device buffers ---------------------------------------------------------
 struct DevBuf {
@@ -202,9 +209,11 @@ struct HFLevel {
 };
 
 struct LFLevel {
-  int R = 0;           // padded rank (multiple of 8)
-  int r = 0;           // rank of the LF skeleton
-  int64_t nleaf = 0, npairs = 0, ngroups = 0;
+  int R = 0;           // padded rank (multiple of 8): the row stride of every LF vector
+  int r = 0;           // rank of the width-1/2 LF skeleton
+  int64_t nleaf = 0;   // leaves (S2M, L2T and the near field run over them)
+  int64_t nbox = 0;    // boxes of width 1/2 (LF-M2L of that level; = nleaf in a uniform tree)
+  int64_t npairs = 0, ngroups = 0;
   double flops = 0.0;
   DevBuf a;            // float4[R]  check points a_LF (box frame)
   DevBuf a64;          // double4[R] the same in float64
@@ -213,6 +222,26 @@ struct LFLevel {
   GGemm m2l;
   DevBuf red_start, red_idx;
   SlotGemm down;       // slot form of LF-M2L + L2L into the leaves
+};
+
+// One low-frequency level below width 1/2 of an adaptive tree (Section 2.2):
+// its boxes are the children of the split boxes of the level above; it has its
+// own skeleton (LF-M2L operators per offset) and the octant operators that
+// connect it to the level above (LF-M2M up, LF-L2L down).
+struct LFDeep {
+  int l = 0;                 // tree level
+  int r = 0;                 // rank of this width's skeleton
+  int64_t nb = 0;            // boxes of this level
+  int64_t base = 0;          // LF vector index of the first of them
+  int64_t npairs = 0, ngroups = 0, nsplit = 0;  // M2L pairs and offsets; split boxes of level l - 1
+  double flops = 0.0;        // M2L flops (8 r r per pair)
+  GGemm m2l;                 // LF-M2L operators, one per offset
+  GGemm m2m;                 // 8 octant operators G(a_P - delta_o, b_C) D_C: parent <- child
+  GGemm l2l;                 // 8 octant operators G(b_C + delta_o, a_P) D_P^T: child <- parent
+  DevBuf red_start, red_idx; // pair-form CSR of the M2L (built with the operators, unused)
+  SlotGemm up;               // LF-M2M: the split boxes of level l - 1 <- their children
+  DevBuf up_dst;             // int32[nsplit]: LF vector index of each of those parents
+  SlotGemm down;             // LF-M2L pairs + LF-L2L term of every box of this level
 };
 
 // Octree with one table per level, boxes in Morton order (host copy).
@@ -311,9 +340,14 @@ size_t plan_device_bytes(const dfmm_plan_s& P);
 // (ws_layout(ws_shape64(P), nrhs, false, 16))
 WsShape ws_shape64(const dfmm_plan_s& P);
 void run_apply64(dfmm_plan_s& P, const double2* f, double2* u, int nrhs, hipStream_t st, void* ws);
-void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT);
+// S2M and L2T weights of every sorted point (float64, then stored in the plan's
+// precision).  DT holds D^T of each LF skeleton at R x R offsets, P.lf.a64 its
+// check points at R offsets; ra the skeletons' ranks, sk_of the skeleton of each leaf.
+void build_leaf_weights(dfmm_plan_s& P, const std::vector<double>& sorted_pts, const std::vector<double>& DT,
+                        const std::vector<int32_t>& ra, const std::vector<int32_t>& sk_of);
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
-                const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx);
+                const OpSetImpl* (*get_ops)(void* ctx, int w_needed),
+                const std::vector<Skel>* (*get_lf_deep)(void* ctx, int n), void* ctx);
 
 }  // namespace dfmm
 
@@ -342,6 +376,13 @@ struct dfmm_plan_s {
   dfmm::DevBuf leaf_center;      // float4[nleaf]
   dfmm::DevBuf near_start, near_src;  // CSR over leaves
   int max_leaf_pts = 0;
+  // adaptive low-frequency tree (leaf_max > 0): boxes of width <= 1/2 split while
+  // they hold more than leaf_max points, down to lf_levels levels below 1/2
+  int leaf_max = 0, lf_levels = 0;
+  int64_t nlfbox = 0;            // LF vectors (flf / ulf): every box of width <= 1/2
+  dfmm::DevBuf leaf_gid;         // int32[nleaf]: LF vector of each leaf (adaptive; empty = identity)
+  std::vector<dfmm::LFDeep> lfd; // levels D + 1 .. of an adaptive tree
+  std::vector<int64_t> leaves;   // export: nleaf x 4 (level, box, first point, end point)
   dfmm::LFLevel lf;
   std::vector<dfmm::HFLevel> hf;  // index e (log2 w), 0 .. e_top
   // apply workspace (owned; see apply.hip)

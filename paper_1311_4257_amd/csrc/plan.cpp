@@ -1,6 +1,7 @@
 // Plan construction: octree, interaction lists, wedges, needed directions and
 // translation tables (Section 2.2, Algorithm 1), resident on the device.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -15,7 +16,8 @@
 
 namespace dfmm {
 
-void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT);
+void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT,
+                       int extra);
 
 namespace {
 
@@ -49,6 +51,79 @@ inline void green64(double dx, double dy, double dz, double* re, double* im) {
 }
 
 int pad8(int r) { return (r + 7) / 8 * 8; }
+
+// ---- adaptive low-frequency tree (Section 2.2) ---------------------------------
+// The device box tables cover every level down to the sort depth, boxes under
+// leaves included.  A box of level l > D exists when its parent exists and is
+// split; a box of width <= 1/2 is split when it holds more than leaf_max points
+// and is above the deepest level.  Kept boxes keep the Morton order.
+struct AdaptiveLevels {
+  int D = 0, Dmax = 0;
+  std::vector<std::vector<int64_t>> box;    // per level (index l - D): device-table index of each kept box
+  std::vector<std::vector<char>> split;     // per kept box: it has children
+  std::vector<std::vector<int64_t>> par;    // per kept box of level > D: kept index of the parent
+  std::vector<std::vector<int64_t>> c0, c1; // per kept box: range of its kept children one level down
+  std::vector<int64_t> base;                // LF vector index of the first kept box of each level
+  std::vector<std::map<std::tuple<int64_t, int64_t, int64_t>, int64_t>> at;  // coordinates -> kept index
+};
+
+AdaptiveLevels adaptive_levels(const Tree& T, int D, int leaf_max) {
+  AdaptiveLevels A;
+  A.D = A.Dmax = D;
+  const int Dk = int(T.lv.size()) - 1;
+  std::vector<int64_t> kprev;  // device index of level l - 1 -> kept index (-1: not kept)
+  for (int l = D; l <= Dk; ++l) {
+    const auto& L = T.lv[size_t(l)];
+    const int64_t nu = int64_t(L.key.size());
+    std::vector<int64_t> kidx(size_t(nu), -1), box, par;
+    std::vector<char> sp;
+    for (int64_t u = 0; u < nu; ++u) {
+      int64_t pk = -1;
+      if (l > D) {
+        pk = kprev[size_t(L.parent[size_t(u)])];
+        if (pk < 0 || !A.split.back()[size_t(pk)]) continue;
+      }
+      kidx[size_t(u)] = int64_t(box.size());
+      box.push_back(u);
+      par.push_back(pk);
+      sp.push_back(char(l < Dk && L.end[size_t(u)] - L.start[size_t(u)] > leaf_max));
+    }
+    if (box.empty()) break;
+    const bool any_split = std::any_of(sp.begin(), sp.end(), [](char c) { return c != 0; });
+    A.box.push_back(std::move(box));
+    A.split.push_back(std::move(sp));
+    A.par.push_back(std::move(par));
+    A.Dmax = l;
+    kprev = std::move(kidx);
+    if (!any_split) break;
+  }
+  const int nl = A.Dmax - D + 1;
+  A.c0.assign(size_t(nl), {});
+  A.c1.assign(size_t(nl), {});
+  A.base.assign(size_t(nl), 0);
+  A.at.assign(size_t(nl), {});
+  int64_t base = 0;
+  for (int k = 0; k < nl; ++k) {
+    const size_t nb = A.box[size_t(k)].size();
+    A.base[size_t(k)] = base;
+    base += int64_t(nb);
+    A.c0[size_t(k)].assign(nb, 0);
+    A.c1[size_t(k)].assign(nb, 0);
+    const auto& L = T.lv[size_t(D + k)];
+    for (size_t b = 0; b < nb; ++b) {
+      const int64_t u = A.box[size_t(k)][b];
+      A.at[size_t(k)][{L.cx[size_t(u)], L.cy[size_t(u)], L.cz[size_t(u)]}] = int64_t(b);
+    }
+    if (k > 0) {  // children of a box are consecutive in the Morton order
+      for (size_t c = 0; c < nb; ++c) {
+        const int64_t p = A.par[size_t(k)][c];
+        if (A.c1[size_t(k - 1)][size_t(p)] == 0) A.c0[size_t(k - 1)][size_t(p)] = int64_t(c);
+        A.c1[size_t(k - 1)][size_t(p)] = int64_t(c) + 1;
+      }
+    }
+  }
+  return A;
+}
 
 }  // namespace
 
@@ -272,17 +347,23 @@ size_t plan_device_bytes(const dfmm_plan_s& P) {
   for (const HFLevel& H : P.hf)
     b += gg_bytes(H.m2m) + gg_bytes(H.l2l) + gg_bytes(H.m2l) + H.m2m_rs.bytes + H.m2m_ri.bytes + H.l2l_rs.bytes +
          H.l2l_ri.bytes + H.red_start.bytes + H.red_idx.bytes + slot_bytes(H.up) + slot_bytes(H.down);
+  b += P.leaf_gid.bytes;
+  for (const LFDeep& Q : P.lfd)
+    b += gg_bytes(Q.m2l) + gg_bytes(Q.m2m) + gg_bytes(Q.l2l) + Q.red_start.bytes + Q.red_idx.bytes +
+         slot_bytes(Q.up) + slot_bytes(Q.down) + Q.up_dst.bytes;
   return b;
 }
 
 void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
-                const OpSetImpl* (*get_ops)(void* ctx, int w_needed), void* ctx) {
+                const OpSetImpl* (*get_ops)(void* ctx, int w_needed),
+                const std::vector<Skel>* (*get_lf_deep)(void* ctx, int n), void* ctx) {
   auto t0 = std::chrono::steady_clock::now();
   P.N = N;
   P.K = K;
   Tree T;
   DevTree DT;
-  build_tree_device(P, points, N, K, T, DT);
+  const bool adaptive = P.leaf_max > 0;
+  build_tree_device(P, points, N, K, T, DT, adaptive ? P.lf_levels : 0);
   const int D = T.D;
   P.D = D;
   dfmm_info& info = P.info;
@@ -292,6 +373,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   info.N = N;
   info.K = K;
   info.depth = D;
+  info.depth_max = D;
 
   // ---- exports of the tree --------------------------------------------------
   P.perm = T.perm;
@@ -334,16 +416,169 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
 
   // ---- near-field lists -------------------------------------------------------
   const auto& LL = T.lv[D];
-  int64_t nleaf = int64_t(LL.key.size());
+  const int64_t nD = int64_t(LL.key.size());  // boxes of width 1/2
+  int64_t nleaf = nD;
   std::vector<int32_t> near_start, near_src;
-  near_lists_device(DT, D, near_start, near_src);
-  for (int64_t b = 0; b < nleaf; ++b)
-    for (int32_t j = near_start[b]; j < near_start[b + 1]; ++j) {
-      const int64_t a = near_src[j];
-      P.near.push_back(b);
-      P.near.push_back(a);
-      info.near_point_pairs += (LL.end[b] - LL.start[b]) * (LL.end[a] - LL.start[a]);
+  AdaptiveLevels AL;
+  int nl = 1;                                        // LF levels D .. D + nl - 1
+  std::vector<int64_t> leaf_lv;                      // adaptive: LF level index of each leaf
+  std::vector<std::vector<PairRec>> dpairs;          // adaptive: M2L pairs of the levels below D
+  if (!adaptive) {
+    near_lists_device(DT, D, near_start, near_src);
+    for (int64_t b = 0; b < nleaf; ++b)
+      for (int32_t j = near_start[b]; j < near_start[b + 1]; ++j) {
+        const int64_t a = near_src[j];
+        P.near.push_back(b);
+        P.near.push_back(a);
+        info.near_point_pairs += (LL.end[b] - LL.start[b]) * (LL.end[a] - LL.start[a]);
+      }
+    P.nlfbox = nD;
+  } else {
+    // adaptive low-frequency part (Section 2.2), built on the host from the
+    // device box tables: kept boxes, leaves in point order, their LF vectors
+    AL = adaptive_levels(T, D, P.leaf_max);
+    nl = AL.Dmax - D + 1;
+    auto coords = [&](int l, int64_t u) {
+      const auto& L = T.lv[size_t(l)];
+      return std::array<int64_t, 3>{L.cx[size_t(u)], L.cy[size_t(u)], L.cz[size_t(u)]};
+    };
+    struct LeafRec {
+      int64_t k, b, s, e;  // LF level index, kept box, point range
+    };
+    std::vector<LeafRec> lv;
+    std::vector<std::vector<int64_t>> leaf_at(static_cast<size_t>(nl));
+    for (int k = 0; k < nl; ++k) {
+      const auto& L = T.lv[size_t(D + k)];
+      leaf_at[size_t(k)].assign(AL.box[size_t(k)].size(), -1);
+      for (size_t b = 0; b < AL.box[size_t(k)].size(); ++b)
+        if (!AL.split[size_t(k)][b]) {
+          const int64_t u = AL.box[size_t(k)][b];
+          lv.push_back({k, int64_t(b), L.start[size_t(u)], L.end[size_t(u)]});
+        }
     }
+    std::sort(lv.begin(), lv.end(), [](const LeafRec& a, const LeafRec& b) { return a.s < b.s; });
+    nleaf = int64_t(lv.size());
+    std::vector<int64_t> lstart(static_cast<size_t>(nleaf));
+    for (int64_t i = 0; i < nleaf; ++i) {
+      leaf_at[size_t(lv[size_t(i)].k)][size_t(lv[size_t(i)].b)] = i;
+      lstart[size_t(i)] = lv[size_t(i)].s;
+    }
+    P.nlfbox = AL.base.back() + int64_t(AL.box.back().size());
+    std::vector<int32_t> ls, gid, lof(static_cast<size_t>(N));
+    std::vector<float> lc(size_t(4) * size_t(nleaf), 0.0f);
+    int mx = 0;
+    P.leaves.clear();
+    for (int64_t i = 0; i < nleaf; ++i) {
+      const LeafRec& r = lv[size_t(i)];
+      const int l = D + int(r.k);
+      const int64_t g = AL.base[size_t(r.k)] + r.b;
+      ls.push_back(int32_t(r.s));
+      gid.push_back(int32_t(g));
+      const auto c = coords(l, AL.box[size_t(r.k)][size_t(r.b)]);
+      const double w = K / std::ldexp(1.0, l);
+      for (int t = 0; t < 3; ++t) lc[size_t(4 * i + t)] = float((double(c[size_t(t)]) + 0.5) * w - K / 2.0);
+      mx = std::max<int>(mx, int(r.e - r.s));
+      for (int64_t j = r.s; j < r.e; ++j) lof[size_t(j)] = int32_t(g);
+      P.leaves.insert(P.leaves.end(), {int64_t(l), r.b, r.s, r.e});
+      leaf_lv.push_back(r.k);
+    }
+    ls.push_back(int32_t(N));
+    P.leaf_start.upload(ls);
+    P.leaf_gid.upload(gid);
+    P.leaf_center.upload(lc);
+    P.leaf_of.upload(lof);
+    P.max_leaf_pts = mx;
+    // near field: leaves whose boxes at the coarser of their two levels are
+    // adjacent (or equal); the finer leaves under an adjacent split box are the
+    // leaves whose first point lies in that box's point range
+    near_start.push_back(0);
+    for (int64_t i = 0; i < nleaf; ++i) {
+      const LeafRec& B = lv[size_t(i)];
+      const int lb = D + int(B.k);
+      const auto cb = coords(lb, AL.box[size_t(B.k)][size_t(B.b)]);
+      std::vector<int32_t> src;
+      for (int la = D; la <= lb; ++la) {
+        const int sh = lb - la, ka = la - D;
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+              auto it = AL.at[size_t(ka)].find({(cb[0] >> sh) + dx, (cb[1] >> sh) + dy, (cb[2] >> sh) + dz});
+              if (it != AL.at[size_t(ka)].end() && !AL.split[size_t(ka)][size_t(it->second)])
+                src.push_back(int32_t(leaf_at[size_t(ka)][size_t(it->second)]));
+            }
+      }
+      const auto& L = T.lv[size_t(lb)];
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            auto it = AL.at[size_t(B.k)].find({cb[0] + dx, cb[1] + dy, cb[2] + dz});
+            if (it == AL.at[size_t(B.k)].end() || !AL.split[size_t(B.k)][size_t(it->second)]) continue;
+            const int64_t u = AL.box[size_t(B.k)][size_t(it->second)];
+            auto lo = std::lower_bound(lstart.begin(), lstart.end(), L.start[size_t(u)]);
+            auto hi = std::lower_bound(lstart.begin(), lstart.end(), L.end[size_t(u)]);
+            for (auto q = lo; q != hi; ++q) src.push_back(int32_t(q - lstart.begin()));
+          }
+      std::sort(src.begin(), src.end());
+      for (int32_t a : src) {
+        near_src.push_back(a);
+        P.near.push_back(i);
+        P.near.push_back(a);
+        info.near_point_pairs += (B.e - B.s) * (lv[size_t(a)].e - lv[size_t(a)].s);
+      }
+      near_start.push_back(int32_t(near_src.size()));
+    }
+    // M2L pairs of the levels below D: the kept children of the boxes adjacent
+    // to the parent that are not adjacent themselves (the classical V-list),
+    // sorted by (B, A)
+    dpairs.assign(size_t(nl), {});
+    for (int k = 1; k < nl; ++k) {
+      const int l = D + k;
+      for (size_t b = 0; b < AL.box[size_t(k)].size(); ++b) {
+        const auto cB = coords(l, AL.box[size_t(k)][b]);
+        const int64_t p = AL.par[size_t(k)][b];
+        const auto cP = coords(l - 1, AL.box[size_t(k - 1)][size_t(p)]);
+        std::vector<int64_t> cand;
+        for (int dx = -1; dx <= 1; ++dx)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+              auto it = AL.at[size_t(k - 1)].find({cP[0] + dx, cP[1] + dy, cP[2] + dz});
+              if (it == AL.at[size_t(k - 1)].end()) continue;
+              for (int64_t c = AL.c0[size_t(k - 1)][size_t(it->second)]; c < AL.c1[size_t(k - 1)][size_t(it->second)]; ++c)
+                cand.push_back(c);
+            }
+        std::sort(cand.begin(), cand.end());
+        for (int64_t c : cand) {
+          const auto cA = coords(l, AL.box[size_t(k)][size_t(c)]);
+          const int64_t nx = cA[0] - cB[0], ny = cA[1] - cB[1], nz = cA[2] - cB[2];
+          if (std::max({std::abs(nx), std::abs(ny), std::abs(nz)}) > 1)
+            dpairs[size_t(k)].push_back(PairRec{int64_t(b), c, nx, ny, nz, -1, -1});
+        }
+      }
+    }
+    // exports and counts of the levels below D
+    P.boxes.resize(size_t(D + nl));
+    P.pairs.resize(size_t(D + nl));
+    for (int k = 1; k < nl; ++k) {
+      const int l = D + k;
+      const auto& L = T.lv[size_t(l)];
+      auto& v = P.boxes[size_t(l)];
+      for (int64_t u : AL.box[size_t(k)])
+        v.insert(v.end(), {L.cx[size_t(u)], L.cy[size_t(u)], L.cz[size_t(u)], L.start[size_t(u)], L.end[size_t(u)]});
+      auto& pv = P.pairs[size_t(l)];
+      std::set<std::tuple<int64_t, int64_t, int64_t>> offs;
+      for (const PairRec& r : dpairs[size_t(k)]) {
+        pv.insert(pv.end(), {r.B, r.A, -1, -1, 0});
+        offs.insert({r.nx, r.ny, r.nz});
+      }
+      if (l < 32) {
+        info.boxes[l] = int64_t(AL.box[size_t(k)].size());
+        info.pairs[l] = int64_t(dpairs[size_t(k)].size());
+        info.offsets[l] = int64_t(offs.size());
+      }
+    }
+    info.depth_max = D + nl - 1;
+  }
+  info.leaves = nleaf;
   info.near_pairs = int64_t(near_src.size());
   P.near_start.upload(near_start);
   P.near_src.upload(near_src);
@@ -363,28 +598,46 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   }
 
   // ---- LF level tables ------------------------------------------------------------
+  // One skeleton per LF width: 1/2, and 1/4, 1/8, ... below it in an adaptive
+  // tree.  Every LF vector has the row stride of the largest rank.
   const Skel& sl = ops.lf;
-  int Rlf = pad8(sl.r);
+  std::vector<const Skel*> lsk{&sl};
+  if (nl > 1) {
+    const std::vector<Skel>* deep = get_lf_deep(ctx, nl - 1);
+    for (int k = 1; k < nl; ++k) lsk.push_back(&(*deep)[size_t(k - 1)]);
+  }
+  int rmax = 0;
+  for (const Skel* q : lsk) rmax = std::max(rmax, q->r);
+  int Rlf = pad8(rmax);
   P.lf.R = Rlf;
   P.lf.r = sl.r;
   P.lf.nleaf = nleaf;
-  info.rank[D] = Rlf;
+  P.lf.nbox = nD;
+  for (int k = 0; k < nl && D + k < 32; ++k) info.rank[D + k] = k == 0 ? Rlf : pad8(lsk[size_t(k)]->r);
   {
+    const int nsk = int(lsk.size());
     std::vector<float> a4(size_t(4) * Rlf, 0.0f);
-    std::vector<double> a64(size_t(4) * Rlf, 0.0), DT(size_t(2) * Rlf * Rlf, 0.0);
+    std::vector<double> a64(size_t(4) * Rlf * nsk, 0.0), DT(size_t(2) * Rlf * Rlf * nsk, 0.0);
+    std::vector<int32_t> ra(static_cast<size_t>(nsk));
     for (int i = 0; i < sl.r; ++i)
-      for (int k = 0; k < 3; ++k) {
-        a4[4 * i + k] = float(sl.a[3 * i + k]);
-        a64[4 * i + k] = sl.a[3 * i + k];
-      }
-    for (int q = 0; q < sl.r; ++q)
-      for (int p = 0; p < sl.r; ++p) {  // DT[p][q] = D[q][p]
-        DT[2 * (size_t(p) * Rlf + q)] = sl.D[2 * (size_t(q) * sl.r + p)];
-        DT[2 * (size_t(p) * Rlf + q) + 1] = sl.D[2 * (size_t(q) * sl.r + p) + 1];
-      }
+      for (int k = 0; k < 3; ++k) a4[4 * i + k] = float(sl.a[3 * i + k]);
+    for (int t = 0; t < nsk; ++t) {  // skeleton t: check points and D^T at offsets t R, t R R
+      const Skel& q = *lsk[size_t(t)];
+      ra[size_t(t)] = q.r;
+      for (int i = 0; i < q.r; ++i)
+        for (int k = 0; k < 3; ++k) a64[size_t(4) * (size_t(t) * Rlf + i) + k] = q.a[3 * i + k];
+      double* dt = DT.data() + size_t(2) * Rlf * Rlf * t;
+      for (int c = 0; c < q.r; ++c)
+        for (int p = 0; p < q.r; ++p) {  // DT[p][c] = D[c][p]
+          dt[2 * (size_t(p) * Rlf + c)] = q.D[2 * (size_t(c) * q.r + p)];
+          dt[2 * (size_t(p) * Rlf + c) + 1] = q.D[2 * (size_t(c) * q.r + p) + 1];
+        }
+    }
     P.lf.a.upload(a4);
     P.lf.a64.upload(a64);
-    build_leaf_weights(P, T.pts, DT);
+    std::vector<int32_t> sk_of(static_cast<size_t>(nleaf), 0);
+    for (size_t i = 0; i < leaf_lv.size(); ++i) sk_of[i] = int32_t(leaf_lv[i]);
+    build_leaf_weights(P, T.pts, DT, ra, sk_of);
   }
 
   // M2L of one level: pairs grouped by offset n; one operator per group,
@@ -518,7 +771,7 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   {
     std::vector<const Skel*> s1{&sl};
     P.lf.npairs = int64_t(pairs[D].size());
-    build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nleaf, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
+    build_m2l(pairs[D], 0.5, Rlf, s1, nullptr, nullptr, nD, P.lf.m2l, P.lf.red_start, P.lf.red_idx,
               P.lf.ngroups, P.lf.flops, 1, lf_terms);
     info.flops_m2l_lf = P.lf.flops;
     info.flops_m2l_level[D] = P.lf.flops;
@@ -689,8 +942,8 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
     {
       std::vector<std::vector<std::pair<int32_t, int32_t>>> by_op(size_t(ndir) * 8);
       if (e == 0) {
-        H.nchild_in = nleaf;
-        for (int64_t c = 0; c < nleaf; ++c) {
+        H.nchild_in = nD;
+        for (int64_t c = 0; c < nD; ++c) {
           int64_t p = C.parent[c];
           for (int d = 0; d < 6; ++d) {
             int64_t sidx = IS[l].at(p, d);
@@ -758,6 +1011,90 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
   for (const SlotTerm& t : lf_terms)
     if (t.kind == 1) info.flops_l2l += P.hf[0].l2l.opflops[size_t(t.op)];
 
+  // ---- LF levels below D (adaptive trees) ---------------------------------------
+  // Per level: the M2L operators of its offsets with its own skeleton, and the
+  // 8 octant operators to the level above, in the folded forms of the HF levels
+  // (child width w, delta_o = (o - 1/2) w): LF-M2M G(a_P - delta_o, b_C) D_C,
+  // LF-L2L G(b_C + delta_o, a_P) D_P^T.
+  auto build_lf_transfer = [&](const Skel& sp, const Skel& sc, double wc, GGemm& up, GGemm& dn) {
+    const int RK = kpad(Rlf, P.prec);
+    const size_t per = size_t(2) * Rlf * RK;  // storage of one operator
+    OpStore Au(fp64, per * 8), Ad(fp64, per * 8);
+    const int Mp = pad8(sp.r), Mc = pad8(sc.r);
+    const int Kpu = kpad(Mc, P.prec), Kpd = kpad(Mp, P.prec);
+    parallel_for(8, [&](int64_t o) {
+      const double dx = ((o & 1) - 0.5) * wc, dy = (((o >> 1) & 1) - 0.5) * wc, dz = (((o >> 2) & 1) - 0.5) * wc;
+      std::vector<double> G(size_t(2) * sp.r * sc.r);  // G[p][j] = G(a_P[p] - delta_o, b_C[j])
+      for (int p = 0; p < sp.r; ++p)
+        for (int j = 0; j < sc.r; ++j)
+          green64(sp.a[3 * p] - dx - sc.b[3 * j], sp.a[3 * p + 1] - dy - sc.b[3 * j + 1],
+                  sp.a[3 * p + 2] - dz - sc.b[3 * j + 2], &G[2 * (size_t(p) * sc.r + j)],
+                  &G[2 * (size_t(p) * sc.r + j) + 1]);
+      std::vector<double> U(size_t(2) * Mp * Kpu, 0.0), Dn(size_t(2) * Mc * Kpd, 0.0);
+      for (int p = 0; p < sp.r; ++p)
+        for (int k = 0; k < sc.r; ++k) {  // (G D_C)[p][k]
+          double re = 0.0, im = 0.0;
+          for (int j = 0; j < sc.r; ++j) {
+            const double gr = G[2 * (size_t(p) * sc.r + j)], gi = G[2 * (size_t(p) * sc.r + j) + 1];
+            const double dr = sc.D[2 * (size_t(j) * sc.r + k)], di = sc.D[2 * (size_t(j) * sc.r + k) + 1];
+            re += gr * dr - gi * di;
+            im += gr * di + gi * dr;
+          }
+          U[2 * (size_t(p) * Kpu + k)] = re;
+          U[2 * (size_t(p) * Kpu + k) + 1] = im;
+        }
+      for (int j = 0; j < sc.r; ++j)
+        for (int q = 0; q < sp.r; ++q) {  // (G^T D_P^T)[j][q] = sum_p G[p][j] D_P[q][p]
+          double re = 0.0, im = 0.0;
+          for (int p = 0; p < sp.r; ++p) {
+            const double gr = G[2 * (size_t(p) * sc.r + j)], gi = G[2 * (size_t(p) * sc.r + j) + 1];
+            const double dr = sp.D[2 * (size_t(q) * sp.r + p)], di = sp.D[2 * (size_t(q) * sp.r + p) + 1];
+            re += gr * dr - gi * di;
+            im += gr * di + gi * dr;
+          }
+          Dn[2 * (size_t(j) * Kpd + q)] = re;
+          Dn[2 * (size_t(j) * Kpd + q) + 1] = im;
+        }
+      Au.pack(U.data(), Mp, Kpu, 1, per * size_t(o));
+      Ad.pack(Dn.data(), Mc, Kpd, 1, per * size_t(o));
+    });
+    for (GGemm* g : {&up, &dn}) {
+      const bool isup = g == &up;
+      g->prec = P.prec;
+      g->M = Rlf;
+      g->K = Rlf;
+      g->T = 1;
+      g->split = 1;
+      g->nops = 8;
+      g->aoff_h.resize(8);
+      g->kpk_h.assign(8, isup ? Kpu : Kpd);
+      g->opflops.assign(8, 8.0 * sp.r * sc.r);
+      for (int o = 0; o < 8; ++o) g->aoff_h[size_t(o)] = int64_t(o) * Rlf * RK / 2;
+    }
+    Au.upload(up.A);
+    Ad.upload(dn.A);
+  };
+  std::vector<std::vector<SlotTerm>> deep_m2l_terms(static_cast<size_t>(nl));
+  P.lfd.clear();
+  P.lfd.resize(size_t(nl > 1 ? nl - 1 : 0));
+  for (int k = 1; k < nl; ++k) {
+    LFDeep& Q = P.lfd[size_t(k - 1)];
+    const int l = D + k;
+    const double w = K / std::ldexp(1.0, l);
+    const Skel& sc = *lsk[size_t(k)];
+    Q.l = l;
+    Q.r = sc.r;
+    Q.nb = int64_t(AL.box[size_t(k)].size());
+    Q.base = AL.base[size_t(k)];
+    Q.npairs = int64_t(dpairs[size_t(k)].size());
+    std::vector<const Skel*> s1{&sc};
+    build_m2l(dpairs[size_t(k)], w, Rlf, s1, nullptr, nullptr, Q.nb, Q.m2l, Q.red_start, Q.red_idx, Q.ngroups,
+              Q.flops, 1, deep_m2l_terms[size_t(k)]);
+    info.flops_m2l_lf += Q.flops;
+    if (l < 32) info.flops_m2l_level[l] = Q.flops;
+    build_lf_transfer(*lsk[size_t(k - 1)], sc, w, Q.m2m, Q.l2l);
+  }
+
   // ---- slot-form tables (fast float32 plans; used from 16 right-hand sides) -------
   if ((!P.precise && P.prec == DFMM_PREC_FP32) || fp64) {
     auto slot_m = [&](int l, int64_t n, bool in) {  // padded rows of each slot's skeleton
@@ -778,8 +1115,41 @@ void build_plan(dfmm_plan_s& P, const double* points, int64_t N, double K,
                       std::max(H.R, e < e_top ? P.hf[size_t(e + 1)].R : 0));
     }
     SlotKind dn[2] = {{&P.lf.m2l, 1}, {e_top >= 0 ? &P.hf[0].l2l : nullptr, hf_split}};
-    build_slot_gemm(P.lf.down, Rlf, nleaf, std::vector<int32_t>(size_t(nleaf), Rlf), lf_terms, dn,
+    build_slot_gemm(P.lf.down, Rlf, nD, std::vector<int32_t>(size_t(nD), Rlf), lf_terms, dn,
                     std::max(Rlf, e_top >= 0 ? P.hf[0].R : 0));
+    // adaptive levels below D.  LF-M2M: a group per split box of level l - 1
+    // (written at its LF vector through up_dst), a term per child.  Downward: a
+    // group per box of level l: its M2L pairs (kind 0, sources at their LF
+    // vectors) and its parent's incoming potentials (kind 1)
+    for (int k = 1; k < nl; ++k) {
+      LFDeep& Q = P.lfd[size_t(k - 1)];
+      const auto& Lc = T.lv[size_t(D + k)];
+      std::vector<SlotTerm> up_t;
+      std::vector<int32_t> up_dst;
+      for (size_t p = 0; p < AL.box[size_t(k - 1)].size(); ++p) {
+        if (!AL.split[size_t(k - 1)][p]) continue;
+        const int32_t g = int32_t(up_dst.size());
+        up_dst.push_back(int32_t(AL.base[size_t(k - 1)] + int64_t(p)));
+        for (int64_t c = AL.c0[size_t(k - 1)][p]; c < AL.c1[size_t(k - 1)][p]; ++c)
+          up_t.push_back({g, int32_t(Lc.octant[size_t(AL.box[size_t(k)][size_t(c)])]),
+                          int32_t(Q.base + c), 0});
+      }
+      Q.nsplit = int64_t(up_dst.size());
+      SlotKind uk[2] = {{&Q.m2m, 1}, {nullptr, 1}};
+      build_slot_gemm(Q.up, Rlf, Q.nsplit, std::vector<int32_t>(up_dst.size(), pad8(lsk[size_t(k - 1)]->r)), up_t,
+                      uk, Rlf);
+      Q.up_dst.upload(up_dst);
+      std::vector<SlotTerm> dn_t;
+      for (const SlotTerm& t : deep_m2l_terms[size_t(k)])
+        dn_t.push_back({t.dst, t.op, int32_t(Q.base + t.src), 0});
+      for (int64_t b = 0; b < Q.nb; ++b)
+        dn_t.push_back({int32_t(b), int32_t(Lc.octant[size_t(AL.box[size_t(k)][size_t(b)])]),
+                        int32_t(AL.base[size_t(k - 1)] + AL.par[size_t(k)][size_t(b)]), 1});
+      SlotKind dk[2] = {{&Q.m2l, 1}, {&Q.l2l, 1}};
+      build_slot_gemm(Q.down, Rlf, Q.nb, std::vector<int32_t>(size_t(Q.nb), pad8(Q.r)), dn_t, dk, Rlf);
+      for (const SlotTerm& t : up_t) info.flops_m2m += Q.m2m.opflops[size_t(t.op)];
+      for (int64_t b = 0; b < Q.nb; ++b) info.flops_l2l += Q.l2l.opflops[0];
+    }
   }
 
   info.device_bytes = int64_t(plan_device_bytes(P));

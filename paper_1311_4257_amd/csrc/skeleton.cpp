@@ -476,6 +476,33 @@ void build_opset(OpSetImpl& set) {
   set.lf = make_skeleton(X, Y, tau, kSeed ^ 0x1f1f1f1fULL);
 }
 
+// Deeper low-frequency widths (adaptive trees, Section 2.2).  The kernel is not
+// scale invariant, so each width w = 1/4, 1/8, ... has its own non-directional
+// skeleton, sampled like the width-1/2 one: the boxes at the interaction-list
+// offsets of width w, plus the check points of the width-2w skeleton seen from
+// the 8 child positions (where LF-M2M and LF-L2L evaluate the child's
+// skeleton).
+void build_lf_deep(OpSetImpl& set, int n) {
+  const double tau = set.tau;
+  const std::vector<int64_t> offs = list_offsets_e2(0);
+  while (int(set.lf_deep.size()) < n) {
+    const int k = int(set.lf_deep.size()) + 1;  // width 2^-(1 + k)
+    const double w = std::ldexp(0.5, -k);
+    const Skel& parent = k == 1 ? set.lf : set.lf_deep[size_t(k) - 2];
+    Rng rng(kSeed ^ (uint64_t(0x5a5a) << 32) ^ uint64_t(k));
+    std::vector<double> cen;
+    for (int64_t v : offs) cen.push_back(w * double(v));
+    int n_own, n_y;
+    sample_sizes(w, tau, &n_own, &n_y);
+    std::vector<double> X;
+    sample_boxes(rng, cen, w, n_own, X);
+    add_inherited(parent, w, X);
+    std::vector<double> Y(3 * size_t(n_y));
+    for (auto& v : Y) v = (rng.uniform() - 0.5) * w;
+    set.lf_deep.push_back(make_skeleton(X, Y, tau, kSeed ^ (uint64_t(0x3c3c) << 40) ^ uint64_t(k)));
+  }
+}
+
 // ---- file format ----------------------------------------------------------
 // "DFMMOPS2", float64 tau, int32 w_hi, int32 count, then `count` skeletons in
 // the order w = 1 (dirs 0..5), w = 2 (0..23), ..., w_hi, then the LF skeleton;
@@ -554,6 +581,71 @@ bool load_opset(OpSetImpl& set, const std::string& path) {
     if (ok) get(set.lf);
   }
   std::fclose(f);
+  return ok;
+}
+
+}  // namespace dfmm
+
+namespace dfmm {
+
+// "DFMMLFD1", float64 tau, int32 n, then n skeletons (widths 1/4, 1/8, ...) as
+// in the operator-set file.
+bool save_lf_deep(const OpSetImpl& set, const std::string& path) {
+  std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return false;
+  bool ok = true;
+  auto W = [&](const void* p, size_t n) { ok = ok && std::fwrite(p, 1, n, f) == n; };
+  W("DFMMLFD1", 8);
+  W(&set.tau, 8);
+  int32_t cnt = int32_t(set.lf_deep.size());
+  W(&cnt, 4);
+  for (const Skel& s : set.lf_deep) {
+    int32_t r = s.r;
+    W(&r, 4);
+    W(s.a.data(), 8 * s.a.size());
+    W(s.b.data(), 8 * s.b.size());
+    W(s.D.data(), 8 * s.D.size());
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  if (ok) ok = std::rename(tmp.c_str(), path.c_str()) == 0;
+  if (!ok) std::remove(tmp.c_str());
+  return ok;
+}
+
+bool load_lf_deep(OpSetImpl& set, const std::string& path, int n) {
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return false;
+  bool ok = true;
+  auto R = [&](void* p, size_t k) { ok = ok && std::fread(p, 1, k, f) == k; };
+  char magic[8];
+  R(magic, 8);
+  ok = ok && std::memcmp(magic, "DFMMLFD1", 8) == 0;
+  double tau = 0.0;
+  int32_t cnt = 0;
+  R(&tau, 8);
+  R(&cnt, 4);
+  ok = ok && tau == set.tau && cnt >= n && cnt <= kMaxLfLevels;
+  std::vector<Skel> out;
+  for (int i = 0; ok && i < n; ++i) {
+    Skel s;
+    int32_t r = 0;
+    R(&r, 4);
+    if (!ok || r < 1 || r > 4096) {
+      ok = false;
+      break;
+    }
+    s.r = r;
+    s.a.resize(3 * size_t(r));
+    s.b.resize(3 * size_t(r));
+    s.D.resize(2 * size_t(r) * r);
+    R(s.a.data(), 8 * s.a.size());
+    R(s.b.data(), 8 * s.b.size());
+    R(s.D.data(), 8 * s.D.size());
+    out.push_back(std::move(s));
+  }
+  std::fclose(f);
+  if (ok) set.lf_deep = std::move(out);
   return ok;
 }
 

@@ -41,10 +41,16 @@ __global__ void k_morton(const double* __restrict__ pts, int64_t n, double half,
 
 }  // namespace
 
-void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT) {
+// extra > 0 (adaptive trees): the points are keyed and sorted at level D + extra
+// and the box tables cover every level down to it (all boxes, split or not);
+// the leaf tables below are those of level D, which a uniform plan uses.
+void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K, Tree& T, DevTree& DT,
+                       int extra) {
   int D = 0;
   while (std::ldexp(1.0, D) < 2.0 * K) ++D;
   T.D = D;
+  const int Dk = D + extra;  // depth of the sort keys
+  if (3 * Dk > 63) throw Error{DFMM_EUNSUPPORTED, "tree too deep for 64-bit Morton keys"};
   DevBuf dpts, k0, k1, v0, v1, tmp;
   dpts.alloc(sizeof(double) * 3 * N);
   DFMM_HIP(hipMemcpy(dpts.p, points, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
@@ -52,13 +58,13 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   k1.alloc(sizeof(unsigned long long) * N);
   v0.alloc(sizeof(int) * N);
   v1.alloc(sizeof(int) * N);
-  double scale = std::ldexp(1.0, D) / K;  // a power of two
+  double scale = std::ldexp(1.0, Dk) / K;  // a power of two
   int bs = 256;
   hipLaunchKernelGGL(k_morton, dim3(unsigned((N + bs - 1) / bs)), dim3(bs), 0, 0, dpts.as<double>(), N,
-                     K / 2.0, scale, D, k0.as<unsigned long long>(), v0.as<int>());
+                     K / 2.0, scale, Dk, k0.as<unsigned long long>(), v0.as<int>());
   DFMM_HIP(hipGetLastError());
   size_t tb = 0;
-  unsigned end_bit = unsigned(3 * D);
+  unsigned end_bit = unsigned(3 * Dk);
   DFMM_HIP(rocprim::radix_sort_pairs(nullptr, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
                                      v0.as<int>(), v1.as<int>(), size_t(N), 0u, end_bit));
   tmp.alloc(tb);
@@ -72,7 +78,7 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
     for (int a = 0; a < 3; ++a) T.pts[3 * s + a] = points[3 * int64_t(idx[s]) + a];
 
   // box tables per level, from the sorted keys (lists.hip)
-  build_levels_device(k1.as<unsigned long long>(), N, D, T, DT);
+  build_levels_device(k1.as<unsigned long long>(), N, Dk, T, DT);
 
   // sorted points on the device, split into float hi + lo parts
   std::vector<float> hi(4 * size_t(N), 0.0f), lo(4 * size_t(N), 0.0f);

@@ -33,6 +33,7 @@ NOALLOC_MAX_BYTES = 64 << 20  # DFMM_NOALLOC_MAX_BYTES
 PREC_FP32, PREC_FP16X3, PREC_BF16X3, PREC_FP64 = 0, 1, 2, 3  # DFMM_PREC_*
 
 EXPORT_PERM, EXPORT_BOXES, EXPORT_PAIRS, EXPORT_NEAR, EXPORT_OUT_SLOTS, EXPORT_IN_SLOTS = 1, 2, 3, 4, 5, 6
+EXPORT_LEAVES = 7
 
 ABI_FUNCTIONS = [
     "dfmm_status_string", "dfmm_last_error", "dfmm_opset_build", "dfmm_opset_create",
@@ -47,7 +48,8 @@ ABI_FUNCTIONS = [
 class Options(C.Structure):
     _fields_ = [("eps", C.c_double), ("opset", C.c_void_p), ("cache_dir", C.c_char_p),
                 ("device", C.c_int), ("precision", C.c_int), ("leaf_width", C.c_double),
-                ("tol_factor", C.c_double), ("hbm_budget_bytes", C.c_uint64), ("reserved", C.c_int * 4)]
+                ("tol_factor", C.c_double), ("hbm_budget_bytes", C.c_uint64), ("leaf_max", C.c_int),
+                ("lf_levels", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class Info(C.Structure):
@@ -60,7 +62,8 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("bytes_m2l_op", C.c_double),
                 ("bytes_m2l_vec", C.c_double), ("flops_m2l_level", C.c_double * 32), ("tau", C.c_double),
                 ("flops_m2m", C.c_double), ("flops_l2l", C.c_double),
-                ("bytes_l2l_op", C.c_double), ("bytes_l2l_vec", C.c_double)]
+                ("bytes_l2l_op", C.c_double), ("bytes_l2l_vec", C.c_double), ("leaves", C.c_int64),
+                ("depth_max", C.c_int), ("reserved_i", C.c_int)]
 
 
 _P = C.c_void_p
@@ -182,7 +185,8 @@ class Plan:
 
     def __init__(self, points, K: float, eps: float = 1e-4, opset: OpSet | None = None,
                  cache_dir: str | None = None, device: int = -1, precision: int = 0,
-                 leaf_width: float = 0.0, tol_factor: float = 0.0, hbm_budget_bytes: int = 0):
+                 leaf_width: float = 0.0, tol_factor: float = 0.0, hbm_budget_bytes: int = 0,
+                 leaf_max: int = 0, lf_levels: int = 0):
         pts = np.ascontiguousarray(points, dtype=np.float64)
         if pts.ndim != 2 or pts.shape[1] != 3:
             raise ValueError("points must be (N, 3)")
@@ -197,6 +201,8 @@ class Plan:
         opt.leaf_width = leaf_width
         opt.tol_factor = tol_factor
         opt.hbm_budget_bytes = hbm_budget_bytes
+        opt.leaf_max = leaf_max
+        opt.lf_levels = lf_levels
         h = _P()
         _check(_lib.dfmm_plan_ex(_dptr(pts), pts.shape[0], float(K), C.byref(opt), C.byref(h)))
         self._h = h
@@ -304,7 +310,7 @@ class Plan:
         buf = np.empty(n.value // 8, dtype=np.int64)
         _check(_lib.dfmm_export(self._h, what, level, buf.ctypes.data_as(C.c_void_p), C.byref(n)))
         width = {EXPORT_PERM: 1, EXPORT_BOXES: 5, EXPORT_PAIRS: 5, EXPORT_NEAR: 2,
-                 EXPORT_OUT_SLOTS: 2, EXPORT_IN_SLOTS: 2}[what]
+                 EXPORT_OUT_SLOTS: 2, EXPORT_IN_SLOTS: 2, EXPORT_LEAVES: 4}[what]
         return buf if width == 1 else buf.reshape(-1, width)
 
     def set_timing(self, applies: int) -> None:

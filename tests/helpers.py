@@ -5,8 +5,9 @@ from oracle import operators as O
 from oracle.cache import oracle_opset  # noqa: F401  (re-exported for the tests)
 
 
-def inject(ops: O.OpSet):
-    """Copy an oracle operator set into a library OpSet (dfmm_opset_create / _set)."""
+def inject(ops: O.OpSet, deep=()):
+    """Copy an oracle operator set into a library OpSet (dfmm_opset_create / _set);
+    ``deep``: the oracle's skeletons of the LF widths 1/4, 1/8, ... (adaptive trees)."""
     from paper_1311_4257_amd import dfmm
 
     s = dfmm.OpSet.create(ops.tau, ops.w_hi)
@@ -14,6 +15,8 @@ def inject(ops: O.OpSet):
         for d, sk in enumerate(sks):
             s.set(float(w), d, sk.a, sk.b, sk.D)
     s.set(0.5, 0, ops.lf.a, ops.lf.b, ops.lf.D)
+    for k, sk in enumerate(deep):
+        s.set(0.5 / 2 ** (k + 1), 0, sk.a, sk.b, sk.D)
     return s
 
 

@@ -68,6 +68,14 @@ def test_bad_inputs_rejected_on_the_host():
         dfmm.Plan(good, 4.0, tol_factor=2.0)        # tau = tol_factor eps needs tol_factor in (0, 1]
     with pytest.raises(dfmm.DfmmError, match="EINVAL"):
         dfmm.Plan(good, 4.0, tol_factor=-0.1)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, leaf_max=-1)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        dfmm.Plan(good, 4.0, leaf_max=16, lf_levels=7)  # at most 6 levels below width 1/2
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 4.0, leaf_max=16, precision=dfmm.PREC_FP16X3)  # adaptive trees: float32 only
+    with pytest.raises(dfmm.DfmmError, match="EUNSUPPORTED"):
+        dfmm.Plan(good, 4.0, eps=1e-6, leaf_max=16)  # ... and eps >= 1e-5 (the slot form)
     lib = dfmm._lib
     n = ctypes.c_size_t()
     assert lib.dfmm_workspace_bytes(None, 1, ctypes.byref(n)) == -1
@@ -152,6 +160,21 @@ def test_opset_roundtrip_and_injection(tmp_path):
             for x, y in zip(s.get(w, d), t.get(w, d)):
                 assert np.array_equal(x, y)
     assert t.info() == (1e-3, 1)
+    # the deeper LF widths of adaptive trees (w = 1/4, 1/8, ...): set, read back;
+    # a width not yet set is refused, and so are widths that are not LF widths
+    for w in (0.25, 0.125):
+        r = 4 if w == 0.25 else 3
+        a, b = rng.random((r, 3)), rng.random((r, 3))
+        Dm = rng.random((r, r)) + 1j * rng.random((r, r))
+        s.set(w, 0, a, b, Dm)
+        ga, gb, gD = s.get(w, 0)
+        assert np.array_equal(ga, a) and np.array_equal(gb, b) and np.array_equal(gD, Dm)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        s.get(0.0625, 0)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        s.set(0.3, 0, a, b, Dm)
+    with pytest.raises(dfmm.DfmmError, match="EINVAL"):
+        s.set(0.25, 1, a, b, Dm)
 
 
 def test_struct_layouts_match_the_header(tmp_path):
