@@ -344,6 +344,9 @@ def main() -> int:
     ap.add_argument("--workload", default="ellipsoid32", choices=sorted(WORKLOADS),
                     help="the K=32 ellipsoid with 32 rhs (default, the headline line) or the K=16 sphere")
     ap.add_argument("--eps", type=float, default=None, help="plan eps (default: the workload's)")
+    ap.add_argument("--leaf-max", type=int, default=0,
+                    help="adaptive low-frequency tree: split boxes of width <= 1/2 holding more points "
+                         "(0: the uniform tree)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--serve", action="store_true", help="the serving mix instead of one workload")
     ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS),
@@ -380,7 +383,7 @@ def main() -> int:
     K, N, nrhs, eps = cfg["K"], cfg["N"], cfg["nrhs"], cfg["eps"]
     dev = torch.device("cuda:0")
     prec, dtype = PRECISIONS[args.precision]
-    plan = dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0, precision=prec)
+    plan = dfmm.Plan(pts, K, eps=eps, cache_dir=CACHE_DIR, device=0, precision=prec, leaf_max=args.leaf_max)
     info = plan.info()
     fd = torch.from_numpy(f.astype(np.complex64)).to(dev)
     u = torch.empty_like(fd)
@@ -491,9 +494,11 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload][0] + f", eps={eps_s}",
+        "config": {"workload": WORKLOADS[args.workload][0] + f", eps={eps_s}"
+                               + (f", adaptive LF tree (leaf_max={args.leaf_max})" if args.leaf_max else ""),
                    "K": K, "N": N, "nrhs": nrhs, "eps": eps, "w_top": info.w_top,
-                   "ranks": [int(info.rank[l]) for l in range(info.depth + 1)]},
+                   "ranks": [int(info.rank[l]) for l in range(info.depth_max + 1)],
+                   "leaves": int(info.leaves), "depth_max": int(info.depth_max)},
         "rel_l2_err": err,
         "accuracy_ok": bool(err <= eps),
         "stage_ms": per_stage,
