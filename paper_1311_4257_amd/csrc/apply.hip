@@ -826,7 +826,11 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
   for (int n = 0; n < NT; ++n)
 #pragma unroll
     for (int q = 0; q < 4; ++q) a64[n][q] = 0.0;
-  auto compute = [&](const Tm& T, const float4 (&r)[PMAX], int buf) {
+  // The products of one term.  The operator tile lives in one set of registers:
+  // as soon as pair p has been turned into MFMA fragments, the next term's pair
+  // p is loaded into it (reload: a term of Q4n steps from base rn), so that
+  // load has a whole term of products to land.
+  auto compute = [&](const Tm& T, float4 (&r)[PMAX], int buf, bool reload, const float4* rn, int Q4n) {
     const int Q4 = T.Kg / 8;
     const float4* bcol = xs + buf * NC * S4 + j * S4 + kr * Q4;
     v4f acc[NT];
@@ -839,6 +843,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
         // the complex A fragments as real rows (even row: Re, -Im; odd row: Im, Re)
         const float a0[4] = {odd ? w.y : v.x, odd ? w.x : -v.y, odd ? w.w : v.z, odd ? w.z : -v.w};
         const float a1[4] = {odd ? v.y : w.x, odd ? v.x : -w.y, odd ? v.w : w.z, odd ? v.z : -w.w};
+        if (reload && 2 * p < Q4n) r[p] = rn[min(2 * p + (odd ? 1 : 0), Q4n - 1) * 32];
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
           const float4 b = bcol[n * 16 * S4 + 2 * p];
@@ -857,6 +862,8 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
             acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b.w, acc[n], 0, 0, 0);
           }
         }
+      } else if (reload && 2 * p < Q4n) {  // the next term is longer than this one
+        r[p] = rn[min(2 * p + (odd ? 1 : 0), Q4n - 1) * 32];
       }
     }
 #pragma unroll
@@ -870,50 +877,32 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     int4* tl = reinterpret_cast<int4*>(xs + 2 * NC * S4);
     for (int i = tid; i < te - tb; i += BS) tl[i] = a.terms[tb + i];
     __syncthreads();
-    float4 ra[PMAX], rb[PMAX];
+    float4 r[PMAX];
     Tm T = decode(tl[0]);
-    if (act) op_load(T, ra);
+    if (act) op_load(T, r);
     x_load(T);
     x_store(0, T);
     __syncthreads();
-    // two terms per iteration, so that the operator registers alternate statically.
-    // Each half first retires every load in flight (the operator tile issued one
-    // term earlier) and only then issues the next term's loads: the compiler
-    // cannot count the conditional loads, and without this wait it waits for
-    // the prefetch itself before the first product of the term.
-    for (int t = tb;;) {
-      {
-        const bool more = t + 1 < te;
-        Tm Tn = T;
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        if (more) {
-          Tn = decode(tl[t + 1 - tb]);
-          if (act) op_load(Tn, rb);
-          x_load(Tn);
-        }
-        if (act) compute(T, ra, 0);
-        if (more) x_store(1, Tn);
-        __syncthreads();
-        if (!more) break;
-        T = Tn;
-        ++t;
+    // Each term first retires every load in flight (its operator tile, loaded
+    // during the previous term) and only then issues the next term's column
+    // loads: the compiler cannot count the conditional loads, and without this
+    // wait it waits for the prefetch itself before the first product.
+    for (int t = tb, buf = 0;; ++t, buf ^= 1) {
+      const bool more = t + 1 < te;
+      Tm Tn = T;
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+      if (more) {
+        Tn = decode(tl[t + 1 - tb]);
+        x_load(Tn);
       }
-      {
-        const bool more = t + 1 < te;
-        Tm Tn = T;
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        if (more) {
-          Tn = decode(tl[t + 1 - tb]);
-          if (act) op_load(Tn, ra);
-          x_load(Tn);
-        }
-        if (act) compute(T, rb, 1);
-        if (more) x_store(0, Tn);
-        __syncthreads();
-        if (!more) break;
-        T = Tn;
-        ++t;
+      if (act) {
+        const int Q4n = Tn.Kg / 8;
+        compute(T, r, buf, more, Tn.A + m * (Q4n * 32) + lofs, Q4n);
       }
+      if (more) x_store(buf ^ 1, Tn);
+      __syncthreads();
+      if (!more) break;
+      T = Tn;
     }
   }
   // lane (j, kr) holds real rows 4 kr .. 4 kr + 3 (complex rows 2 kr, 2 kr + 1) of
