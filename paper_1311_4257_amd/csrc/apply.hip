@@ -20,6 +20,8 @@
 #include <mutex>
 #include <set>
 #include <string>
+#include <type_traits>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -750,6 +752,17 @@ constexpr int SLOT_UB = 2;  // staged float4 per thread and term
 // 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
 constexpr int kWaitVm0 = 0x0F70;
 
+// f(std::integral_constant<int, q>) for the runtime q in 1 .. QMAX (nothing
+// for any other q): one branch-free body per term length
+template <int QMAX, typename F, int... I>
+__device__ __forceinline__ void slot_dispatch_seq(int q, F&& f, std::integer_sequence<int, I...>) {
+  (void)((q == I + 1 && (f(std::integral_constant<int, I + 1>{}), true)) || ...);
+}
+template <int QMAX, typename F>
+__device__ __forceinline__ void slot_dispatch(int q, F&& f) {
+  slot_dispatch_seq<QMAX>(q, static_cast<F&&>(f), std::make_integer_sequence<int, QMAX>{});
+}
+
 template <int NT, int PMAX>
 __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* __restrict__ Y) {
   constexpr int NC = NT * 16;
@@ -774,9 +787,13 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
   struct Tm {
     const float4* A;
     const float2* X;  // column c0 of the source slot
-    int KX, Kg, split;
+    int KX, Kg, split, mg;
   };
-  auto decode = [&](const int4 e) {  // e: the term's table entry
+  auto decode = [&](int4 e) {  // e: the term's table entry (wave-uniform)
+    e.x = __builtin_amdgcn_readfirstlane(e.x);
+    e.y = __builtin_amdgcn_readfirstlane(e.y);
+    e.z = __builtin_amdgcn_readfirstlane(e.z);
+    e.w = __builtin_amdgcn_readfirstlane(e.w);
     const int kind = (e.z >> 14) & 1;
     Tm r;
     r.KX = kind ? a.KX1 : a.KX0;
@@ -784,9 +801,12 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     r.X = (kind ? a.X1 : a.X0) + (int64_t(e.y) * nrhs + c0) * r.KX;
     r.Kg = e.z & 0xFFF;
     r.split = (e.z >> 12) & 3;
+    r.mg = e.w;
     return r;
   };
   float4 xv[SLOT_UB];
+  // thread index idx < 2^11 as (column, float4 of the column): idx / (Kg / 2) by
+  // the term's multiplier
   auto x_load = [&](const Tm& T) {  // this thread's share of the term's columns
     const int per_col = T.Kg / 2, pcs = per_col / T.split, nel = NC * per_col;
 #pragma unroll
@@ -794,7 +814,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
       const int idx = tid + u * BS;
       xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (idx < nel) {
-        const int col = idx / per_col, q4 = idx - col * per_col;
+        const int col = int(__umul24(unsigned(idx), unsigned(T.mg)) >> 23), q4 = idx - col * per_col;
         if (col < nc)
           xv[u] = reinterpret_cast<const float4*>(T.X + int64_t(col) * T.KX)[q4 < pcs ? q4 : q4 - pcs];
       }
@@ -807,65 +827,63 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     for (int u = 0; u < SLOT_UB; ++u) {
       const int idx = tid + u * BS;
       if (idx < nel) {
-        const int col = idx / per_col, q4 = idx - col * per_col;
+        const int col = int(__umul24(unsigned(idx), unsigned(T.mg)) >> 23), q4 = idx - col * per_col;
         xb[col * S4 + q4] = xv[u];
       }
     }
   };
-  // this wave's tile of the term's operator: pair p holds k-steps 2p (even lane)
-  // and 2p + 1 (odd lane; the last step again past an odd end)
-  auto op_load = [&](const Tm& T, float4 (&r)[PMAX]) {
-    const int Q4 = T.Kg / 8;
-    const float4* base = T.A + m * (Q4 * 32) + lofs;
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p)
-      if (2 * p < Q4) r[p] = base[min(2 * p + (odd ? 1 : 0), Q4 - 1) * 32];
-  };
+  // this wave's tile of a term's operator (Q4 k-steps from base): pair p holds
+  // k-steps 2p (even lane) and 2p + 1 (odd lane); pairs past the end repeat the
+  // last step, so every load stays inside the tile
+  auto op_pair = [&](const float4* base, int Q4, int p) { return base[min(2 * p + (odd ? 1 : 0), Q4 - 1) * 32]; };
   double a64[NT][4];
 #pragma unroll
   for (int n = 0; n < NT; ++n)
 #pragma unroll
     for (int q = 0; q < 4; ++q) a64[n][q] = 0.0;
-  // The products of one term.  The operator tile lives in one set of registers:
-  // as soon as pair p has been turned into MFMA fragments, the next term's pair
-  // p is loaded into it (reload: a term of Q4n steps from base rn), so that
-  // load has a whole term of products to land.
-  auto compute = [&](const Tm& T, float4 (&r)[PMAX], int buf, bool reload, const float4* rn, int Q4n) {
-    const int Q4 = T.Kg / 8;
+  // The products of one term of Q4 k-steps (a compile-time count, so the body
+  // has no branches).  The operator tile lives in one set of registers: as soon
+  // as pair p has been turned into MFMA fragments, the next term's pair p is
+  // loaded into it (a term of Q4n steps from base rn), so that load has a whole
+  // term of products to land.
+  auto compute = [&](auto q4c, float4 (&r)[PMAX], int buf, const float4* rn, int Q4n) {
+    constexpr int Q4 = decltype(q4c)::value;
     const float4* bcol = xs + buf * NC * S4 + j * S4 + kr * Q4;
     v4f acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-      if (2 * p < Q4) {
-        const float4 v = r[p], w = swap_pair(v);
-        // the complex A fragments as real rows (even row: Re, -Im; odd row: Im, Re)
-        const float a0[4] = {odd ? w.y : v.x, odd ? w.x : -v.y, odd ? w.w : v.z, odd ? w.z : -v.w};
-        const float a1[4] = {odd ? v.y : w.x, odd ? v.x : -w.y, odd ? v.w : w.z, odd ? v.z : -w.w};
-        if (reload && 2 * p < Q4n) r[p] = rn[min(2 * p + (odd ? 1 : 0), Q4n - 1) * 32];
+    for (int p = 0; p < (Q4 + 1) / 2; ++p) {
+      const float4 v = r[p], w = swap_pair(v);
+      // the complex A fragments as real rows (even row: Re, -Im; odd row: Im, Re)
+      const float a0[4] = {odd ? w.y : v.x, odd ? w.x : -v.y, odd ? w.w : v.z, odd ? w.z : -v.w};
+      const float a1[4] = {odd ? v.y : w.x, odd ? v.x : -w.y, odd ? v.w : w.z, odd ? v.z : -w.w};
+      r[p] = op_pair(rn, Q4n, p);
+      // the scheduler would otherwise move the reload down to the end of the
+      // term, where it can no longer land during the products
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const float4 b = bcol[n * 16 * S4 + 2 * p];
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b.x, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b.y, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b.z, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b.w, acc[n], 0, 0, 0);
+      }
+      if (2 * p + 1 < Q4) {
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const float4 b = bcol[n * 16 * S4 + 2 * p];
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[0], b.x, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[1], b.y, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[2], b.z, acc[n], 0, 0, 0);
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[3], b.w, acc[n], 0, 0, 0);
+          const float4 b = bcol[n * 16 * S4 + 2 * p + 1];
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b.x, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b.y, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b.z, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b.w, acc[n], 0, 0, 0);
         }
-        if (2 * p + 1 < Q4) {
-#pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            const float4 b = bcol[n * 16 * S4 + 2 * p + 1];
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[0], b.x, acc[n], 0, 0, 0);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[1], b.y, acc[n], 0, 0, 0);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[2], b.z, acc[n], 0, 0, 0);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[3], b.w, acc[n], 0, 0, 0);
-          }
-        }
-      } else if (reload && 2 * p < Q4n) {  // the next term is longer than this one
-        r[p] = rn[min(2 * p + (odd ? 1 : 0), Q4n - 1) * 32];
       }
     }
+    // the next term is longer than this one
+#pragma unroll
+    for (int p = (Q4 + 1) / 2; p < PMAX; ++p) r[p] = op_pair(rn, Q4n, p);
 #pragma unroll
     for (int n = 0; n < NT; ++n)
 #pragma unroll
@@ -879,14 +897,19 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     __syncthreads();
     float4 r[PMAX];
     Tm T = decode(tl[0]);
-    if (act) op_load(T, r);
+    if (act) {
+      const float4* base = T.A + m * (T.Kg / 8 * 32) + lofs;
+#pragma unroll
+      for (int p = 0; p < PMAX; ++p) r[p] = op_pair(base, T.Kg / 8, p);
+    }
     x_load(T);
     x_store(0, T);
     __syncthreads();
     // Each term first retires every load in flight (its operator tile, loaded
     // during the previous term) and only then issues the next term's column
-    // loads: the compiler cannot count the conditional loads, and without this
-    // wait it waits for the prefetch itself before the first product.
+    // loads: without this wait the compiler waits for the prefetch itself
+    // before the first product.  The last term reloads its own tile (a
+    // harmless repeat) so that the body is the same for every term.
     for (int t = tb, buf = 0;; ++t, buf ^= 1) {
       const bool more = t + 1 < te;
       Tm Tn = T;
@@ -897,7 +920,8 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
       }
       if (act) {
         const int Q4n = Tn.Kg / 8;
-        compute(T, r, buf, more, Tn.A + m * (Q4n * 32) + lofs, Q4n);
+        const float4* rn = Tn.A + m * (Q4n * 32) + lofs;
+        slot_dispatch<2 * PMAX>(T.Kg / 8, [&](auto q4c) { compute(q4c, r, buf, rn, Q4n); });
       }
       if (more) x_store(buf ^ 1, Tn);
       __syncthreads();

@@ -305,13 +305,16 @@ void build_slot_gemm(SlotGemm& S, int M, int64_t ngroups, const std::vector<int3
     if (!k.G) throw Error{DFMM_EINVAL, "slot term of a kind without operators"};
     const int64_t aoff = k.G->aoff_h[size_t(t.op)];
     const int kp = k.G->kpk_h[size_t(t.op)];
-    if (aoff > INT32_MAX || kp >= (1 << 12) || k.split > 3)
+    if (aoff > INT32_MAX || kp >= (1 << 12) || kp < 8 || kp % 8 != 0 || k.split > 3)
       throw Error{DFMM_EUNSUPPORTED, "operator table too large for the slot-form GEMM"};
     int32_t* e = &tab[size_t(4) * size_t(pos[size_t(t.dst)]++)];
     e[0] = int32_t(aoff);
     e[1] = t.src;
     e[2] = kp | (k.split << 12) | (t.kind << 14);
-    e[3] = 0;
+    // column staging divides a thread's index (< 2^11) by the term's float4 per
+    // column (kp / 2 < 2^11): the quotient is (idx * e[3]) >> 23 exactly for
+    // e[3] = ceil(2^23 / (kp / 2)), since idx times the rounding excess is < 2^23
+    e[3] = int32_t(((1u << 23) + uint32_t(kp / 2) - 1) / uint32_t(kp / 2));
     kmax = std::max(kmax, kp);
     S.split2 = S.split2 || k.split != 1;
     S.flops[t.kind] += k.G->opflops[size_t(t.op)];
