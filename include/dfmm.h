@@ -194,7 +194,9 @@ int dfmm_plan_ex(const double* points, int64_t N, double K, const dfmm_options* 
  * graph (stream capture on `stream`) once an uncaptured apply with the same
  * nrhs has run on the plan; the captured apply reads f and writes u at the
  * addresses given at capture.  Capturing before that returns DFMM_EINVAL;
- * stage timing is off inside a capture. */
+ * stage timing is off inside a capture.  A captured graph stays valid when a
+ * later apply with more right-hand sides grows the workspace: once a plan has
+ * been captured, the workspaces it replaces are kept until dfmm_destroy. */
 int dfmm_apply(dfmm_plan_t plan, const void* f, void* u, int nrhs, void* stream);
 
 /* Batched form of dfmm_apply for a request loop: nreq (1 .. DFMM_MAX_BATCH)

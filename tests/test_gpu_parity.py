@@ -215,7 +215,8 @@ def test_back_to_back_applies_on_a_stream(cuda):
 def test_graph_captured_apply_replays_match_eager(cuda):
     """An apply captured into a HIP graph (after one uncaptured apply with the same
     nrhs) replays bitwise equal to eager applies, with eager work and host
-    synchronisation between the replays; capturing first is refused."""
+    synchronisation between the replays, also after a larger apply has grown
+    the plan's workspace; capturing first is refused."""
     import torch
 
     pts, _, cfg = workloads.make_config("sphere4")
@@ -250,6 +251,17 @@ def test_graph_captured_apply_replays_match_eager(cuda):
             assert np.array_equal(u.cpu().numpy(), ref)
     # the eager path still works after the capture
     assert np.array_equal(plan.apply(xs[0]).cpu().numpy(), eager[0])
+    # a larger apply grows the workspace; the graph still addresses the old one,
+    # which the plan keeps, so replays stay equal to the eager results
+    big = _to_dev(rng.standard_normal((12, N)) + 1j * rng.standard_normal((12, N)), cuda)
+    plan.apply(big)
+    torch.cuda.synchronize()
+    for xx, ref in zip(xs, eager):
+        x.copy_(xx)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref)
 
 
 def test_repeat_is_bitwise_deterministic(cuda):
