@@ -276,7 +276,8 @@ def serving_bench(args) -> int:
                               "rel_l2_err_batched_form": acc_b[nm]}
                              for nm, pl, ps in zip(names, plans, plan_s)],
                    "single_form": "fp32, one request per pass, one pass at a time",
-                   "batched_form": f"{args.precision}, continuous batching per plan, plans concurrent",
+                   "batched_form": f"{args.precision}, continuous batching per plan, plans concurrent "
+                                   "(the library's native request loop)",
                    "max_batch_rhs": 32, "hbm_budget_gib": budget / 2 ** 30},
         "serving": {
             "saturation": sat,
@@ -287,6 +288,8 @@ def serving_bench(args) -> int:
             "footprint_gib": batched.footprint() / 2 ** 30,
         },
     }
+    single.close()
+    batched.close()
     print(json.dumps(line))
     return 0
 

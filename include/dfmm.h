@@ -260,6 +260,56 @@ int dfmm_apply_noalloc(dfmm_plan_t plan, const void* f, void* u, int nrhs, void*
 void dfmm_destroy(dfmm_plan_t plan);
 
 /* ------------------------------------------------------------------------
+ * Serving: continuous batching of matvec requests over resident plans.
+ *
+ * An iterative boundary-integral solver issues one matvec per iteration
+ * (Section 1); a serving process keeps the plans of several geometries on one
+ * device and takes such requests as they come.  A server owns one stream per
+ * plan (default priority) and a worker thread.  The worker starts a plan's next
+ * pass (one dfmm_apply_batch) as soon as the plan's previous pass has
+ * finished, so passes of different plans run concurrently and requests that
+ * arrive while a plan is busy join its next pass.  A pass takes the plan's
+ * queued requests in submission order, up to max_batch_rhs right-hand sides
+ * (a longer request runs alone) and DFMM_MAX_BATCH requests, while the HBM
+ * footprint stays within hbm_budget_bytes.  The footprint counts the resident
+ * plans (dfmm_info.device_bytes) plus each plan's workspace at the largest
+ * pass it has run (dfmm_workspace_bytes; workspaces only grow).  Plans whose
+ * oldest queued request is older start first.  With single != 0 a pass holds
+ * one request and one pass runs at a time, in submission order: the plain
+ * form, for comparison.  Completion is reported by a host function enqueued
+ * behind each pass; nothing polls.
+ *
+ * The plans must share one device and must not be applied elsewhere while the
+ * server lives; float64 plans are refused (DFMM_EUNSUPPORTED).  Each request
+ * reads f and writes u (DEVICE pointers, complex64, [nrhs][N], caller's point
+ * order, not overlapping): f must hold its values when dfmm_server_submit is
+ * called (synchronize the stream that wrote them first), and neither may be
+ * touched or freed until dfmm_server_wait has returned for it.  A request that
+ * can never fit the budget fails with DFMM_ENOMEM, at submission when it does
+ * not fit then, else in its dfmm_server_wait.  Times are seconds on the
+ * server's monotonic clock (dfmm_server_now, 0 at creation): t_submit when the
+ * request was taken, t_done when the host function after its pass ran. */
+typedef struct dfmm_server_s* dfmm_server_t;
+int dfmm_server_create(const dfmm_plan_t* plans, int nplans, size_t hbm_budget_bytes, int max_batch_rhs,
+                       int single, dfmm_server_t* out);
+/* Queues a request for plan index `plan` (into the array given at creation);
+ * *ticket names it in dfmm_server_wait.  Thread-safe; does not wait. */
+int dfmm_server_submit(dfmm_server_t s, int plan, const void* f, void* u, int nrhs, int64_t* ticket);
+/* Blocks until the request has finished; returns its status (DFMM_OK, or the
+ * error of its pass).  Either time pointer may be null. */
+int dfmm_server_wait(dfmm_server_t s, int64_t ticket, double* t_submit, double* t_done);
+/* Blocks until no request is queued or in flight. */
+int dfmm_server_drain(dfmm_server_t s);
+double dfmm_server_now(dfmm_server_t s);
+/* Passes started so far, and pass i's plan index, request count and total nrhs. */
+int dfmm_server_passes(dfmm_server_t s, int64_t* n);
+int dfmm_server_pass(dfmm_server_t s, int64_t i, int* plan, int* nreq, int* nrhs);
+/* The current HBM footprint under the admission rule. */
+int dfmm_server_footprint(dfmm_server_t s, size_t* bytes);
+/* Waits for every submitted request, then frees the server (not the plans). */
+void dfmm_server_destroy(dfmm_server_t s);
+
+/* ------------------------------------------------------------------------
  * Introspection (tests and benchmarks)
  * ---------------------------------------------------------------------- */
 

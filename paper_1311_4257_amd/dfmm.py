@@ -28,6 +28,7 @@ _lib = C.CDLL(LIB_PATH)
 STAGES = ["permute_in", "s2m", "hf_m2m", "hf_m2l", "hf_reduce", "hf_l2l", "lf_m2l", "lf_reduce",
           "leaf_eval", "zero", "near_field"]
 
+OK, EINVAL, EDOMAIN, EUNSUPPORTED, ENOMEM, EDEVICE, EIO = 0, -1, -2, -3, -4, -5, -6  # dfmm_status
 MAX_BATCH = 32  # DFMM_MAX_BATCH
 NOALLOC_MAX_BYTES = 64 << 20  # DFMM_NOALLOC_MAX_BYTES
 PREC_FP32, PREC_FP16X3, PREC_BF16X3, PREC_FP64 = 0, 1, 2, 3  # DFMM_PREC_*
@@ -42,6 +43,8 @@ ABI_FUNCTIONS = [
     "dfmm_apply_batch", "dfmm_workspace_bytes", "dfmm_apply_ws", "dfmm_apply_noalloc", "dfmm_destroy",
     "dfmm_plan_info", "dfmm_export",
     "dfmm_set_timing", "dfmm_stage_times",
+    "dfmm_server_create", "dfmm_server_submit", "dfmm_server_wait", "dfmm_server_drain", "dfmm_server_now",
+    "dfmm_server_passes", "dfmm_server_pass", "dfmm_server_footprint", "dfmm_server_destroy",
 ]
 
 
@@ -93,6 +96,15 @@ _sig = {
     "dfmm_export": (C.c_int, [_P, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_size_t)]),
     "dfmm_set_timing": (C.c_int, [_P, C.c_int]),
     "dfmm_stage_times": (C.c_int, [_P, _D, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
+    "dfmm_server_create": (C.c_int, [C.POINTER(_P), C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(_P)]),
+    "dfmm_server_submit": (C.c_int, [_P, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int64)]),
+    "dfmm_server_wait": (C.c_int, [_P, C.c_int64, _D, _D]),
+    "dfmm_server_drain": (C.c_int, [_P]),
+    "dfmm_server_now": (C.c_double, [_P]),
+    "dfmm_server_passes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "dfmm_server_pass": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "dfmm_server_footprint": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "dfmm_server_destroy": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -328,6 +340,79 @@ class Plan:
     def close(self) -> None:
         if self._h:
             _lib.dfmm_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A continuous-batching request loop over resident plans (dfmm_server_*):
+    one stream per plan and a native worker thread that starts each plan's
+    next pass when its previous one has finished.  Blocking calls release the
+    GIL."""
+
+    def __init__(self, plans, budget_bytes: int, max_batch_rhs: int = 32, single: bool = False):
+        self.plans = list(plans)
+        arr = (_P * len(self.plans))(*[p._h.value for p in self.plans])
+        h = _P()
+        _check(_lib.dfmm_server_create(arr, len(self.plans), int(budget_bytes), int(max_batch_rhs),
+                                       int(bool(single)), C.byref(h)))
+        self._h = h
+
+    def submit(self, plan: int, f, u) -> int:
+        """Queue u = A f for plan index ``plan`` ((nrhs, N) complex64 CUDA tensors;
+        f must hold its values already); returns the request's ticket."""
+        import torch
+
+        if not 0 <= plan < len(self.plans):
+            raise ValueError("no such plan")
+        N = self.plans[plan].N
+        if f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous() or f.dim() != 2 or f.shape[1] != N:
+            raise ValueError("f must be a contiguous (nrhs, N) complex64 CUDA tensor")
+        if u.shape != f.shape or u.dtype != f.dtype or not u.is_contiguous():
+            raise ValueError("u must be a contiguous tensor shaped and typed like f")
+        t = C.c_int64()
+        _check(_lib.dfmm_server_submit(self._h, plan, C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()),
+                                       f.shape[0], C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int):
+        """Blocks until the request has finished; returns (t_submit, t_done) in
+        seconds on the server's clock, or raises DfmmError with its status."""
+        a, b = C.c_double(), C.c_double()
+        _check(_lib.dfmm_server_wait(self._h, int(ticket), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def drain(self) -> None:
+        _check(_lib.dfmm_server_drain(self._h))
+
+    def now(self) -> float:
+        return _lib.dfmm_server_now(self._h)
+
+    def passes(self) -> list:
+        """(plan, requests, nrhs) of every pass started so far, in order."""
+        n = C.c_int64()
+        _check(_lib.dfmm_server_passes(self._h, C.byref(n)))
+        out = []
+        p, q, k = C.c_int(), C.c_int(), C.c_int()
+        for i in range(n.value):
+            _check(_lib.dfmm_server_pass(self._h, i, C.byref(p), C.byref(q), C.byref(k)))
+            out.append((p.value, q.value, k.value))
+        return out
+
+    def footprint(self) -> int:
+        b = C.c_size_t()
+        _check(_lib.dfmm_server_footprint(self._h, C.byref(b)))
+        return b.value
+
+    def close(self) -> None:
+        """Waits for every submitted request, then frees the server."""
+        if self._h:
+            _lib.dfmm_server_destroy(self._h)
             self._h = _P()
 
     def __del__(self):

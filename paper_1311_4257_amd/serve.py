@@ -1,32 +1,23 @@
-"""Continuous-batching request loop over plans resident on one GPU.
+"""Serving harness over the library's request loop (``dfmm.Server``).
 
 An iterative boundary-integral solver issues one matvec per iteration; a
-serving process holds the plans of several geometries (each plan keeps its
-tree, lists and translation operators on the device) and receives such
-matvec requests as they come.  This loop:
+serving process holds the plans of several geometries and receives such
+matvec requests as they come.  The loop itself is native (``dfmm_server_*``):
+one stream per plan (default priority), a worker thread that starts a plan's
+next pass, as one ``dfmm_apply_batch``, when its previous pass has finished,
+from the plan's requests queued so far (submission order, up to
+``max_batch_rhs`` right-hand sides and ``dfmm.MAX_BATCH`` requests, within an
+HBM budget with grow-only workspaces), and completion reported by a host
+function behind each pass.  ``mode="single"`` is the plain single-request
+form: one request per pass and one pass at a time, in submission order.
 
-* keeps one stream per plan (default priority) and at most one batch in flight
-  per plan; batches of different plans run concurrently on the device;
-* forms a plan's next batch, when its previous one has finished, from the
-  requests of that plan queued so far, in arrival order, up to ``max_batch_rhs``
-  right-hand sides and ``dfmm.MAX_BATCH`` requests, and only while the HBM
-  footprint stays within ``budget_bytes``: the resident plans plus every plan's
-  workspace at the largest batch it has run (the workspace is grow-only);
-* runs a batch as one ``dfmm_apply_batch`` pass (densities gathered from the
-  requests' own buffers, potentials scattered to theirs), so requests that
-  arrive while others are on the GPU join the next pass of their plan.
-
-``mode="single"`` is the plain single-request form for comparison: one request
-per pass and one pass in flight at a time, in arrival order.
-
-Completion times come from timing events recorded after each pass on the
-plan's stream, read against an event recorded when the run starts, so a
-latency is (pass end on the GPU) - (arrival on the host clock) without host
-polling granularity.
+This module replays a list of requests against such a server at their
+arrival times (the calling thread sleeps until each arrival and submits it)
+and reads back every request's submission and completion time on the
+server's clock, for throughput and latency figures.
 """
 from __future__ import annotations
 
-import collections
 import dataclasses
 import time
 
@@ -41,151 +32,79 @@ class Request:
     plan: int          # index into the server's plans
     f: object          # (nrhs, N) complex64 device tensor
     u: object          # (nrhs, N) complex64 device tensor, written by the pass
-    arrival: float     # seconds after the run starts
+    arrival: float     # seconds after the run starts (when it is submitted)
+    submitted: float = float("nan")  # seconds after the run starts, server clock
     done: float = float("nan")
+    ticket: int = -1
 
     @property
     def nrhs(self) -> int:
         return int(self.f.shape[0])
 
+    @property
+    def latency(self) -> float:
+        return self.done - self.submitted
+
 
 class Server:
-    def __init__(self, plans, budget_bytes: int, max_batch_rhs: int = 32, mode: str = "batched", device=0):
+    """A native server over ``plans`` plus the replay harness.  The plans must
+    not be applied elsewhere while a run is in progress."""
+
+    def __init__(self, plans, budget_bytes: int, max_batch_rhs: int = 32, mode: str = "batched"):
         if mode not in ("batched", "single"):
             raise ValueError(mode)
         self.plans = list(plans)
-        self.budget = int(budget_bytes)
-        self.max_rhs = int(max_batch_rhs)
         self.mode = mode
-        self.device = device
-        self.streams = None  # created on first use (one per plan)
-        self.resident = sum(int(p.info().device_bytes) for p in self.plans)
-        self.cap = [0] * len(self.plans)  # largest batch nrhs run per plan (workspace size)
-        self._wsb = {}
-        self.batches = []  # (plan, [rid...], nrhs) of the last run, in launch order
+        self.srv = dfmm.Server(self.plans, budget_bytes, max_batch_rhs, single=mode == "single")
+        self.batches = []  # (plan, requests, nrhs) of the last run's passes, in launch order
 
-    def ws_bytes(self, p: int, nrhs: int) -> int:
-        if nrhs <= 0:
-            return 0
-        key = (p, nrhs)
-        if key not in self._wsb:
-            self._wsb[key] = self.plans[p].workspace_bytes(nrhs)
-        return self._wsb[key]
-
-    def footprint(self, p: int | None = None, nrhs: int = 0) -> int:
-        """HBM bytes held with plan p's workspace grown to nrhs (current state if p is None)."""
-        tot = self.resident
-        for q in range(len(self.plans)):
-            c = self.cap[q]
-            if q == p:
-                c = max(c, nrhs)
-            tot += self.ws_bytes(q, c)
-        return tot
-
-    def _dev(self):
-        import torch
-
-        if self.streams is None:
-            self.device = torch.device("cuda", self.device) if isinstance(self.device, int) else self.device
-            self.streams = [torch.cuda.Stream(device=self.device) for _ in self.plans]
-        return self.device
+    def footprint(self) -> int:
+        return self.srv.footprint()
 
     def warm(self, sizes):
-        """Run one pass per plan and batch size (workspace growth, tuning, chunk
-        tables) before the timed runs, as far as the budget allows."""
+        """One pass per plan and batch size (workspace growth, launch shapes,
+        chunk tables) before the timed runs, as far as the budget allows."""
         import torch
 
-        self._dev()
         for p, plan in enumerate(self.plans):
             for n in sorted(set(sizes)):
-                if self.footprint(p, n) > self.budget:
-                    break
-                f = torch.zeros((n, plan.N), dtype=torch.complex64, device=self.device)
+                f = torch.zeros((n, plan.N), dtype=torch.complex64, device="cuda")
                 u = torch.empty_like(f)
-                plan.apply_batch([f], [u], self.streams[p])
-                self.cap[p] = max(self.cap[p], n)
-            self.streams[p].synchronize()
+                torch.cuda.synchronize()
+                try:
+                    self.srv.wait(self.srv.submit(p, f, u))
+                except dfmm.DfmmError as e:
+                    if e.status != dfmm.ENOMEM:
+                        raise
+                    break
 
-    def _take(self, p: int, q: collections.deque):
-        """Requests of plan p's next batch (removed from q), or [] if none fits."""
-        take, n = [], 0
-        while q and len(take) < dfmm.MAX_BATCH:
-            r = q[0]
-            if take and (n + r.nrhs > self.max_rhs or self.mode == "single"):
-                break
-            if self.footprint(p, n + r.nrhs) > self.budget:
-                break
-            take.append(q.popleft())
-            n += r.nrhs
-        return take, n
-
-    def run(self, requests):
-        """Serve ``requests`` (sorted by arrival); fills each one's ``done`` and
-        returns the run's makespan in seconds."""
+    def run(self, requests) -> float:
+        """Submit ``requests`` at their arrival times, wait for all of them, fill
+        each one's ``submitted`` and ``done``; returns the span from the first
+        submission to the last completion, in seconds."""
         import torch
 
-        self._dev()
         reqs = sorted(requests, key=lambda r: r.arrival)
-        P = len(self.plans)
-        queues = [collections.deque() for _ in range(P)]
-        fifo = collections.deque()  # single mode: one queue over all plans
-        inflight = [None] * P       # (event, requests)
-        ends = []                   # (event, requests) of every pass
-        self.batches = []
-        torch.cuda.synchronize(self.device)
-        start = torch.cuda.Event(enable_timing=True)
-        start.record(torch.cuda.current_stream(self.device))
-        t0 = time.perf_counter()
-        i, busy = 0, 0
-        while i < len(reqs) or busy or any(queues) or fifo:
-            now = time.perf_counter() - t0
-            while i < len(reqs) and reqs[i].arrival <= now:
-                r = reqs[i]
-                (fifo if self.mode == "single" else queues[r.plan]).append(r)
-                i += 1
-            for p in range(P):
-                if inflight[p] is not None and inflight[p][0].query():
-                    inflight[p] = None
-                    busy -= 1
-            if self.mode == "single":
-                if busy == 0 and fifo:
-                    r = fifo[0]
-                    self._launch(r.plan, [fifo.popleft()], r.nrhs, inflight, ends)
-                    busy += 1
-                continue
-            # idle plans, oldest queued request first
-            idle = [p for p in range(P) if inflight[p] is None and queues[p]]
-            for p in sorted(idle, key=lambda p: queues[p][0].arrival):
-                take, n = self._take(p, queues[p])
-                if take:
-                    self._launch(p, take, n, inflight, ends)
-                    busy += 1
-            if busy == 0 and any(queues):
-                raise RuntimeError("a request does not fit the HBM budget even alone")
-        torch.cuda.synchronize(self.device)
-        last = 0.0
-        for ev, batch in ends:
-            t = start.elapsed_time(ev) * 1e-3
-            for r in batch:
-                r.done = t
-            last = max(last, t)
-        first = reqs[0].arrival if reqs else 0.0
-        return last - first
+        torch.cuda.synchronize()  # every request's densities are in place
+        before = len(self.srv.passes())
+        t0 = self.srv.now()
+        for r in reqs:
+            d = t0 + r.arrival - self.srv.now()
+            if d > 0:
+                time.sleep(d)
+            r.ticket = self.srv.submit(r.plan, r.f, r.u)
+        self.srv.drain()
+        for r in reqs:
+            ts, td = self.srv.wait(r.ticket)
+            r.submitted, r.done = ts - t0, td - t0
+        self.batches = self.srv.passes()[before:]
+        return max(r.done for r in reqs) - min(r.submitted for r in reqs) if reqs else 0.0
 
-    def _launch(self, p, batch, n, inflight, ends):
-        import torch
-
-        s = self.streams[p]
-        self.plans[p].apply_batch([r.f for r in batch], [r.u for r in batch], s)
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record(s)
-        self.cap[p] = max(self.cap[p], n)
-        inflight[p] = (ev, batch)
-        ends.append((ev, batch))
-        self.batches.append((p, [r.rid for r in batch], n))
+    def close(self) -> None:
+        self.srv.close()
 
 
 def latency_stats(requests) -> dict:
-    lat = np.array([r.done - r.arrival for r in requests])
+    lat = np.array([r.latency for r in requests])
     return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3)}

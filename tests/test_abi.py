@@ -84,6 +84,20 @@ def test_bad_inputs_rejected_on_the_host():
     arr = (ctypes.c_void_p * 1)(None)
     cnt = (ctypes.c_int * 1)(1)
     assert lib.dfmm_apply_batch(None, 1, arr, arr, cnt, None) == -1
+    # the serving loop's entry points refuse null or empty arguments on the host
+    srv = ctypes.c_void_p()
+    plans = (ctypes.c_void_p * 1)(None)
+    assert lib.dfmm_server_create(None, 1, 1 << 30, 16, 0, ctypes.byref(srv)) == -1
+    assert lib.dfmm_server_create(plans, 0, 1 << 30, 16, 0, ctypes.byref(srv)) == -1
+    assert lib.dfmm_server_create(plans, 1, 1 << 30, 16, 0, ctypes.byref(srv)) == -1  # null plan
+    assert lib.dfmm_server_create(plans, 1, 1 << 30, 0, 0, ctypes.byref(srv)) == -1   # max_batch_rhs
+    assert lib.dfmm_server_create(plans, 1, 1 << 30, 16, 0, None) == -1
+    t = ctypes.c_int64()
+    assert lib.dfmm_server_submit(None, 0, None, None, 1, ctypes.byref(t)) == -1
+    assert lib.dfmm_server_wait(None, 0, None, None) == -1
+    assert lib.dfmm_server_drain(None) == -1
+    assert lib.dfmm_server_passes(None, ctypes.byref(t)) == -1
+    lib.dfmm_server_destroy(None)
 
 
 def test_hbm_budget_refuses_a_plan_before_any_device_call():

@@ -1,4 +1,4 @@
-"""GPU: batched applies and the continuous-batching request loop.
+"""GPU: batched applies and the native continuous-batching request loop.
 
 Every request's result must be the same alone and in a batch or a mix of
 plans: the columns of a pass do not share arithmetic, so the comparison is
@@ -88,15 +88,19 @@ def test_apply_batch_matches_separate_applies(cuda):
 
 
 def test_request_loop_results_equal_alone_results(cuda):
-    """A mix of two plans, requests arriving together and staggered, nrhs 1-5:
-    the loop must batch (some pass holds several requests), overlap plans, and
-    return for every request what its plan gives it alone; the single-request
-    form returns the same."""
+    """A mix of two plans, requests arriving together and staggered, nrhs 1-5,
+    through the native request loop: it must batch (some pass holds several
+    requests), keep passes within the rhs cap, and return for every request
+    what its plan gives it alone; the single-request form returns the same.
+    A sample of the served results also meets eps against the float64 direct
+    sum of Eq. 1."""
     import torch
 
+    from oracle.kernel import direct_sum, rel_l2
     from paper_1311_4257_amd.serve import Request, Server, latency_stats
 
     plans = _plans()
+    pts = [workloads.sphere_points(4096, 4.0, 1), workloads.ellipsoid_points(6000, (4.0, 2.0, 1.0), 3)]
     gen = torch.Generator(device=cuda)
     gen.manual_seed(12)
     rng = np.random.default_rng(13)
@@ -118,10 +122,59 @@ def test_request_loop_results_equal_alone_results(cuda):
         print(mode, f"{len(srv.batches)} passes, span {span * 1e3:.1f} ms", latency_stats(reqs))
         assert np.isfinite(span) and span > 0
         for r, a in zip(reqs, alone):
-            assert r.done >= r.arrival
+            assert r.done >= r.submitted >= 0
             assert _rel(r.u.cpu().numpy(), a) <= TOL, (mode, r.rid)
         if mode == "batched":
-            assert max(len(b[1]) for b in srv.batches) > 1
-            assert all(b[2] <= 16 or len(b[1]) == 1 for b in srv.batches)
+            assert max(b[1] for b in srv.batches) > 1
+            assert all(b[2] <= 16 or b[1] == 1 for b in srv.batches)
         else:
-            assert len(srv.batches) == len(reqs)
+            assert len(srv.batches) == len(reqs) and all(b[1] == 1 for b in srv.batches)
+        assert sum(b[1] for b in srv.batches) == len(reqs)
+        srv.close()
+    for r in reqs[:6]:
+        tg = workloads.sample_targets(plans[r.plan].N, 256, 100 + r.rid)
+        ref = direct_sum(pts[r.plan], r.f.cpu().numpy().astype(np.complex128), tg)
+        assert rel_l2(r.u.cpu().numpy().astype(np.complex128)[:, tg], ref) <= 1e-4, r.rid
+
+
+def test_server_admission_and_errors(cuda):
+    """The native loop's admission and argument checks on the device: a request
+    that can never fit the HBM budget is refused at submission (DFMM_ENOMEM),
+    one that fits runs; bad plan indices, shapes and float64 plans are refused;
+    the footprint is the resident plans plus the grown workspaces."""
+    import torch
+
+    from paper_1311_4257_amd import dfmm
+
+    plans = _plans()
+    resident = sum(int(p.info().device_bytes) for p in plans)
+    ws4 = plans[0].workspace_bytes(4)
+    srv = dfmm.Server(plans, budget_bytes=resident + ws4, max_batch_rhs=16)
+    assert srv.footprint() == resident
+    gen = torch.Generator(device=cuda)
+    gen.manual_seed(14)
+    f = _dens(torch, plans[0].N, 4, gen, cuda)
+    u = torch.empty_like(f)
+    torch.cuda.synchronize()
+    srv.wait(srv.submit(0, f, u))
+    assert srv.footprint() == resident + ws4
+    assert _rel(u.cpu().numpy(), plans[0].apply(f).cpu().numpy()) <= TOL
+    big = _dens(torch, plans[0].N, 5, gen, cuda)
+    with pytest.raises(dfmm.DfmmError) as e:
+        srv.submit(0, big, torch.empty_like(big))
+    assert e.value.status == dfmm.ENOMEM
+    with pytest.raises(dfmm.DfmmError) as e:  # plan 1's workspace does not fit next to plan 0's
+        g = _dens(torch, plans[1].N, 1, gen, cuda)
+        srv.submit(1, g, torch.empty_like(g))
+    assert e.value.status == dfmm.ENOMEM
+    with pytest.raises(ValueError):
+        srv.submit(2, f, u)
+    with pytest.raises(ValueError):
+        srv.submit(1, f, u)  # wrong N for plan 1
+    assert [p[0] for p in srv.passes()] == [0]
+    srv.close()
+    pts, _, cfg = workloads.make_config("sphere4")
+    p64 = dfmm.Plan(pts, cfg["K"], eps=1e-8, cache_dir=CACHE, device=0, precision=dfmm.PREC_FP64)
+    with pytest.raises(dfmm.DfmmError) as e:
+        dfmm.Server([p64], budget_bytes=1 << 40)
+    assert e.value.status == dfmm.EUNSUPPORTED
