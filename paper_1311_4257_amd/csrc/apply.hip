@@ -1753,7 +1753,19 @@ static void launch_gemm(const Launch& L, int nrhs, const float2* X, float2* Y, h
 }
 
 // ---- slot-form launches ----------------------------------------------------------------
-constexpr int kSlotMinRhs = 16;  // fast float32 plans take the slot form from this many rhs
+// Columns per slot-form workgroup: 32 from 17 right-hand sides on (padding one
+// chunk is cheaper than a second chunk that reads every operator again).
+static int slot_nt(int nrhs) { return nrhs > 16 ? 2 : 1; }
+
+// The slot form pads its work to whole 32-column chunks and costs about 0.92 of
+// the pair form per column at 32 columns (0.90-1.02 over the six serving plans
+// and the K = 32 ellipsoid), so a fast float32 plan takes it where the padded
+// columns still cost less: 30-32, 59-64, ... right-hand sides.
+static bool slot_pays(int nrhs) {
+  if (nrhs <= 16) return false;
+  const int padded = (nrhs + 31) / 32 * 32;
+  return 0.92 * padded <= double(nrhs);
+}
 
 static size_t slot_lds_bytes(const SlotGemm& S, int nt) {
   return size_t(2) * size_t(nt * 16) * size_t(gg_stride(S.Kmax)) * sizeof(float) +
@@ -1778,11 +1790,11 @@ static bool prepare_slot(SlotLaunch& L, const SlotGemm& S, int nrhs, int nt) {
          slot_lds_bytes(S, nt) <= size_t(kGgDynLds);
 }
 
-// The slot form serves fast float32 plans with at least kSlotMinRhs right-hand
-// sides (DFMM_SLOT=0 forces the pair form, =1 allows it from 1 rhs).
+// The slot form serves fast float32 plans where it pays (DFMM_SLOT=0 forces the
+// pair form, =1 the slot form wherever its launches fit).
 static bool use_slot(const dfmm_plan_s& P, int nrhs) {
   if (P.leaf_max > 0) {  // adaptive trees run the LF levels in the slot form only
-    const int nt = nrhs >= 32 ? 2 : 1;
+    const int nt = slot_nt(nrhs);
     SlotLaunch tmp;
     bool ok = prepare_slot(tmp, P.lf.down, nrhs, nt);
     for (const auto& H : P.hf) ok = ok && prepare_slot(tmp, H.up, nrhs, nt) && prepare_slot(tmp, H.down, nrhs, nt);
@@ -1791,13 +1803,13 @@ static bool use_slot(const dfmm_plan_s& P, int nrhs) {
     return true;
   }
   if (P.precise || P.prec != DFMM_PREC_FP32) return false;
-  int minr = kSlotMinRhs;
+  bool want = slot_pays(nrhs);
   if (const char* e = std::getenv("DFMM_SLOT")) {
     if (e[0] == '0') return false;
-    if (e[0] == '1') minr = 1;
+    if (e[0] == '1') want = true;
   }
-  if (nrhs < minr) return false;
-  const int nt = nrhs >= 32 ? 2 : 1;
+  if (!want) return false;
+  const int nt = slot_nt(nrhs);
   SlotLaunch tmp;
   for (const auto& H : P.hf)
     if (!prepare_slot(tmp, H.up, nrhs, nt) || !prepare_slot(tmp, H.down, nrhs, nt)) return false;
@@ -1832,7 +1844,7 @@ static void launch_slot(const SlotLaunch& L, const float4* A0, const float2* X0,
 }
 
 static void prepare_slot_set(const dfmm_plan_s& P, int nrhs, LaunchSet& LS) {
-  const int nt = nrhs >= 32 ? 2 : 1;
+  const int nt = slot_nt(nrhs);
   LS.slot = true;
   LS.up.resize(P.hf.size());
   LS.down.resize(P.hf.size());
@@ -2217,10 +2229,13 @@ static LaunchSet& launch_set(dfmm_plan_s& P, ApplyState& AS, const Ws& S, int nr
   } else if ((nrhs & (nrhs - 1)) == 0) {
     tune_launches(P, nrhs, S, *ls, st);
   } else {
+    // the pair form's shapes from the largest power of two below whose set is
+    // in the pair form (1 always is)
     int p2 = 1;
     while (2 * p2 < nrhs) p2 *= 2;
+    while (p2 > 1 && use_slot(P, p2)) p2 /= 2;
     const LaunchSet& from = launch_set(P, AS, S, p2, st);
-    if (from.slot) prepare_slot_set(P, nrhs, *ls);  // no tuned shapes to inherit
+    if (from.slot) tune_launches(P, nrhs, S, *ls, st);  // no pair-form shapes below
     else inherit_launches(P, nrhs, from, *ls);
   }
   return *AS.sets.emplace(nrhs, std::move(ls)).first->second;

@@ -65,6 +65,8 @@ def test_injected_k8_matches_oracle(cuda, k8, monkeypatch, nrhs, fused, prec):
     32 rhs) against the oracle's float64 pass."""
     pts, st, ops, f, ref = k8
     monkeypatch.setenv("DFMM_FUSED", fused)
+    if nrhs >= 16:
+        monkeypatch.setenv("DFMM_SLOT", "1")  # the slot form, also where the pair form costs less
     plan = _dfmm().Plan(pts, 8.0, opset=inject(ops), device=0, precision=prec)
     u = plan.apply(_to_dev(f[:nrhs], cuda)).cpu().numpy()
     _check(u, ref[:nrhs], f"K=8 injected nrhs={nrhs} fused={fused} prec={prec}")
@@ -82,7 +84,7 @@ def test_slot_form_equals_pair_form(cuda, monkeypatch, nrhs):
     f = workloads.densities(len(pts), nrhs, 52)
     fd = _to_dev(f, cuda)
     out = {}
-    for mode in ("0", ""):
+    for mode in ("0", "1"):
         monkeypatch.setenv("DFMM_SLOT", mode)
         plan = dfmm.Plan(pts, 8.0, eps=1e-4, cache_dir=CACHE, device=0)
         a = plan.apply(fd).cpu().numpy()
@@ -91,7 +93,7 @@ def test_slot_form_equals_pair_form(cuda, monkeypatch, nrhs):
         out[mode] = a.astype(np.complex128)
         plan.close()
     for k in range(nrhs):
-        d = rel_l2(out[""][k], out["0"][k])
+        d = rel_l2(out["1"][k], out["0"][k])
         assert d < 1e-6, (k, d)
     tg = workloads.sample_targets(len(pts), 256, 53)
     ref = direct_sum(pts, f, tg)
@@ -99,10 +101,11 @@ def test_slot_form_equals_pair_form(cuda, monkeypatch, nrhs):
         assert rel_l2(out[mode][:, tg], ref) <= 1e-4
 
 
-def test_slot_form_column_chunks(cuda):
+def test_slot_form_column_chunks(cuda, monkeypatch):
     """16 rhs (one 16-column tile per slot) and 32 rhs (one 32-column tile) give the
     same columns to float32 rounding: a column's far-field arithmetic does not
     depend on the other columns of its tile."""
+    monkeypatch.setenv("DFMM_SLOT", "1")
     pts = workloads.sphere_points(16384, 8.0, 61)
     f = workloads.densities(len(pts), 32, 62)
     plan = _dfmm().Plan(pts, 8.0, eps=1e-4, cache_dir=CACHE, device=0)
@@ -132,3 +135,20 @@ def test_injected_k16_matches_oracle(cuda, k16, monkeypatch, nrhs, fused, prec):
     plan = _dfmm().Plan(pts, 16.0, opset=inject(ops), device=0, precision=prec)
     u = plan.apply(_to_dev(f[:nrhs], cuda)).cpu().numpy()
     _check(u, ref[:nrhs], f"K=16 injected nrhs={nrhs} fused={fused} prec={prec}")
+
+
+@pytest.mark.parametrize("nrhs,form", [(16, "0"), (20, "0"), (31, "1"), (32, "1"), (40, "0")])
+def test_default_form_follows_the_cost_rule(cuda, monkeypatch, nrhs, form):
+    """Without DFMM_SLOT a float32 plan takes the slot form only where its work,
+    padded to 32-column chunks, still costs less than the pair form's (30-32,
+    59-64, ... rhs): the default apply equals the forced form bit for bit."""
+    dfmm = _dfmm()
+    pts = workloads.sphere_points(8192, 8.0, 71)
+    fd = _to_dev(workloads.densities(len(pts), nrhs, 72), cuda)
+    out = {}
+    for mode in ("", form):
+        monkeypatch.setenv("DFMM_SLOT", mode)
+        plan = dfmm.Plan(pts, 8.0, eps=1e-4, cache_dir=CACHE, device=0)
+        out[mode] = plan.apply(fd).cpu().numpy()
+        plan.close()
+    assert np.array_equal(out[""], out[form])
