@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdfmm.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "skeleton.cpp", "serve.cpp", "tree.hip", "lists.hip", "apply.hip", "apply64.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "skeleton.cpp", "serve.cpp", "radix.hip", "tree.hip", "lists.hip", "apply.hip", "apply64.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -285,6 +285,13 @@ struct DevTree {
   std::vector<DevBuf> incl;  // per level: inclusive box count at each sorted point
 };
 void build_levels_device(const unsigned long long* sorted_key, int64_t N, int D, Tree& T, DevTree& DT);
+// radix.hip: stable LSD radix sort of 64-bit keys (and int values) over the key
+// bits [0, end_bit) into separate outputs, and int32 prefix sums (null stream)
+void sort_pairs_u64(const unsigned long long* kin, unsigned long long* kout, const int* vin, int* vout, int64_t n,
+                    int end_bit);
+void sort_keys_u64(const unsigned long long* kin, unsigned long long* kout, int64_t n, int end_bit);
+void scan_incl(const int* in, int* out, int64_t n);
+void scan_excl(const int* in, int* out, int64_t n);
 // I^B of every box of level l, sorted by (B, A); `fields` keeps the device copy
 // ([np][7] int32: B, A, nx, ny, nz, l_in, l_out).
 std::vector<PairRec> level_pairs_device(const DevTree& DT, int D, int l, DevBuf& fields);

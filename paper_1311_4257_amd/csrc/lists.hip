@@ -15,8 +15,6 @@
 // built from it.
 #include <hip/hip_runtime.h>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <vector>
@@ -210,22 +208,6 @@ std::vector<T> download(const DevBuf& b, int64_t n) {
   return h;
 }
 
-void scan_incl(const int* in, int* out, int64_t n) {
-  size_t tb = 0;
-  DFMM_HIP(rocprim::inclusive_scan(nullptr, tb, in, out, size_t(n), rocprim::plus<int>()));
-  DevBuf tmp;
-  tmp.alloc(std::max<size_t>(tb, 4));
-  DFMM_HIP(rocprim::inclusive_scan(tmp.p, tb, in, out, size_t(n), rocprim::plus<int>()));
-}
-
-void scan_excl(const int* in, int* out, int64_t n) {
-  size_t tb = 0;
-  DFMM_HIP(rocprim::exclusive_scan(nullptr, tb, in, out, 0, size_t(n), rocprim::plus<int>()));
-  DevBuf tmp;
-  tmp.alloc(std::max<size_t>(tb, 4));
-  DFMM_HIP(rocprim::exclusive_scan(tmp.p, tb, in, out, 0, size_t(n), rocprim::plus<int>()));
-}
-
 int64_t last_int(const DevBuf& b, int64_t i) {
   int v = 0;
   DFMM_HIP(hipMemcpy(&v, static_cast<const int*>(b.p) + i, sizeof(int), hipMemcpyDeviceToHost));
@@ -340,17 +322,12 @@ std::vector<PairRec> level_pairs_device(const DevTree& DT, int D, int l, DevBuf&
   const int64_t np = offsets_of(cnt, off, L.nb);
   fields.alloc(sizeof(int) * 7 * size_t(std::max<int64_t>(1, np)));
   if (np == 0) return out;
-  DevBuf k0, k1, tmp;
+  DevBuf k0, k1;
   k0.alloc(sizeof(unsigned long long) * size_t(np));
   k1.alloc(sizeof(unsigned long long) * size_t(np));
   hipLaunchKernelGGL((k_pairs<1>), dim3(nblk(L.nb)), dim3(kBS), 0, 0, L, U, e2, noff.as<int>(), nnoff, nullptr,
                      off.as<int>(), k0.as<unsigned long long>());
-  size_t tb = 0;
-  DFMM_HIP(rocprim::radix_sort_keys(nullptr, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
-                                    size_t(np)));
-  tmp.alloc(std::max<size_t>(tb, 4));
-  DFMM_HIP(rocprim::radix_sort_keys(tmp.p, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
-                                    size_t(np)));
+  sort_keys_u64(k0.as<unsigned long long>(), k1.as<unsigned long long>(), np, 64);
   hipLaunchKernelGGL(k_pair_fields, dim3(nblk(np)), dim3(kBS), 0, 0, k1.as<unsigned long long>(), np, L, e2,
                      fields.as<int>());
   DFMM_HIP(hipGetLastError());

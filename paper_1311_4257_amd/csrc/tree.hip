@@ -7,11 +7,9 @@
 // [0, 2^D - 1], the sum rounded first in float64 and the scaling by a power of
 // two exact.  The key interleaves the bits of (ix, iy, iz) with x lowest, so
 // the root octant is the most significant digit.  Points are ordered by
-// (key, original index): a stable LSD radix sort over the 3D key bits of
-// pairs whose values start as the identity.
+// (key, original index): a stable LSD radix sort (radix.hip) over the 3D key
+// bits of pairs whose values start as the identity.
 #include <hip/hip_runtime.h>
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -51,7 +49,7 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   T.D = D;
   const int Dk = D + extra;  // depth of the sort keys
   if (3 * Dk > 63) throw Error{DFMM_EUNSUPPORTED, "tree too deep for 64-bit Morton keys"};
-  DevBuf dpts, k0, k1, v0, v1, tmp;
+  DevBuf dpts, k0, k1, v0, v1;
   dpts.alloc(sizeof(double) * 3 * N);
   DFMM_HIP(hipMemcpy(dpts.p, points, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
   k0.alloc(sizeof(unsigned long long) * N);
@@ -63,13 +61,8 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   hipLaunchKernelGGL(k_morton, dim3(unsigned((N + bs - 1) / bs)), dim3(bs), 0, 0, dpts.as<double>(), N,
                      K / 2.0, scale, Dk, k0.as<unsigned long long>(), v0.as<int>());
   DFMM_HIP(hipGetLastError());
-  size_t tb = 0;
-  unsigned end_bit = unsigned(3 * Dk);
-  DFMM_HIP(rocprim::radix_sort_pairs(nullptr, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
-                                     v0.as<int>(), v1.as<int>(), size_t(N), 0u, end_bit));
-  tmp.alloc(tb);
-  DFMM_HIP(rocprim::radix_sort_pairs(tmp.p, tb, k0.as<unsigned long long>(), k1.as<unsigned long long>(),
-                                     v0.as<int>(), v1.as<int>(), size_t(N), 0u, end_bit));
+  sort_pairs_u64(k0.as<unsigned long long>(), k1.as<unsigned long long>(), v0.as<int>(), v1.as<int>(), N,
+                 3 * Dk);
   std::vector<int> idx(N);
   DFMM_HIP(hipMemcpy(idx.data(), v1.p, sizeof(int) * N, hipMemcpyDeviceToHost));
   T.perm.assign(idx.begin(), idx.end());
