@@ -852,6 +852,11 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
     v4f acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
+    // The workgroup barrier keeps a SIMD's waves in step, so they reach their
+    // staging work (term decode, column loads and stores) together and the
+    // matrix core idles meanwhile; a wave in its products takes issue
+    // priority over one that is staging.
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int p = 0; p < (Q4 + 1) / 2; ++p) {
       const float4 v = r[p], w = swap_pair(v);
@@ -881,6 +886,7 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     // the next term is longer than this one
 #pragma unroll
     for (int p = (Q4 + 1) / 2; p < PMAX; ++p) r[p] = op_pair(rn, Q4n, p);
