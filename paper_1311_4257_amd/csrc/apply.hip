@@ -848,7 +848,11 @@ __device__ __forceinline__ void slot_gemm(const SlotArgs& a, int nrhs, float2* _
   // term of products to land.
   auto compute = [&](auto q4c, float4 (&r)[PMAX], int buf, const float4* rn, int Q4n) {
     constexpr int Q4 = decltype(q4c)::value;
-    const float4* bcol = xs + buf * NC * S4 + j * S4 + kr * Q4;
+    // kr made opaque for each term: otherwise the compiler hoists kr * Q4 for
+    // every length out of the term loop and spills the fourteen offsets
+    int kro = kr;
+    asm volatile("" : "+v"(kro));
+    const float4* bcol = xs + buf * NC * S4 + j * S4 + kro * Q4;
     v4f acc[NT];
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[n] = v4f{0.f, 0.f, 0.f, 0.f};
