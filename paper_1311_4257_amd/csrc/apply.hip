@@ -1363,17 +1363,19 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           continue;
         }
-        // products: MFMA step q covers sources 2q, 2q + 1
+        // products: MFMA step q covers sources 2q, 2q + 1.  The lane's A entry
+        // is component rodd ^ kp of G (Re G, -Im G on even rows, Im G, Re G on
+        // odd ones: negated where the row is even and k is Im), its B entry
+        // component kp of the density: single-float reads, no selects.
+        const float* gf = reinterpret_cast<const float*>(gw + tr * GS + (kk >> 1)) + ((rodd ? 1 : 0) ^ kp);
+        const float* ff = reinterpret_cast<const float*>(sf + (kk >> 1) * NCOL + rr) + kp;
+        const unsigned gneg = (!rodd && kp) ? 0x80000000u : 0u;
 #pragma unroll 4
         for (int q = 0; q < NM_SC / 2; ++q) {
-          const int src = 2 * q + (kk >> 1);
-          const float2 g = gw[tr * GS + src];
-          const float av = rodd ? (kp ? g.x : g.y) : (kp ? -g.y : g.x);
+          const float av = __uint_as_float(__float_as_uint(gf[2 * 2 * q]) ^ gneg);
 #pragma unroll
-          for (int c = 0; c < NCT; ++c) {
-            const float2 f = sf[src * NCOL + c * 16 + rr];
-            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, kp ? f.y : f.x, acc[i][c], 0, 0, 0);
-          }
+          for (int c = 0; c < NCT; ++c)
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ff[2 * (2 * q * NCOL + c * 16)], acc[i][c], 0, 0, 0);
           if ((q & 7) == 7) {
 #pragma unroll
             for (int c = 0; c < NCT; ++c) {
