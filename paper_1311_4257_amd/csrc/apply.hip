@@ -51,44 +51,18 @@ __device__ __forceinline__ double2 green_d(double dx, double dy, double dz) {
   return make_double2(double(c) * ri, double(s) * ri);
 }
 
-// sin and cos of 2 pi t for |t| <= 1/2 (t in turns): quadrant q = rint(4 t),
-// f = t - q/4 (exact), x = 2 pi f in [-pi/4, pi/4]; Taylor polynomials of sin
-// (to x^9) and cos (to x^10) have truncation errors below 2e-9 there, so the
-// float32 rounding (~1e-7) dominates; the quadrant rotates the pair.
-__device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
-  const float q = rintf(4.0f * t);
-  const float f = fmaf(-0.25f, q, t);
-  const float x = f * 6.28318530717958648f;
-  const float x2 = x * x;
-  float ps = fmaf(x2, 2.7557319e-06f, -1.9841270e-04f);   // 1/9!, -1/7!
-  ps = fmaf(x2, ps, 8.3333333e-03f);                        // 1/5!
-  ps = fmaf(x2, ps, -1.6666667e-01f);                       // -1/3!
-  ps = x * fmaf(x2, ps, 1.0f);
-  float pc = fmaf(x2, -2.7557319e-07f, 2.4801587e-05f);     // -1/10!, 1/8!
-  pc = fmaf(x2, pc, -1.3888889e-03f);                       // -1/6!
-  pc = fmaf(x2, pc, 4.1666668e-02f);                        // 1/4!
-  pc = fmaf(x2, pc, -0.5f);                                 // -1/2!
-  pc = fmaf(x2, pc, 1.0f);
-  // rotate by qi quarter turns without branches: odd qi swaps the pair, the
-  // sine is negative for qi = 2, 3 and the cosine for qi = 1, 2
-  const int qi = int(q) & 3;
-  const bool sw = (qi & 1) != 0;
-  const float s0 = sw ? pc : ps, c0 = sw ? ps : pc;
-  s = __int_as_float(__float_as_int(s0) ^ ((qi & 2) << 30));
-  c = __int_as_float(__float_as_int(c0) ^ (((qi + 1) & 2) << 30));
-}
-
 // G for a float32 separation: r from float32 squares and the hardware
-// reciprocal square root, phase r - rint(r), sin/cos by sincos_turns.  Phase
-// error ~2e-7 r rad: for the eps >= 1e-5 plans.  A coincident pair (r = 0)
-// gives 0 without a branch (1/r taken as 0, so r and the phase are 0 too).
+// reciprocal square root, phase t = r - rint(r) in turns, and the hardware
+// sine and cosine, which take turns (over |t| <= 1/2 they are within 1.3e-7
+// of sin and cos of 2 pi t, rms 3.5e-8).  Phase error ~2e-7 r rad: for the
+// eps >= 1e-5 plans.  A coincident pair (r = 0) gives 0 without a branch (1/r
+// taken as 0, so r and the phase are 0 too).
 __device__ __forceinline__ float2 green_f(float dx, float dy, float dz) {
   const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
   const float ri = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
   const float r = r2 * ri;
-  float s, c;
-  sincos_turns(r - rintf(r), s, c);
-  return make_float2(c * ri, s * ri);
+  const float t = r - rintf(r);
+  return make_float2(__builtin_amdgcn_cosf(t) * ri, __builtin_amdgcn_sinf(t) * ri);
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
@@ -1245,6 +1219,9 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
           j = nb_beg[q] + (g - nb_off[q]);
           sh[i] = phi[j];
           sq[i] = plo[j];
+        } else {  // an unused lane's source: a finite point (its densities are 0)
+          sh[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          sq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         sj[i] = j;
       }
@@ -1294,7 +1271,10 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
         for (int t = 0; t < 8; ++t) {
           const float4 a = th[rt * 8 + t], c = tq[rt * 8 + t];
           gv[t] = green_f((a.x - h.x) + (c.x - l.x), (a.y - h.y) + (c.y - l.y), (a.z - h.z) + (c.z - l.z));
-          if (!sval || s0 + rt * 8 + t >= s1) gv[t] = make_float2(0.f, 0.f);
+          // float32 products need no mask: unused sources have zero densities
+          // and rows past the leaf's targets are not stored; the 16-bit split
+          // scales by the tile's largest |G|, which must see only real pairs
+          if (PREC != 0 && (!sval || s0 + rt * 8 + t >= s1)) gv[t] = make_float2(0.f, 0.f);
         }
         int eg = 0;  // 16-bit plans: the tile's scale exponent (largest |G| below 2^14)
         if constexpr (PREC == PREC_F16) {
