@@ -1135,8 +1135,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
 constexpr int NM_SC = 64;   // sources per staged chunk
 constexpr int kNearMfmaMinRhs = 4;  // fast plans with at least this many rhs take the MFMA path
 constexpr int NM_NW = 4;    // waves per workgroup
-constexpr int NM_MAXT = 4;  // row tiles per wave
-constexpr int NM_TB = 8 * NM_NW * NM_MAXT;  // targets per workgroup (128)
+constexpr int NM_MAXT = 2;  // row tiles per wave
+constexpr int NM_TB = 8 * NM_NW * NM_MAXT;  // targets per workgroup (64)
 template <int NCT, int PREC>
 __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restrict__ phi, const float4* __restrict__ plo,
                                                           const int* __restrict__ lstart,
