@@ -1478,6 +1478,87 @@ __global__ void __launch_bounds__(L2T_BS) k_l2t_leaf(const float2* __restrict__ 
   }
 }
 
+// L2T for many right-hand sides as a complex GEMM on MFMA: per leaf, the
+// potentials of its targets are W (targets x R) times the leaf's incoming
+// potentials (R x rhs).  A workgroup takes (leaf, 16 NCT right-hand sides,
+// block of L2T_MT_TB targets); the incoming potentials of those columns are
+// staged in LDS, and each wave owns 8-target row tiles.  Complex is
+// interleaved real as in the near field: the lane's A entry is component
+// (row parity) xor (k part) of W (negated on even rows' Im entries), its B
+// entry component (k part) of the potential; products sum in float32 over
+// the R ranks, as in the VALU form, and the near-field sum is added in
+// float64 before the float32 store in the caller's point order.
+constexpr int L2T_MT_NW = 4;                      // waves per workgroup
+constexpr int L2T_MT_MAXT = 2;                    // row tiles per wave
+constexpr int L2T_MT_TB = 8 * L2T_MT_NW * L2T_MT_MAXT;  // targets per workgroup (64)
+template <int NCT>
+__global__ void __launch_bounds__(64 * L2T_MT_NW) k_l2t_mfma(const float2* __restrict__ W,
+                                                             const float2* __restrict__ ulf,
+                                                             const int* __restrict__ lstart,
+                                                             const int* __restrict__ gid,
+                                                             const double2* __restrict__ unear,
+                                                             const int* __restrict__ perm, int R, int RS, int nrhs,
+                                                             int64_t N, const ReqTable Q) {
+  constexpr int NCOL = 16 * NCT;
+  extern __shared__ float2 us[];  // [NCOL][RS]: the leaf's incoming potentials of this block's columns
+  const int b = blockIdx.x;
+  const int bo = gid ? gid[b] : b;  // the leaf's LF vector (adaptive trees)
+  const int c0 = int(blockIdx.y) * NCOL;
+  const int s0 = lstart[b] + int(blockIdx.z) * L2T_MT_TB;
+  const int s1 = min(lstart[b + 1], s0 + L2T_MT_TB);
+  if (s0 >= s1) return;  // uniform: this target block is past the leaf's end
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int nc = min(NCOL, nrhs - c0);
+  for (int e = threadIdx.x; e < NCOL * R; e += 64 * L2T_MT_NW) {
+    const int c = e / R, q = e - c * R;
+    us[c * RS + q] = c < nc ? ulf[(int64_t(bo) * nrhs + c0 + c) * R + q] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int ntiles = (s1 - s0 + 7) / 8;
+  const int j = lane & 15, kr = lane >> 4;  // A row / B column, k index of this lane
+  const int kp = kr & 1;                     // Re / Im part of k
+  const bool rodd = (j & 1) != 0;
+  const int comp = (rodd ? 1 : 0) ^ kp;
+  const unsigned neg = (!rodd && kp) ? 0x80000000u : 0u;
+#pragma unroll
+  for (int i = 0; i < L2T_MT_MAXT; ++i) {
+    const int rt = w + L2T_MT_NW * i;
+    if (rt >= ntiles) break;
+    // this lane's target row (rows past the leaf's end repeat its last target)
+    const int t = min(s0 + rt * 8 + (j >> 1), s1 - 1);
+    const float* wa = reinterpret_cast<const float*>(W + int64_t(t) * R + (kr >> 1)) + comp;
+    const float* ub = reinterpret_cast<const float*>(us + j * RS + (kr >> 1)) + kp;
+    v4f acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+    // MFMA step q covers ranks 2q, 2q + 1 (R is a multiple of 8)
+#pragma unroll 4
+    for (int q = 0; q < R / 2; ++q) {
+      const float av = __uint_as_float(__float_as_uint(wa[2 * 2 * q]) ^ neg);
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, ub[2 * (2 * q + c * 16 * RS)], acc[c], 0, 0, 0);
+    }
+    // lane holds rows 4 kr .. 4 kr + 3 = (Re, Im) of targets 2 kr, 2 kr + 1, column j
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c0 + c * 16 + j;
+      if (col >= nrhs) continue;
+      const int r = req_of(Q, col);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int tt = s0 + rt * 8 + 2 * kr + h;
+        if (tt < s1) {
+          const double2 nf = unear[int64_t(col) * N + tt];
+          Q.u[r][int64_t(col - Q.k0[r]) * N + perm[tt]] =
+              make_float2(float(double(acc[c][2 * h]) + nf.x), float(double(acc[c][2 * h + 1]) + nf.y));
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_zero(float2* __restrict__ p, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = make_float2(0.f, 0.f);
@@ -2459,8 +2540,20 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
     mark(ST_LF_REDUCE);
   }
   if (own) DFMM_HIP(hipStreamWaitEvent(st, AS.join, 0));
-  if (Rl > 16 * L2T_QMAX) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank too large for L2T"};
-  if (nrhs >= 4) {
+  if (Rl > 16 * L2T_QMAX || Rl % 2 != 0) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank unsupported by L2T"};
+  if (nrhs >= 16) {
+    // k_l2t_mfma: the staged column stride RS is odd (in float2), which spreads
+    // the 16 columns a wave reads at one rank over the LDS banks
+    const int RS = Rl | 1;
+    const int nt = nrhs > 16 ? 2 : 1;
+    const size_t lds = sizeof(float2) * size_t(16 * nt) * size_t(RS);
+    const dim3 grid(unsigned(nleaf), unsigned((nrhs + 16 * nt - 1) / (16 * nt)),
+                    unsigned((P.max_leaf_pts + L2T_MT_TB - 1) / L2T_MT_TB));
+    auto kern = nt == 2 ? &k_l2t_mfma<2> : &k_l2t_mfma<1>;
+    ensure_lds_limit(reinterpret_cast<const void*>(kern));
+    hipLaunchKernelGGL(kern, grid, dim3(64 * L2T_MT_NW), lds, st, P.lf.W.as<float2>(), S.ulf.as<float2>(),
+                       P.leaf_start.as<int>(), gid, S.unear.as<double2>(), P.perm_d.as<int>(), Rl, RS, nrhs, N, R);
+  } else if (nrhs >= 4) {
     const int kc = std::min(nrhs, std::max(1, int((48 << 10) / (sizeof(float2) * Rl))));
     hipLaunchKernelGGL(k_l2t_leaf, dim3(unsigned(nleaf)), dim3(L2T_BS), sizeof(float2) * size_t(kc) * Rl, st,
                        P.lf.W.as<float2>(), S.ulf.as<float2>(), P.leaf_start.as<int>(), gid, S.unear.as<double2>(),
