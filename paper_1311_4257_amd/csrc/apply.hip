@@ -188,6 +188,73 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
   }
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));  // an MFMA accumulator tile
+
+// S2M for many right-hand sides as a complex GEMM on MFMA: per leaf, the
+// outgoing check potentials are V^T (R x points) times the leaf's densities
+// (points x rhs).  A workgroup takes (leaf, 16 NCT right-hand sides); the
+// leaf's densities of those columns are staged in LDS (zeros past the last
+// point, an even count), and the waves take the 8-row tiles of R in turn.
+// The fragments are those of the near field and of L2T: the lane's A entry is
+// component (row parity) xor (k part) of V (negated on even rows' Im
+// entries), its B entry component (k part) of a density; float32 sums over
+// the leaf's points, as in the VALU form.
+constexpr int S2M_MT_NW = 4;  // waves per workgroup
+template <int NCT>
+__global__ void __launch_bounds__(64 * S2M_MT_NW) k_s2m_mfma(const int* __restrict__ lstart,
+                                                             const float2* __restrict__ V,
+                                                             const float2* __restrict__ fs, int R, int nrhs,
+                                                             const int* __restrict__ gid, float2* __restrict__ clf) {
+  constexpr int NCOL = 16 * NCT;
+  extern __shared__ float2 fsh[];  // [point (even count)][NCOL]
+  const int b = blockIdx.x;
+  const int bo = gid ? gid[b] : b;  // the leaf's LF vector (adaptive trees)
+  const int c0 = int(blockIdx.y) * NCOL;
+  const int s0 = lstart[b], s1 = lstart[b + 1];
+  const int np = s1 - s0, np2 = (np + 1) & ~1;
+  const int nc = min(NCOL, nrhs - c0);
+  for (int e = threadIdx.x; e < np2 * NCOL; e += 64 * S2M_MT_NW) {
+    const int j = e / NCOL, c = e - j * NCOL;
+    fsh[e] = (j < np && c < nc) ? fs[int64_t(s0 + j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  if (np == 0) return;  // uniform
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int jr = lane & 15, kr = lane >> 4;  // A row / B column, k index of this lane
+  const int kp = kr & 1;                      // Re / Im part of k
+  const bool rodd = (jr & 1) != 0;
+  const int comp = (rodd ? 1 : 0) ^ kp;
+  const unsigned neg = (!rodd && kp) ? 0x80000000u : 0u;
+  const float* fb = reinterpret_cast<const float*>(fsh + (kr >> 1) * NCOL + jr) + kp;
+  for (int m = w; m < R / 8; m += S2M_MT_NW) {
+    const int p = m * 8 + (jr >> 1);  // this lane's row (complex)
+    v4f acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+    // MFMA step q covers points 2q, 2q + 1 of the leaf (past the last point the
+    // weights of the last one, against zero densities)
+#pragma unroll 4
+    for (int q = 0; q < np2 / 2; ++q) {
+      const int j = min(2 * q + (kr >> 1), np - 1);
+      const float av = __uint_as_float(
+          __float_as_uint(reinterpret_cast<const float*>(V + int64_t(s0 + j) * R + p)[comp]) ^ neg);
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb[2 * (2 * q * NCOL + c * 16)], acc[c], 0, 0, 0);
+    }
+    // lane holds rows 4 kr .. 4 kr + 3 = (Re, Im) of rows 2 kr, 2 kr + 1 of the tile, column jr
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int col = c * 16 + jr;
+      if (col >= nc) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        clf[(int64_t(bo) * nrhs + c0 + col) * R + m * 8 + 2 * kr + h] = make_float2(acc[c][2 * h], acc[c][2 * h + 1]);
+    }
+  }
+}
+
 // ---- grouped gather GEMM on MFMA: Y[vdst] = A[op] X[vsrc] ------------------------
 // The complex product y = A x is done as a real product on interleaved data:
 // real row 2q (re) of A is (Re A[q][p], -Im A[q][p]) per column pair (2p, 2p+1)
@@ -205,7 +272,6 @@ __global__ void __launch_bounds__(S2M_BS) k_s2m(const int* __restrict__ lstart, 
 // pairs are in flight in a register ring, and a load is issued for every step
 // pair (past the end it repeats the last address) so that each wait is for the
 // oldest load only.
-typedef float v4f __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline int gg_stride(int K) {
   int s = 2 * K;
@@ -2425,9 +2491,17 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   else if (nrhs < 24)
     hipLaunchKernelGGL(k_s2m<8>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid, S.flf.as<float2>());
-  else  // one pass over the weights for up to 32 right-hand sides
+  else if (size_t(P.max_leaf_pts + 1) * 32 * sizeof(float2) > size_t(kGgDynLds) || Rl % 8 != 0)
+    // one pass over the weights for up to 32 right-hand sides
     hipLaunchKernelGGL(k_s2m<32>, dim3(unsigned(nleaf)), dim3(S2M_BS), 0, st, P.leaf_start.as<int>(),
                        P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid, S.flf.as<float2>());
+  else {  // k_s2m_mfma: the leaf's densities of 32 columns in LDS
+    const size_t lds = sizeof(float2) * size_t(32) * size_t((P.max_leaf_pts + 1) & ~1);
+    ensure_lds_limit(reinterpret_cast<const void*>(&k_s2m_mfma<2>));
+    hipLaunchKernelGGL(k_s2m_mfma<2>, dim3(unsigned(nleaf), unsigned((nrhs + 31) / 32)), dim3(64 * S2M_MT_NW),
+                       lds, st, P.leaf_start.as<int>(), P.lf.V.as<float2>(), S.fs.as<float2>(), Rl, nrhs, gid,
+                       S.flf.as<float2>());
+  }
   mark(ST_S2M);
   if (LS.slot) {
     // slot form: M2M fine to coarse; then per level, coarse to fine, one launch
