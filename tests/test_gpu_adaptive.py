@@ -11,7 +11,8 @@ summed directly in the near field.
   levels below width 1/2, the leaves and the near-field pairs, bit for bit.
 * With the oracle's skeletons injected (every LF width included) the pass must
   equal the oracle's float64 pass over the same adaptive tree to float32
-  rounding: 5e-6 relative L2 and max, at 1, 3 and 20 rhs.
+  rounding: 5e-6 relative L2 and max, at 1, 3, 20 and 32 rhs (32: the
+  MFMA S2M, whose leaves sit at several LF levels).
 * With the library's own skeletons the pass must meet eps against the float64
   direct sum of Eq. 1.
 """
@@ -90,7 +91,7 @@ def test_adaptive_structure_matches_oracle(cuda, case):
     assert info.leaves == len(leaves)
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 20])
+@pytest.mark.parametrize("nrhs", [1, 3, 20, 32])
 def test_adaptive_injected_matches_oracle_pass(cuda, case, nrhs):
     """The oracle's skeletons of every width on both sides: the GPU pass against
     the oracle's float64 pass of the same adaptive tree, element by element."""

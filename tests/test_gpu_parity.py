@@ -106,6 +106,34 @@ def test_structure_points_on_dyadic_faces(cuda):
     assert plan.info().w_top == st.w_top
 
 
+@pytest.mark.parametrize("nrhs", [3, 32])
+def test_dense_leaf_matches_oracle_fmm(cuda, nrhs):
+    """One leaf of the K = 4 sphere holds 722 points (720 added uniformly in the
+    middle fifth of a width-1/2 box): its targets span 12 blocks of the MFMA near
+    field and of the MFMA L2T, and at 32 rhs its densities no longer fit the LDS
+    block of the MFMA S2M, so S2M takes the VALU form.  With the oracle's
+    skeletons on both sides the pass equals the oracle's float64 pass of the same
+    tree to float32 rounding (3 rhs: pair form and VALU leaf kernels)."""
+    pts, _, cfg = workloads.make_config("sphere4")
+    K = cfg["K"]
+    w = K / 2 ** build_structure(pts, K).tree.D
+    c = (np.floor((0.8 * pts[0] + K / 2) / w) + 0.5) * w - K / 2
+    rng = np.random.default_rng(907)
+    pts = np.concatenate([pts, c + rng.uniform(-0.2 * w, 0.2 * w, size=(720, 3))])
+    st = build_structure(pts, K)
+    lv = st.tree.levels[st.tree.D]
+    assert int(np.max(lv.end - lv.start)) == 722
+    oops = oracle_opset(1e-4, 1)
+    f = workloads.densities(len(pts), nrhs, 911)
+    u_orc = fmm_apply(st, oops, f)
+    plan = _dfmm().Plan(pts, K, opset=inject(oops), device=0)
+    u = plan.apply(_to_dev(f, cuda)).cpu().numpy().astype(np.complex128)
+    err = rel_l2(u, u_orc)
+    worst = np.max(np.abs(u - u_orc)) / np.max(np.abs(u_orc))
+    print(f"dense leaf (722 points) nrhs={nrhs}: rel L2 {err:.2e}  max {worst:.2e}")
+    assert err < 5e-6 and worst < 5e-6
+
+
 @pytest.mark.parametrize("eps", [1e-4, 1e-6])
 def test_flat_ellipsoid_meets_eps(cuda, eps):
     """The 4:2:1 ellipsoid of the serving mix (K = 32, N = 131,072, 129 points per
