@@ -1191,7 +1191,8 @@ __global__ void __launch_bounds__(EV_BS) k_leaf_eval(const float4* __restrict__ 
 // Near field for many right-hand sides (fast plans): per leaf, U[t][k] +=
 // sum_s G(x_t, x_s) F[s][k] as a complex GEMM on MFMA.  A workgroup takes a
 // leaf, a block of up to NM_TB of its targets and 16 NCT right-hand sides;
-// the adjacent leaves' points and densities are staged in LDS NM_SC at a time.
+// the adjacent leaves' points are taken NM_SC at a time, one per lane of every
+// wave (in registers), and their densities staged in LDS.
 // Each wave owns 8-target row tiles (w, w + 4, ...): it evaluates G for its 8
 // targets x NM_SC sources once (one source per lane, the hi/lo separations of
 // the VALU path) into LDS, then runs the products on v_mfma_f32_16x16x4f32 with
@@ -1211,11 +1212,11 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
                                                           double2* __restrict__ unear) {
   constexpr int NCOL = 16 * NCT;
   constexpr int GS = NM_SC + 1;  // G row stride (float2): rows of different targets on different banks
-  __shared__ float4 sh[NM_SC], sq[NM_SC];
+  static_assert(NM_SC == 64 && NB_CHUNK <= 32, "one source per lane; the neighbour search covers 32 ranges");
+  static_assert(NM_SC * NCOL % (64 * NM_NW) == 0, "whole staged densities per thread");
   __shared__ float4 th[NM_TB], tq[NM_TB];
   __shared__ float2 sf[NM_SC * NCOL];
   __shared__ float2 sg[NM_NW * 8 * GS];
-  __shared__ int sj[NM_SC];
   __shared__ int nb_beg[64], nb_off[65];
   __shared__ int fexp[NCOL];  // 16-bit plans: scale exponent of each staged density column
   const int b = blockIdx.x;
@@ -1272,31 +1273,35 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
     const int total = nb_off[nn];
     for (int base = 0; base < total; base += NM_SC) {
       const int fill = min(NM_SC, total - base);
-      __syncthreads();  // the previous chunk is consumed
-      if (threadIdx.x < NM_SC) {
-        const int i = threadIdx.x;
-        int j = -1;
-        if (i < fill) {
-          const int g = base + i;
-          int q = 0;  // the neighbour holding element g: largest q with nb_off[q] <= g
+      // every wave finds the chunk's sources itself, lane i -> source base + i,
+      // and keeps that point (hi/lo parts) in registers; the densities are
+      // loaded through the index of their source's lane, all before the
+      // barrier, so the loads overlap the other waves' products
+      const bool sval = lane < fill;
+      int j = -1;
+      float4 h = make_float4(0.f, 0.f, 0.f, 0.f), l = h;  // an unused lane's source: a finite point (zero densities)
+      if (sval) {
+        const int g = base + lane;
+        int q = 0;  // the neighbour holding element g: largest q with nb_off[q] <= g
 #pragma unroll
-          for (int step = 16; step > 0; step >>= 1)
-            if (q + step < nn && nb_off[q + step] <= g) q += step;
-          j = nb_beg[q] + (g - nb_off[q]);
-          sh[i] = phi[j];
-          sq[i] = plo[j];
-        } else {  // an unused lane's source: a finite point (its densities are 0)
-          sh[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          sq[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        sj[i] = j;
+        for (int step = 16; step > 0; step >>= 1)
+          if (q + step < nn && nb_off[q + step] <= g) q += step;
+        j = nb_beg[q] + (g - nb_off[q]);
+        h = phi[j];
+        l = plo[j];
       }
-      __syncthreads();
-      for (int e = threadIdx.x; e < NM_SC * NCOL; e += 64 * NM_NW) {
+      constexpr int FPT = NM_SC * NCOL / (64 * NM_NW);  // staged densities per thread
+      float2 fv[FPT];
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) {
+        const int e = int(threadIdx.x) + k * 64 * NM_NW;
         const int i = e / NCOL, c = e % NCOL;
-        const int j = sj[i];
-        sf[e] = (j >= 0 && c0 + c < nrhs) ? fs[int64_t(j) * nrhs + c0 + c] : make_float2(0.f, 0.f);
+        const int ji = __shfl(j, i, 64);
+        fv[k] = (ji >= 0 && c0 + c < nrhs) ? fs[int64_t(ji) * nrhs + c0 + c] : make_float2(0.f, 0.f);
       }
+      __syncthreads();  // the previous chunk is consumed
+#pragma unroll
+      for (int k = 0; k < FPT; ++k) sf[int(threadIdx.x) + k * 64 * NM_NW] = fv[k];
       __syncthreads();
       if constexpr (PREC != 0) {  // densities as (hi re | hi im, lo re | lo im) words, scaled per column
         if (threadIdx.x < NCOL) {
@@ -1325,8 +1330,6 @@ __global__ void __launch_bounds__(64 * NM_NW) k_near_mfma(const float4* __restri
         }
         __syncthreads();
       }
-      const bool sval = lane < fill;
-      const float4 h = sh[lane], l = sq[lane];
 #pragma unroll
       for (int i = 0; i < NM_MAXT; ++i) {
         const int rt = w + NM_NW * i;
