@@ -86,6 +86,56 @@ __global__ void k_permute_in(const ReqTable R, float2* __restrict__ fs, const in
   fs[i] = R.f[r][int64_t(k - R.k0[r]) * N + perm[s]];
 }
 
+// Many right-hand sides: the permutation through a tile in LDS of PT_P points,
+// taken in the caller's order, by PT_C columns.  The caller's side is read (or
+// written) as runs of PT_P consecutive points per column, the tree-order side
+// ([point][rhs]) as runs of the tile's columns per point; iperm maps a caller
+// index to its tree position.
+constexpr int PT_P = 64, PT_C = 32, PT_BS = 256;
+__global__ void __launch_bounds__(PT_BS) k_permute_in_tile(const ReqTable R, float2* __restrict__ fs,
+                                                           const int* __restrict__ iperm, int64_t N, int nrhs) {
+  __shared__ float2 t[PT_C][PT_P + 1];
+  const int64_t i0 = int64_t(blockIdx.x) * PT_P;
+  const int c0 = int(blockIdx.y) * PT_C;
+  const int nc = min(PT_C, nrhs - c0);
+  const int np = int(min(int64_t(PT_P), N - i0));
+  const int p = int(threadIdx.x) % PT_P;
+  if (p < np)
+    for (int c = int(threadIdx.x) / PT_P; c < nc; c += PT_BS / PT_P) {
+      const int k = c0 + c;
+      const int r = req_of(R, k);
+      t[c][p] = R.f[r][int64_t(k - R.k0[r]) * N + i0 + p];
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < np * PT_C; e += PT_BS) {
+    const int q = e / PT_C, c = e % PT_C;
+    if (c < nc) fs[int64_t(iperm[i0 + q]) * nrhs + c0 + c] = t[c][q];
+  }
+}
+
+// The inverse: potentials in tree order ut ([point][rhs]) to the caller's
+// outputs (each request's [rhs][N] in the caller's point order).
+__global__ void __launch_bounds__(PT_BS) k_permute_out_tile(const ReqTable R, const float2* __restrict__ ut,
+                                                            const int* __restrict__ iperm, int64_t N, int nrhs) {
+  __shared__ float2 t[PT_C][PT_P + 1];
+  const int64_t i0 = int64_t(blockIdx.x) * PT_P;
+  const int c0 = int(blockIdx.y) * PT_C;
+  const int nc = min(PT_C, nrhs - c0);
+  const int np = int(min(int64_t(PT_P), N - i0));
+  for (int e = threadIdx.x; e < np * PT_C; e += PT_BS) {
+    const int q = e / PT_C, c = e % PT_C;
+    if (c < nc) t[c][q] = ut[int64_t(iperm[i0 + q]) * nrhs + c0 + c];
+  }
+  __syncthreads();
+  const int p = int(threadIdx.x) % PT_P;
+  if (p < np)
+    for (int c = int(threadIdx.x) / PT_P; c < nc; c += PT_BS / PT_P) {
+      const int k = c0 + c;
+      const int r = req_of(R, k);
+      R.u[r][int64_t(k - R.k0[r]) * N + i0 + p] = t[c][p];
+    }
+}
+
 // ---- per-point leaf weights (plan time, float64) -----------------------------------
 // For sorted point j in leaf B (centre c):
 //   V[j][p] = G(c + a_p, x_j)                       (S2M: check potential weights)
@@ -1556,7 +1606,9 @@ __global__ void __launch_bounds__(L2T_BS) k_l2t_leaf(const float2* __restrict__ 
 // (row parity) xor (k part) of W (negated on even rows' Im entries), its B
 // entry component (k part) of the potential; products sum in float32 over
 // the R ranks, as in the VALU form, and the near-field sum is added in
-// float64 before the float32 store in the caller's point order.
+// float64 before the float32 store.  The potentials go to ut in tree order,
+// [point][rhs] (k_permute_out_tile then writes the caller's order), so that a
+// wave's stores of one target are its 16 consecutive columns.
 constexpr int L2T_MT_NW = 4;                      // waves per workgroup
 constexpr int L2T_MT_MAXT = 2;                    // row tiles per wave
 constexpr int L2T_MT_TB = 8 * L2T_MT_NW * L2T_MT_MAXT;  // targets per workgroup (64)
@@ -1565,9 +1617,8 @@ __global__ void __launch_bounds__(64 * L2T_MT_NW) k_l2t_mfma(const float2* __res
                                                              const float2* __restrict__ ulf,
                                                              const int* __restrict__ lstart,
                                                              const int* __restrict__ gid,
-                                                             const double2* __restrict__ unear,
-                                                             const int* __restrict__ perm, int R, int RS, int nrhs,
-                                                             int64_t N, const ReqTable Q) {
+                                                             const double2* __restrict__ unear, int R, int RS,
+                                                             int nrhs, int64_t N, float2* __restrict__ ut) {
   constexpr int NCOL = 16 * NCT;
   extern __shared__ float2 us[];  // [NCOL][RS]: the leaf's incoming potentials of this block's columns
   const int b = blockIdx.x;
@@ -1614,13 +1665,12 @@ __global__ void __launch_bounds__(64 * L2T_MT_NW) k_l2t_mfma(const float2* __res
     for (int c = 0; c < NCT; ++c) {
       const int col = c0 + c * 16 + j;
       if (col >= nrhs) continue;
-      const int r = req_of(Q, col);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int tt = s0 + rt * 8 + 2 * kr + h;
         if (tt < s1) {
           const double2 nf = unear[int64_t(col) * N + tt];
-          Q.u[r][int64_t(col - Q.k0[r]) * N + perm[tt]] =
+          ut[int64_t(tt) * nrhs + col] =
               make_float2(float(double(acc[c][2 * h]) + nf.x), float(double(acc[c][2 * h + 1]) + nf.y));
         }
       }
@@ -2443,8 +2493,15 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   auto mark = [&](int stage) {
     if (tm) tm->mark(stage, st);
   };
-  hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, R, S.fs.as<float2>(),
-                     P.perm_d.as<int>(), N, nrhs);
+  // the tiled permutations pay from 16 rhs; the L2T of as many writes tree order
+  const bool tiled = nrhs >= 16;
+  const dim3 pt_grid(nblocks(N, PT_P), unsigned((nrhs + PT_C - 1) / PT_C));
+  if (tiled)
+    hipLaunchKernelGGL(k_permute_in_tile, pt_grid, dim3(PT_BS), 0, st, R, S.fs.as<float2>(), P.iperm_d.as<int>(), N,
+                       nrhs);
+  else
+    hipLaunchKernelGGL(k_permute_in, dim3(nblocks(N * nrhs, 256)), dim3(256), 0, st, R, S.fs.as<float2>(),
+                       P.perm_d.as<int>(), N, nrhs);
   mark(ST_PERMUTE);
   // the near field needs only the permuted densities: it runs on the plan's
   // second stream while the far-field passes run on st (on st itself when the
@@ -2618,7 +2675,7 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
   }
   if (own) DFMM_HIP(hipStreamWaitEvent(st, AS.join, 0));
   if (Rl > 16 * L2T_QMAX || Rl % 2 != 0) throw Error{DFMM_EUNSUPPORTED, "leaf skeleton rank unsupported by L2T"};
-  if (nrhs >= 16) {
+  if (tiled) {
     // k_l2t_mfma: the staged column stride RS is odd (in float2), which spreads
     // the 16 columns a wave reads at one rank over the LDS banks
     const int RS = Rl | 1;
@@ -2628,8 +2685,12 @@ void run_apply(dfmm_plan_s& P, const ReqTable& R, int nrhs, hipStream_t st, void
                     unsigned((P.max_leaf_pts + L2T_MT_TB - 1) / L2T_MT_TB));
     auto kern = nt == 2 ? &k_l2t_mfma<2> : &k_l2t_mfma<1>;
     ensure_lds_limit(reinterpret_cast<const void*>(kern));
+    // the potentials in tree order go to fs: the densities there are dead once
+    // S2M and the near field (joined above) have run
     hipLaunchKernelGGL(kern, grid, dim3(64 * L2T_MT_NW), lds, st, P.lf.W.as<float2>(), S.ulf.as<float2>(),
-                       P.leaf_start.as<int>(), gid, S.unear.as<double2>(), P.perm_d.as<int>(), Rl, RS, nrhs, N, R);
+                       P.leaf_start.as<int>(), gid, S.unear.as<double2>(), Rl, RS, nrhs, N, S.fs.as<float2>());
+    hipLaunchKernelGGL(k_permute_out_tile, pt_grid, dim3(PT_BS), 0, st, R, S.fs.as<const float2>(),
+                       P.iperm_d.as<int>(), N, nrhs);
   } else if (nrhs >= 4) {
     const int kc = std::min(nrhs, std::max(1, int((48 << 10) / (sizeof(float2) * Rl))));
     hipLaunchKernelGGL(k_l2t_leaf, dim3(unsigned(nleaf)), dim3(L2T_BS), sizeof(float2) * size_t(kc) * Rl, st,

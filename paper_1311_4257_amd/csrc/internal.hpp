@@ -377,7 +377,8 @@ struct dfmm_plan_s {
   std::vector<std::vector<int64_t>> out_slots, in_slots;  // per level: ns x 2
   // device
   dfmm::DevBuf pthi, ptlo;       // float4[N] sorted points (hi, lo split)
-  dfmm::DevBuf perm_d;           // int32[N]
+  dfmm::DevBuf perm_d;           // int32[N]: tree position -> caller's index
+  dfmm::DevBuf iperm_d;          // int32[N]: caller's index -> tree position
   dfmm::DevBuf leaf_start;       // int32[nleaf + 1]
   dfmm::DevBuf leaf_of;          // int32[N]: leaf of each sorted point
   dfmm::DevBuf leaf_center;      // float4[nleaf]

@@ -343,7 +343,7 @@ static size_t gg_bytes(const GGemm& G) {
 }
 static size_t slot_bytes(const SlotGemm& S) { return S.order.bytes + S.t0.bytes + S.gm.bytes + S.terms.bytes; }
 size_t plan_device_bytes(const dfmm_plan_s& P) {
-  size_t b = P.pthi.bytes + P.ptlo.bytes + P.perm_d.bytes + P.leaf_start.bytes + P.leaf_of.bytes +
+  size_t b = P.pthi.bytes + P.ptlo.bytes + P.perm_d.bytes + P.iperm_d.bytes + P.leaf_start.bytes + P.leaf_of.bytes +
              P.leaf_center.bytes + P.near_start.bytes + P.near_src.bytes;
   b += P.lf.a.bytes + P.lf.a64.bytes + P.lf.V.bytes + P.lf.W.bytes + gg_bytes(P.lf.m2l) + P.lf.red_start.bytes +
        P.lf.red_idx.bytes + slot_bytes(P.lf.down);

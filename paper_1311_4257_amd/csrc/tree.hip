@@ -86,6 +86,9 @@ void build_tree_device(dfmm_plan_s& P, const double* points, int64_t N, double K
   P.ptlo.upload(lo);
   std::vector<int32_t> perm32(idx.begin(), idx.end());
   P.perm_d.upload(perm32);
+  std::vector<int32_t> iperm32(size_t(N), 0);
+  for (int64_t s = 0; s < N; ++s) iperm32[size_t(perm32[size_t(s)])] = int32_t(s);
+  P.iperm_d.upload(iperm32);
   const auto& LL = T.lv[D];
   std::vector<int32_t> ls(LL.start.begin(), LL.start.end());
   ls.push_back(int32_t(N));
