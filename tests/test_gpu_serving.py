@@ -87,6 +87,29 @@ def test_apply_batch_matches_separate_applies(cuda):
         plan.apply_batch([fs[0]] * (dfmm.MAX_BATCH + 1), [us[0]] * (dfmm.MAX_BATCH + 1))
 
 
+def test_many_rhs_batch_equals_one_apply_of_its_columns(cuda):
+    """From 16 rhs the permutations in and out go through tiles of 64 points by
+    32 columns, each column mapped to its request.  A batch of 7, 9 and 20 rhs
+    (two request boundaries inside the first column tile, the second tile
+    inside the last request) on the N = 6,000 plan (a last tile of 48 points)
+    must equal, bit for bit, one apply of its 36 columns stacked: the columns
+    share no arithmetic, and both take the launch shapes of 36 rhs."""
+    import torch
+
+    plan = _plans()[1]
+    gen = torch.Generator(device=cuda)
+    gen.manual_seed(12)
+    sizes = (7, 9, 20)
+    fs = [_dens(torch, plan.N, k, gen, cuda) for k in sizes]
+    whole = plan.apply(torch.cat(fs, 0).contiguous()).cpu().numpy()
+    us = [torch.empty_like(f) for f in fs]
+    plan.apply_batch(fs, us)
+    k = 0
+    for u, n in zip(us, sizes):
+        assert np.array_equal(u.cpu().numpy(), whole[k:k + n]), (k, n)
+        k += n
+
+
 def test_request_loop_results_equal_alone_results(cuda):
     """A mix of two plans, requests arriving together and staggered, nrhs 1-5,
     through the native request loop: it must batch (some pass holds several
