@@ -46,3 +46,19 @@ def cached_oracle_pass(key: str, st, ops, f):
     np.save(tmp, u)
     os.replace(tmp, fn)
     return u
+
+
+def k16_case():
+    """The K = 16 injected-skeleton case: 16,384 points on the sphere of
+    diameter 16 (seed 16, tree levels w = 4, 2, 1 and LF), the oracle's
+    tau = 1e-5 skeletons up to w = 4, 32 rhs of densities (seed 116), and the
+    oracle's float64 pass over them (cached)."""
+    from oracle.tree import build_structure
+    from paper_1311_4257_amd import workloads
+
+    pts = workloads.sphere_points(16384, 16.0, seed=16)
+    st = build_structure(pts, 16.0)
+    assert st.w_top == 4
+    ops = oracle_opset(1e-5, 4)
+    f = workloads.densities(len(pts), 32, seed=116)
+    return pts, st, ops, f, cached_oracle_pass("sphere16_16384_s16_f116_tau1e-5_w4", st, ops, f)

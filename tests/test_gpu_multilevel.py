@@ -19,7 +19,7 @@ from oracle.fmm import fmm_apply
 from oracle.kernel import direct_sum, rel_l2
 from oracle.tree import build_structure
 from paper_1311_4257_amd import workloads
-from tests.helpers import cached_oracle_pass, inject, oracle_opset
+from tests.helpers import inject, k16_case, oracle_opset
 
 pytestmark = pytest.mark.gpu
 
@@ -116,12 +116,7 @@ def test_slot_form_column_chunks(cuda, monkeypatch):
 
 @pytest.fixture(scope="module")
 def k16():
-    pts = workloads.sphere_points(16384, 16.0, seed=16)
-    st = build_structure(pts, 16.0)
-    assert st.w_top == 4
-    ops = oracle_opset(1e-5, 4)
-    f = workloads.densities(len(pts), 32, seed=116)
-    return pts, st, ops, f, cached_oracle_pass("sphere16_16384_s16_f116_tau1e-5_w4", st, ops, f)
+    return k16_case()
 
 
 @pytest.mark.parametrize("nrhs,fused,prec", [(1, "0", 0), (1, "1", 0), (1, "0", 1), (32, "0", 0)])
